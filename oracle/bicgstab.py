@@ -1,0 +1,523 @@
+"""Plain FP64 BiCGStab, one right-hand side at a time.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the library never calls
+this module.
+
+Each function below takes the steps of one listing of the paper's Appendix B in
+the listing's order and notation, for ONE column b of the right-hand-side block
+(1-D NumPy arrays, SciPy CSR for the matrix-vector product). Multi-RHS solves
+treat the columns as independent systems that share A: every dot product of
+the paper yields one scalar per right-hand side (the message of a grouped
+reduction holds 8*m*k bytes, Section 3.1.2), so the scalars alpha, omega, rho,
+... are per column and the method is not a block-Krylov method.
+
+Readings where the paper is silent (the paper sets convergence issues aside,
+Section 1):
+
+* Stop test. The listings break when the squared residual estimate drops below
+  eps^2; here eps = tol * ||b||_2 per column, with a strict '<'. Classical
+  basic (Alg. 1) uses the explicit (r_{j+1}, r_{j+1}); the merged forms use the
+  estimate the listing prints (theta - omega*phi for Alg. 2/5, eta - omega*theta
+  for Alg. 6, pi - omega*theta for Alg. 4/7). tol <= 0 disables the test (fixed
+  iteration count). The iteration count is the number of loop passes entered,
+  including the one that terminates.
+* Before the loop: a non-finite ||b||^2 or (r_0, r_0) gives NONFINITE after 0
+  iterations; b = 0 gives x = 0, CONVERGED after 0 iterations; (r_0, r_0) <
+  eps^2 gives CONVERGED after 0 iterations with x = x_0.
+* Zero divisors. delta = 0 (Alg. 1, 2, 5, 6) and (r_0, w_0) = 0 (Alg. 4, 7)
+  stop the column as BREAKDOWN before any update of that pass. psi = 0 (phi = 0
+  in Alg. 4, 6, 7) sets omega = 0 instead of dividing; if the stop test then
+  fails, the pass's x and r updates are still applied and the column stops as
+  BREAKDOWN. rho_{j+1} = 0 and a zero denominator for alpha_{j+1} (Alg. 4, 7)
+  stop the column as BREAKDOWN after that pass's x and r updates.
+* A non-finite alpha, omega, stop estimate, beta or alpha_{j+1} stops the
+  column as NONFINITE at the point where that scalar is formed.
+* Alg. 7 typos: the initial line reads w-hat_0 = M^{-1} w_0, and the line after
+  the last grouped update reads w-hat_{j+1} = M^{-1} w_{j+1},
+  t_{j+1} = A w-hat_{j+1}.
+* Pipelined "previous" vectors are zero before the first pass, with
+  beta_{-1} = 0 and omega_{-1} = 1.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+RUNNING = -1
+CONVERGED = 0
+MAXIT = 1
+BREAKDOWN = 2
+NONFINITE = 3
+
+STATUS_NAMES = {RUNNING: "running", CONVERGED: "converged", MAXIT: "maxit", BREAKDOWN: "breakdown", NONFINITE: "nonfinite"}
+
+
+@dataclass
+class ColumnResult:
+    x: np.ndarray
+    r: np.ndarray  # the recursively updated residual at exit
+    iters: int
+    status: int
+    trace: list = field(default_factory=list)
+
+
+def dot(u, w) -> float:
+    """Euclidean inner product (u, w)."""
+    return float(np.dot(u, w))
+
+
+def identity_preconditioner(A):
+    """M = I: M^{-1} u is a copy of u (the preconditioner of Section 2.3)."""
+    return lambda u: u.copy()
+
+
+def jacobi_preconditioner(A):
+    """M = diag(A): M^{-1} u = u / a_ii. A zero diagonal entry is an error."""
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    if np.any(d == 0.0):
+        raise ValueError("Jacobi preconditioner: zero diagonal entry")
+    return lambda u: u / d
+
+
+class _Recorder:
+    def __init__(self, trace, vectors: bool):
+        self.trace = trace
+        self.vectors = vectors
+
+    def __call__(self, j, scal: dict, **vecs):
+        if self.trace is None:
+            return
+        rec = {"j": j}
+        rec.update(scal)
+        if self.vectors:
+            rec["vec"] = {k: v.copy() for k, v in vecs.items()}
+        self.trace.append(rec)
+
+
+def _begin(A, b, x0, tol):
+    """Shared start: norms, eps^2 and the initial residual r_0 = b - A x_0.
+    Returns (early ColumnResult or None, x, r, rho0, eps2)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    bb = dot(b, b)
+    if not np.isfinite(bb):
+        return ColumnResult(x, b - A @ x, 0, NONFINITE), None, None, None, None
+    if bb == 0.0:
+        z = np.zeros_like(x)
+        return ColumnResult(z, np.zeros_like(x), 0, CONVERGED), None, None, None, None
+    eps2 = tol * tol * bb if tol > 0 else -np.inf
+    r = b - A @ x
+    rho0 = dot(r, r)
+    if not np.isfinite(rho0):
+        return ColumnResult(x, r, 0, NONFINITE), None, None, None, None
+    if rho0 < eps2:
+        return ColumnResult(x, r, 0, CONVERGED), None, None, None, None
+    return None, x, r, rho0, eps2
+
+
+# ------------------------------------------------------------- classical ---
+
+def alg1_bicgstab(A, b, x0, tol, maxit, Minv=None, trace=None, trace_vectors=False):
+    """Alg. 1 (Van der Vorst's BiCGStab), one operation per statement. With a
+    preconditioner the two products become v = A M^{-1} p and t = A M^{-1} s and
+    the solution update uses the preconditioned vectors (right preconditioning,
+    as in Alg. 5). Stop test: explicit (r_{j+1}, r_{j+1}) < eps^2."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    M = Minv if Minv is not None else (lambda u: u)
+    r0 = r.copy()
+    p = r.copy()
+    for j in range(maxit):
+        ph = M(p)
+        v = A @ ph
+        delta = dot(v, r0)
+        if delta == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        alpha = rho / delta
+        if not np.isfinite(alpha):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        s = r - alpha * v
+        sh = M(s)
+        t = A @ sh
+        phi = dot(t, s)
+        psi = dot(t, t)
+        omega = phi / psi if psi != 0.0 else 0.0
+        if not np.isfinite(omega):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        rr = dot(r, r)
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": rr}, x=x, r=r)
+        if not np.isfinite(rr):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        if rr < eps2:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if omega == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        rho_next = dot(r, r0)
+        if rho_next == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        beta = (rho_next / rho) * (alpha / omega)
+        if not np.isfinite(beta):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        p = r + beta * (p - omega * v)
+        rho = rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+def alg2_merged_bicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False):
+    """Alg. 2: merged BiCGStab. theta = (s, s) is formed with phi and psi, and
+    the stop test uses theta - omega*phi, which equals (r_{j+1}, r_{j+1}) in
+    exact arithmetic (footnote in Section 1)."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    p = r.copy()
+    for j in range(maxit):
+        v = A @ p
+        delta = dot(v, r0)
+        if delta == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        alpha = rho / delta
+        if not np.isfinite(alpha):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        s = r - alpha * v
+        t = A @ s
+        phi, psi, theta = dot(t, s), dot(t, t), dot(s, s)
+        omega = phi / psi if psi != 0.0 else 0.0
+        est = theta - omega * phi
+        if not (np.isfinite(omega) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r)
+        if est < eps2:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if omega == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        rho_next = dot(r, r0)
+        if rho_next == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        beta = (rho_next / rho) * (alpha / omega)
+        if not np.isfinite(beta):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        p = r + beta * (p - omega * v)
+        rho = rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
+    """Alg. 5: merged preconditioned BiCGStab (p-hat = M^{-1} p, s-hat =
+    M^{-1} s). The solution update x += alpha p-hat + omega s-hat does not
+    depend on beta; it is formed before the breakdown checks on rho_{j+1} so a
+    column that stops there keeps the pass's x and r updates."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    p = r.copy()
+    for j in range(maxit):
+        ph = Minv(p)
+        v = A @ ph
+        delta = dot(v, r0)
+        if delta == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        alpha = rho / delta
+        if not np.isfinite(alpha):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        s = r - alpha * v
+        sh = Minv(s)
+        t = A @ sh
+        phi, psi, theta = dot(t, s), dot(t, t), dot(s, s)
+        omega = phi / psi if psi != 0.0 else 0.0
+        est = theta - omega * phi
+        if not (np.isfinite(omega) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        if est < eps2:
+            x = x + alpha * ph + omega * sh
+            r = s - omega * t
+            rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r)
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        r = s - omega * t
+        rho_next = dot(r, r0)
+        x = x + alpha * ph + omega * sh
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r)
+        if omega == 0.0 or rho_next == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        beta = (rho_next / rho) * (alpha / omega)
+        if not np.isfinite(beta):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        p = r + beta * (p - omega * v)
+        rho = rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+# ------------------------------------------------------------- reordered ---
+
+def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
+    """Alg. 6: merged Reordered BiCGStab. The preconditioner is applied to
+    v_j and t_j (s_j = M^{-1} v_j, q_j = M^{-1} t_j) so that z_{j+1} = M^{-1}
+    r_{j+1} comes from a vector update; rho_{j+1} = -omega_j psi_j uses the
+    exact-arithmetic orthogonality (r-tilde_j, r_0) = 0. The z_{j+1} line is
+    taken as printed (it already carries the paper's fix of the original)."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    z = Minv(r)
+    vh = z.copy()
+    for j in range(maxit):
+        v = A @ vh
+        delta = dot(v, r0)
+        if delta == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        s = Minv(v)
+        alpha = rho / delta
+        if not np.isfinite(alpha):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        th = z - alpha * s
+        t = A @ th
+        rt = r - alpha * v
+        theta, phi, psi, eta = dot(t, rt), dot(t, t), dot(t, r0), dot(rt, rt)
+        q = Minv(t)
+        omega = theta / phi if phi != 0.0 else 0.0
+        est = eta - omega * theta
+        if not (np.isfinite(omega) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        stop = est < eps2
+        stop_breakdown = False
+        if not stop:
+            rho_next = -omega * psi
+            stop_breakdown = omega == 0.0 or rho_next == 0.0
+            if not stop_breakdown:
+                beta = (rho_next / rho) * (alpha / omega)
+                if not np.isfinite(beta):
+                    return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        r = rt - omega * t
+        x = x + alpha * vh + omega * th
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r, rt=rt, r0=r0)
+        if stop:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if stop_breakdown:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        z = th - omega * q
+        vh = z + beta * (vh - omega * s)
+        rho = rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+# ------------------------------------------------------------- pipelined ---
+
+def _pipelined_scalars(alpha, omega, rho, rho_next, sigma, delta, psi):
+    """beta_j and alpha_{j+1} of Alg. 4/7; returns (status or None, beta, alpha')."""
+    if rho_next == 0.0:
+        return BREAKDOWN, None, None
+    beta = (alpha / omega) * (rho_next / rho)
+    denom = sigma + beta * delta - beta * omega * psi
+    if denom == 0.0:
+        return BREAKDOWN, None, None
+    alpha_next = rho_next / denom
+    if not (np.isfinite(beta) and np.isfinite(alpha_next)):
+        return NONFINITE, None, None
+    return None, beta, alpha_next
+
+
+def alg4_merged_pipebicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False):
+    """Alg. 4: merged Pipelined BiCGStab (Cools and Vanroose). The auxiliary
+    vectors satisfy s = A p, z = A s, w = A r, t = A w, y = A q, v = A z in
+    exact arithmetic; the stop test is pi - omega*theta."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    w = A @ r
+    t = A @ w
+    rw = dot(r, w)
+    if rw == 0.0:
+        return ColumnResult(x, r, 0, BREAKDOWN)
+    alpha = rho / rw
+    if not np.isfinite(alpha):
+        return ColumnResult(x, r, 0, NONFINITE)
+    beta, omega = 0.0, 1.0
+    p = np.zeros_like(r)
+    s = np.zeros_like(r)
+    z = np.zeros_like(r)
+    v = np.zeros_like(r)
+    for j in range(maxit):
+        p = r + beta * (p - omega * s)
+        s = w + beta * (s - omega * z)
+        z = t + beta * (z - omega * v)
+        q = r - alpha * s
+        y = w - alpha * z
+        theta, phi, pi = dot(q, y), dot(y, y), dot(q, q)
+        v = A @ z
+        omega = theta / phi if phi != 0.0 else 0.0
+        est = pi - omega * theta
+        if not (np.isfinite(omega) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        x = x + alpha * p + omega * q
+        r = q - omega * y
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r, p=p, s=s, z=z, q=q, y=y, v=v, w=w, t=t)
+        if est < eps2:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if omega == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        w = y - omega * (t - alpha * v)
+        rho_next, psi, sigma, delta = dot(r0, r), dot(r0, z), dot(r0, w), dot(r0, s)
+        t = A @ w
+        st, beta, alpha_next = _pipelined_scalars(alpha, omega, rho, rho_next, sigma, delta, psi)
+        if st is not None:
+            return ColumnResult(x, r, j + 1, st, trace)
+        alpha, rho = alpha_next, rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+def alg7_merged_ppipebicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
+    """Alg. 7: merged preconditioned Pipelined BiCGStab. Hat vectors are the
+    preconditioned ones (r-hat = M^{-1} r, ...); the shadow residual is r_0."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, rho, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    rh = Minv(r)
+    w = A @ rh
+    wh = Minv(w)
+    t = A @ wh
+    rw = dot(r, w)
+    if rw == 0.0:
+        return ColumnResult(x, r, 0, BREAKDOWN)
+    alpha = rho / rw
+    if not np.isfinite(alpha):
+        return ColumnResult(x, r, 0, NONFINITE)
+    beta, omega = 0.0, 1.0
+    ph = np.zeros_like(r)
+    sh = np.zeros_like(r)
+    zh = np.zeros_like(r)
+    s = np.zeros_like(r)
+    z = np.zeros_like(r)
+    v = np.zeros_like(r)
+    for j in range(maxit):
+        ph = rh + beta * (ph - omega * sh)
+        sh = wh + beta * (sh - omega * zh)
+        qh = rh - alpha * sh
+        s = w + beta * (s - omega * z)
+        z = t + beta * (z - omega * v)
+        q = r - alpha * s
+        y = w - alpha * z
+        theta, phi, pi = dot(q, y), dot(y, y), dot(q, q)
+        zh = Minv(z)
+        v = A @ zh
+        omega = theta / phi if phi != 0.0 else 0.0
+        est = pi - omega * theta
+        if not (np.isfinite(omega) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        x = x + alpha * ph + omega * qh
+        r = q - omega * y
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r, ph=ph, sh=sh, qh=qh, s=s, z=z, zh=zh,
+            q=q, y=y, v=v, w=w, wh=wh, t=t, rh=rh)
+        if est < eps2:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if omega == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        rh = qh - omega * (wh - alpha * zh)
+        w = y - omega * (t - alpha * v)
+        rho_next, psi, sigma, delta = dot(r0, r), dot(r0, z), dot(r0, w), dot(r0, s)
+        wh = Minv(w)
+        t = A @ wh
+        st, beta, alpha_next = _pipelined_scalars(alpha, omega, rho, rho_next, sigma, delta, psi)
+        if st is not None:
+            return ColumnResult(x, r, j + 1, st, trace)
+        alpha, rho = alpha_next, rho_next
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
+# -------------------------------------------------------------- dispatch ---
+
+VARIANTS = ("classical", "reordered", "pipelined")
+FORMULATIONS = ("merged", "basic")
+PRECONDS = ("none", "jacobi")
+
+
+def solve_column(A, b, x0=None, variant="classical", formulation="merged", precond="none", tol=1e-8, maxit=1000,
+                 trace=None, trace_vectors=False) -> ColumnResult:
+    """One column. The basic and merged forms of the Reordered and Pipelined
+    methods run the same statements (merging changes which statements share a
+    pass over memory, Table 2, not what they compute), so both map to the
+    listing; for the classical method the basic form is Alg. 1 with its
+    explicit residual-norm stop test."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    b = np.asarray(b, dtype=np.float64)
+    x0 = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64)
+    if variant not in VARIANTS or formulation not in FORMULATIONS or precond not in PRECONDS:
+        raise ValueError(f"unknown method {variant}/{formulation}/{precond}")
+    if precond == "jacobi":
+        Minv = jacobi_preconditioner(A)
+    else:
+        Minv = identity_preconditioner(A)
+    kw = dict(trace=trace, trace_vectors=trace_vectors)
+    if variant == "classical":
+        if formulation == "basic":
+            return alg1_bicgstab(A, b, x0, tol, maxit, Minv if precond == "jacobi" else None, **kw)
+        if precond == "none":
+            return alg2_merged_bicgstab(A, b, x0, tol, maxit, **kw)
+        return alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, **kw)
+    if variant == "reordered":
+        return alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, **kw)
+    if precond == "none":
+        return alg4_merged_pipebicgstab(A, b, x0, tol, maxit, **kw)
+    return alg7_merged_ppipebicgstab(A, b, x0, tol, maxit, Minv, **kw)
+
+
+@dataclass
+class BlockResult:
+    x: np.ndarray  # n x k
+    r: np.ndarray  # n x k, recursive residual
+    iters: np.ndarray  # k
+    status: np.ndarray  # k
+    relres_true: np.ndarray  # k, ||b - A x|| / ||b||
+    relres_recursive: np.ndarray  # k, ||r|| / ||b||
+    traces: list
+
+
+def solve(A, B, X0=None, variant="classical", formulation="merged", precond="none", tol=1e-8, maxit=1000,
+          columns=None, trace=False, trace_vectors=False) -> BlockResult:
+    """Solve A X = B for an n x k block, column by column (independent
+    recurrences). `columns` restricts the work to a subset of columns; the
+    other columns of the result are NaN."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    B = np.asarray(B, dtype=np.float64)
+    if B.ndim == 1:
+        B = B[:, None]
+    n, k = B.shape
+    X0 = np.zeros_like(B) if X0 is None else np.asarray(X0, dtype=np.float64).reshape(n, k)
+    cols = range(k) if columns is None else columns
+    X = np.full((n, k), np.nan)
+    R = np.full((n, k), np.nan)
+    iters = np.full(k, -1, dtype=np.int64)
+    status = np.full(k, RUNNING, dtype=np.int64)
+    rt = np.full(k, np.nan)
+    rr = np.full(k, np.nan)
+    traces = [None] * k
+    for c in cols:
+        tr = [] if trace else None
+        res = solve_column(A, B[:, c], X0[:, c], variant, formulation, precond, tol, maxit, tr, trace_vectors)
+        X[:, c], R[:, c], iters[c], status[c], traces[c] = res.x, res.r, res.iters, res.status, tr
+        nb = np.linalg.norm(B[:, c])
+        if nb > 0:
+            rt[c] = np.linalg.norm(B[:, c] - A @ res.x) / nb
+            rr[c] = np.linalg.norm(res.r) / nb
+        else:
+            rt[c] = rr[c] = 0.0
+    return BlockResult(X, R, iters, status, rt, rr, traces)

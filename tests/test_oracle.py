@@ -1,0 +1,297 @@
+"""Pins for the CPU oracle: each checks it against something other than itself
+(a LAPACK dense solve, a manufactured solution, identities that hold in exact
+arithmetic, special cases with known answers, and numbers the paper prints).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import BREAKDOWN, CONVERGED, MAXIT, NONFINITE, solve, solve_column
+from oracle import bicgstab as ob
+from oracle import model as om
+from workloads import conv_diff, manufactured_rhs, random_sparse
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
+
+
+def _tiny_systems():
+    out = []
+    A = conv_diff(8, 2, (1.0, 0.5))
+    out.append(("cd2d_8", A.to_scipy()))
+    A = conv_diff(6, 3, (1.0, 0.7, 0.3))
+    out.append(("cd3d_6", A.to_scipy()))
+    A = random_sparse(50, 10, seed=3)
+    out.append(("rand50", A.to_scipy()))
+    return out
+
+
+@pytest.mark.parametrize("name,A", _tiny_systems(), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_dense_solve(name, A, variant, formulation, precond):
+    """Converged oracle solutions agree with numpy.linalg.solve within the
+    bound kappa_2 * tol that the stop test implies."""
+    rng = np.random.default_rng(11)
+    B = rng.uniform(-1, 1, (A.shape[0], 3))
+    Ad = A.toarray()
+    Xd = np.linalg.solve(Ad, B)
+    kappa = np.linalg.cond(Ad)
+    tol = 1e-10
+    res = solve(A, B, variant=variant, formulation=formulation, precond=precond, tol=tol, maxit=2000)
+    assert np.all(res.status == CONVERGED)
+    for c in range(B.shape[1]):
+        err = np.linalg.norm(res.x[:, c] - Xd[:, c]) / np.linalg.norm(Xd[:, c])
+        assert err <= 2 * kappa * tol, (c, err, kappa)
+    assert np.all(res.relres_true <= 1.1 * tol)
+
+
+def test_manufactured_solution():
+    A = conv_diff(16, 2, (1.0, 0.5))
+    S = A.to_scipy()
+    b, xs = manufactured_rhs(A, 4, seed=5)
+    kappa = np.linalg.cond(S.toarray())
+    for variant, formulation, precond in METHODS:
+        res = solve(S, b, variant=variant, formulation=formulation, precond=precond, tol=1e-10, maxit=2000)
+        err = np.linalg.norm(res.x - xs, axis=0) / np.linalg.norm(xs, axis=0)
+        assert np.all(res.status == CONVERGED)
+        assert np.all(err <= kappa * 1e-10), (variant, formulation, precond, err)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_residual_gap(variant, formulation, precond):
+    """The recursively updated residual stays equal to b - A x_j (up to
+    rounding) along the whole run."""
+    A = conv_diff(10, 3, (1.0, 0.7, 0.3)).to_scipy()
+    rng = np.random.default_rng(2)
+    b = rng.uniform(-1, 1, A.shape[0])
+    tr = []
+    res = solve_column(A, b, None, variant, formulation, precond, 1e-12, 500, trace=tr, trace_vectors=True)
+    assert res.status == CONVERGED
+    nb = np.linalg.norm(b)
+    for rec in tr:
+        gap = np.linalg.norm((b - A @ rec["vec"]["x"]) - rec["vec"]["r"]) / nb
+        assert gap <= 1e-11, (rec["j"], gap)
+
+
+def test_classical_merged_estimate_is_residual_norm():
+    """theta - omega*phi = (r_{j+1}, r_{j+1}) in exact arithmetic (footnote of
+    Section 1): the merged estimate tracks the explicit norm while the residual
+    is well above rounding level."""
+    A = conv_diff(12, 3, (1.0, 0.7, 0.3)).to_scipy()
+    b = np.random.default_rng(4).uniform(-1, 1, A.shape[0])
+    for precond in ("none", "jacobi"):
+        tr = []
+        solve_column(A, b, None, "classical", "merged", precond, 1e-12, 400, trace=tr, trace_vectors=True)
+        rr0 = b @ b
+        checked = 0
+        for rec in tr:
+            rr = rec["vec"]["r"] @ rec["vec"]["r"]
+            if rr > 1e-8 * rr0:
+                assert abs(rec["est"] - rr) <= 1e-7 * rr, (rec["j"], rec["est"], rr)
+                checked += 1
+        assert checked > 5
+
+
+def test_reordered_orthogonality():
+    """(r-tilde_j, r_0) = 0 in exact arithmetic, which is why Alg. 6 may take
+    rho_{j+1} = -omega_j psi_j."""
+    A = conv_diff(12, 3, (1.0, 0.7, 0.3)).to_scipy()
+    b = np.random.default_rng(6).uniform(-1, 1, A.shape[0])
+    tr = []
+    solve_column(A, b, None, "reordered", "merged", "jacobi", 1e-12, 30, trace=tr, trace_vectors=True)
+    for rec in tr[:15]:
+        rt, r0 = rec["vec"]["rt"], rec["vec"]["r0"]
+        assert abs(rt @ r0) <= 1e-10 * np.linalg.norm(rt) * np.linalg.norm(r0)
+
+
+def test_pipelined_auxiliary_vectors():
+    """Alg. 4 keeps s = A p, z = A s, y = A q, v = A z, w = A r, t = A w;
+    Alg. 7 keeps the same with hat vectors on the right (s = A p-hat, ...) and
+    p-hat = M^{-1} p-like relations for the hats."""
+    A = conv_diff(10, 3, (1.0, 0.7, 0.3)).to_scipy()
+    b = np.random.default_rng(8).uniform(-1, 1, A.shape[0])
+    tr = []
+    solve_column(A, b, None, "pipelined", "merged", "none", 1e-14, 25, trace=tr, trace_vectors=True)
+
+    def rel(u, w):
+        return np.linalg.norm(u - w) / max(np.linalg.norm(w), 1e-300)
+
+    for rec in tr[:15]:
+        V = rec["vec"]
+        assert rel(V["s"], A @ V["p"]) < 1e-9
+        assert rel(V["z"], A @ V["s"]) < 1e-9
+        assert rel(V["y"], A @ V["q"]) < 1e-9
+        assert rel(V["v"], A @ V["z"]) < 1e-14
+        assert rel(V["t"], A @ V["w"]) < 1e-9
+    d = A.diagonal()
+    tr = []
+    solve_column(A, b, None, "pipelined", "merged", "jacobi", 1e-14, 25, trace=tr, trace_vectors=True)
+    prev_r = None
+    for rec in tr[:15]:
+        V = rec["vec"]
+        assert rel(V["s"], A @ V["ph"]) < 1e-9
+        assert rel(V["z"], A @ V["sh"]) < 1e-9
+        assert rel(V["y"], A @ V["qh"]) < 1e-9
+        assert rel(V["v"], A @ V["zh"]) < 1e-14
+        assert rel(V["t"], A @ V["wh"]) < 1e-9
+        assert rel(V["wh"], V["w"] / d) < 1e-9
+        assert rel(V["sh"], V["s"] / d) < 1e-9
+        assert rel(V["qh"], V["q"] / d) < 1e-9
+        if prev_r is not None:
+            assert rel(V["rh"], prev_r / d) < 1e-9
+        prev_r = V["r"]
+
+
+def test_cross_variant_equivalence():
+    """All forms are reformulations of one method: the first iterates agree."""
+    A = conv_diff(12, 3, (1.0, 0.7, 0.3)).to_scipy()
+    b = np.random.default_rng(9).uniform(-1, 1, A.shape[0])
+    ref = solve_column(A, b, None, "classical", "merged", "none", 0.0, 10).x
+    for variant, formulation, precond in METHODS:
+        x = solve_column(A, b, None, variant, formulation, precond, 0.0, 10).x
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10, (variant, formulation, precond)
+    full = {m: solve_column(A, b, None, *m, 1e-10, 1000) for m in METHODS}
+    its = [r.iters for r in full.values()]
+    # the tail of BiCGStab convergence is irregular, so the rounding of each
+    # form moves the stopping pass by a few
+    assert max(its) - min(its) <= 5
+    assert all(r.status == CONVERGED for r in full.values())
+
+
+def test_identity_preconditioner_reduces_exactly():
+    """With M = I the preconditioned listings compute exactly the
+    unpreconditioned iterates: Alg. 5 with M = I equals Alg. 2, Alg. 7 with
+    M = I equals Alg. 4, Alg. 1 with M = I equals Alg. 1 without M."""
+    A = conv_diff(10, 3, (1.0, 0.7, 0.3)).to_scipy()
+    b = np.random.default_rng(10).uniform(-1, 1, A.shape[0])
+    x0 = np.zeros_like(b)
+    eye = ob.identity_preconditioner(A)
+    pairs = [
+        (ob.alg5_merged_pbicgstab(A, b, x0, 1e-10, 500, eye), ob.alg2_merged_bicgstab(A, b, x0, 1e-10, 500)),
+        (ob.alg7_merged_ppipebicgstab(A, b, x0, 1e-10, 500, eye), ob.alg4_merged_pipebicgstab(A, b, x0, 1e-10, 500)),
+        (ob.alg1_bicgstab(A, b, x0, 1e-10, 500, eye), ob.alg1_bicgstab(A, b, x0, 1e-10, 500, None)),
+    ]
+    for a, c in pairs:
+        assert a.iters == c.iters and a.status == c.status == CONVERGED
+        assert np.array_equal(a.x, c.x)
+
+
+def test_jacobi_on_constant_diagonal():
+    """Jacobi on a constant diagonal is a uniform scaling: same iterates as the
+    unpreconditioned method up to rounding."""
+    A = conv_diff(10, 3, (1.0, 0.7, 0.3)).to_scipy()  # diagonal 6 everywhere
+    b = np.random.default_rng(12).uniform(-1, 1, A.shape[0])
+    for variant in ("classical", "reordered", "pipelined"):
+        a = solve_column(A, b, None, variant, "merged", "none", 1e-10, 500)
+        j = solve_column(A, b, None, variant, "merged", "jacobi", 1e-10, 500)
+        assert abs(a.iters - j.iters) <= 2
+        assert np.linalg.norm(a.x - j.x) / np.linalg.norm(a.x) < 1e-8
+
+
+@pytest.mark.parametrize("c", [2.0, 3.0])
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_scaled_identity(c, variant, formulation, precond):
+    """A = cI is solved in the first pass with x = b / c."""
+    n = 17
+    A = sp.csr_matrix(c * np.eye(n))
+    b = np.random.default_rng(13).uniform(-1, 1, n)
+    res = solve_column(A, b, None, variant, formulation, precond, 1e-12, 10)
+    assert res.status == CONVERGED and res.iters == 1
+    assert np.allclose(res.x, b / c, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_diagonal_matrix_finite_termination(variant, formulation, precond):
+    """For a diagonal matrix with d distinct eigenvalues the BiCG polynomial
+    vanishes on the spectrum after d steps, so BiCGStab stops within d passes
+    (one more is allowed for rounding)."""
+    d = 4
+    eig = np.array([1.0, 2.5, 4.0, 7.0])
+    diag = np.repeat(eig, 10)
+    A = sp.diags(diag).tocsr()
+    b = np.random.default_rng(14).uniform(-1, 1, diag.size)
+    res = solve_column(A, b, None, variant, formulation, "none", 1e-10, 50)
+    assert res.status == CONVERGED and res.iters <= d + 1, res.iters
+    assert np.allclose(res.x, b / diag, rtol=1e-8)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_breakdown_skew(variant, formulation, precond):
+    """A = [[0,1],[-1,0]] is skew, so (A r_0, r_0) = 0: delta_0 = 0 for the
+    classical and Reordered forms and (r_0, w_0) = 0 for the Pipelined ones."""
+    if precond == "jacobi":
+        pytest.skip("zero diagonal: Jacobi is undefined")
+    A = sp.csr_matrix(np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    b = np.array([1.0, 2.0])
+    res = solve_column(A, b, None, variant, formulation, precond, 1e-10, 10)
+    assert res.status == BREAKDOWN
+    assert res.iters == (0 if variant == "pipelined" else 1)
+    assert np.array_equal(res.x, np.zeros(2))
+
+
+def test_jacobi_zero_diagonal_is_error():
+    A = sp.csr_matrix(np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    with pytest.raises(ValueError):
+        solve_column(A, np.ones(2), None, "classical", "merged", "jacobi", 1e-10, 10)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_edge_columns(variant, formulation, precond):
+    """Zero column: x = 0 after 0 passes. NaN: NONFINITE. maxit = 1: MAXIT.
+    Exact initial guess: converged after 0 passes."""
+    A = conv_diff(6, 2, (1.0, 0.5)).to_scipy()
+    n = A.shape[0]
+    rng = np.random.default_rng(15)
+    xs = rng.uniform(-1, 1, n)
+    B = np.stack([np.zeros(n), A @ xs, A @ xs, A @ xs], axis=1)
+    B[3, 1] = np.nan
+    X0 = np.zeros_like(B)
+    X0[:, 3] = xs
+    X0[:, 0] = 1.0  # ignored for a zero right-hand side
+    res = solve(A, B, X0, variant, formulation, precond, 1e-10, 1)
+    assert res.status[0] == CONVERGED and res.iters[0] == 0 and np.all(res.x[:, 0] == 0)
+    assert res.status[1] == NONFINITE and res.iters[1] == 0
+    assert res.status[2] == MAXIT and res.iters[2] == 1
+    assert res.status[3] == CONVERGED and res.iters[3] == 0 and np.array_equal(res.x[:, 3], xs)
+
+
+def test_stop_test_is_strict_and_first():
+    """The count is the first pass whose estimate is below eps^2."""
+    A = conv_diff(12, 2, (1.0, 0.5)).to_scipy()
+    b = np.random.default_rng(16).uniform(-1, 1, A.shape[0])
+    tol = 1e-9
+    eps2 = tol * tol * (b @ b)
+    for variant, formulation, precond in METHODS:
+        tr = []
+        res = solve_column(A, b, None, variant, formulation, precond, tol, 500, trace=tr)
+        ests = [rec["est"] for rec in tr]
+        assert res.iters == len(ests)
+        assert ests[-1] < eps2 and all(e >= eps2 for e in ests[:-1])
+
+
+def test_multi_rhs_columns_are_independent():
+    A = conv_diff(8, 3, (1.0, 0.7, 0.3)).to_scipy()
+    rng = np.random.default_rng(17)
+    u = rng.uniform(-1, 1, A.shape[0])
+    w = rng.uniform(-1, 1, A.shape[0])
+    B = np.stack([u, w, u], axis=1)
+    r1 = solve(A, B, tol=1e-10, maxit=500)
+    r2 = solve(A, B[:, [1, 2, 0]], tol=1e-10, maxit=500)
+    assert np.array_equal(r1.x[:, 0], r1.x[:, 2])
+    assert np.array_equal(r1.x[:, [1, 2, 0]], r2.x)
+
+
+def test_paper_model_tables():
+    """The traffic model reproduces the 'Model' columns of Tables 5 and 6."""
+    g = json.load(open(GOLDEN))["model_single_node"]
+    N = g["grid"] ** 3
+    C = (7 * N - 6 * g["grid"] ** 2) / N
+    for mach in g["machines"].values():
+        B = mach["node_GBps"] * 1000 * 2**20
+        for meth, vals in mach["model"].items():
+            for m, v in zip(mach["m"], vals):
+                t = om.iteration_time(meth, N, m, C, B)
+                assert abs(t - v) / v < 0.03, (meth, m, t, v)
