@@ -1,0 +1,183 @@
+/*
+ * bicgstab.h -- C ABI of the MI355X multi-right-hand-side BiCGStab library.
+ *
+ * The library solves A X = B for a general sparse square matrix A (CSR, int32
+ * indices) and k right-hand sides at once with the BiCGStab methods analysed
+ * in Krasnopolsky, "Revisiting Performance of BiCGStab Methods for Solving
+ * Systems with Multiple Right-Hand Sides" (arXiv:1907.12874):
+ *   - classical BiCGStab            (Appendix B, Alg. 1 basic; Alg. 2 / Alg. 5 merged)
+ *   - Reordered BiCGStab            (Appendix B, Alg. 6)
+ *   - Pipelined BiCGStab            (Appendix B, Alg. 4 / Alg. 7)
+ * each in the "basic" form (one memory pass per vector operation, the Basic
+ * columns of Table 2) and the "merged" form (the operations of one listing
+ * line share one pass, the Merged columns of Table 2), optionally with a
+ * Jacobi preconditioner M = diag(A).
+ *
+ * Multi-vectors are n x k, row-major (element (i, c) at index i*k + c, the
+ * row-wise storage of Section 3.1). Each column is an independent system that
+ * shares A: every dot product yields one scalar per column (Section 3.1.2), and
+ * every column has its own alpha, omega, rho, stop test and status.
+ *
+ * Conventions for every function:
+ *   - Pointers named d_* are DEVICE pointers on the device that was current
+ *     when the handle was created. The library borrows them: it never frees
+ *     or retains them beyond the call, except the matrix arrays, which must
+ *     stay valid and unchanged (except through bicgstab_update_values) for the
+ *     lifetime of the handle.
+ *   - Work is enqueued on the handle's HIP stream. bicgstab_solve* return after
+ *     the stream has finished the solve (they synchronise the stream).
+ *   - Return value: BICGSTAB_OK (0) or a negative error code; a failed call
+ *     leaves the handle usable. bicgstab_last_error() gives a message for the
+ *     last failure on the calling thread.
+ *   - A numerical breakdown is NOT an error: it is reported per column in
+ *     bicgstab_info.status.
+ *   - Handles are not thread-safe; one handle must not be used from two
+ *     threads at once.
+ */
+#ifndef BICGSTAB_H
+#define BICGSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BICGSTAB_MAX_K 64 /* maximum number of right-hand sides per handle */
+
+/* Error codes. */
+enum {
+  BICGSTAB_OK = 0,
+  BICGSTAB_EINVAL = -1,      /* invalid argument (shape, enum, zero diagonal for Jacobi, ...) */
+  BICGSTAB_EHIP = -2,        /* a HIP runtime call failed */
+  BICGSTAB_ENOMEM = -3,      /* workspace too small or allocation failed */
+  BICGSTAB_EUNSUPPORTED = -4 /* valid but unsupported combination */
+};
+
+/* Methods (Appendix B). */
+enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2 };
+/* Formulations: merged = Table 2 "Merged" grouping, basic = Table 2 "Basic";
+ * fused = the merged grouping with the further fusions only a single device
+ * allows (the Jacobi scaling folded into the products and updates, adjacent
+ * passes of one scalar phase joined). */
+enum { BICGSTAB_MERGED = 0, BICGSTAB_BASIC = 1, BICGSTAB_FUSED = 2 };
+/* Preconditioners: none, or Jacobi M = diag(A) applied as u / a_ii. */
+enum { BICGSTAB_PRECOND_NONE = 0, BICGSTAB_PRECOND_JACOBI = 1 };
+/* Precision: FP64 throughout, or FP32 matrix/Krylov vectors with FP64
+ * scalars, FP64 dot accumulation and FP64 iterative refinement. */
+enum { BICGSTAB_FP64 = 0, BICGSTAB_FP32_REFINE = 1 };
+
+/* Per-column termination status. */
+enum {
+  BICGSTAB_COL_CONVERGED = 0, /* estimate of ||r||^2 below (tol*||b||)^2, or b = 0 */
+  BICGSTAB_COL_MAXIT = 1,     /* maxit passes done */
+  BICGSTAB_COL_BREAKDOWN = 2, /* a zero divisor (delta, rho, omega, alpha denominator) */
+  BICGSTAB_COL_NONFINITE = 3  /* a NaN or Inf scalar */
+};
+
+/* A CSR matrix on the device: row_ptr has n+1 entries, row_ptr[0] = 0,
+ * row_ptr[n] = nnz; col_idx and values have nnz entries; column indices of a
+ * row need not be sorted but must lie in [0, n). values are double. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* d_row_ptr;
+  const int32_t* d_col_idx;
+  const double* d_values;
+} bicgstab_csr;
+
+/* Per-column results, HOST arrays of length k owned by the caller (any may be
+ * NULL). relres_true = ||b - A x|| / ||b|| recomputed at exit; relres_recursive
+ * = ||r|| / ||b|| of the recursively updated residual (both 0 when b = 0). */
+typedef struct {
+  int32_t* iters;
+  int32_t* status;
+  double* relres_true;
+  double* relres_recursive;
+} bicgstab_info;
+
+typedef struct bicgstab_ctx* bicgstab_t;
+
+/* Create a solver for A with k right-hand sides (1 <= k <= BICGSTAB_MAX_K).
+ * Reads row_ptr once (device to host) to plan the sparse products; no other
+ * work. stream: a hipStream_t (NULL = the null stream). The Jacobi diagonal is
+ * extracted at the first solve; a zero diagonal entry then fails with
+ * BICGSTAB_EINVAL. */
+int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant, int32_t formulation,
+                    int32_t precond, int32_t precision, void* stream, bicgstab_t* out);
+
+/* Device workspace the handle needs, in bytes (vectors n x k per Krylov
+ * vector, the diagonal, reduction partials and per-column state). */
+int bicgstab_workspace_bytes(bicgstab_t h, size_t* bytes);
+
+/* Give the handle a caller-owned device workspace of at least
+ * bicgstab_workspace_bytes() bytes (256-byte aligned). Without this call the
+ * handle allocates its own at the first solve and frees it in destroy. */
+int bicgstab_set_workspace(bicgstab_t h, void* d_ptr, size_t bytes);
+
+/* Change the stream later work is enqueued on. */
+int bicgstab_set_stream(bicgstab_t h, void* stream);
+
+/* Solve A X = B. d_b: n x k right-hand sides (read only). d_x: n x k, the
+ * initial guess on input and the solution on output. tol: per-column relative
+ * tolerance, a column stops when its residual estimate satisfies
+ * est < (tol * ||b_c||)^2; tol <= 0 disables the test (exactly maxit passes,
+ * unless a breakdown). maxit >= 0. The solve polls the device for completion
+ * every few iterations and returns when every column has stopped. */
+int bicgstab_solve(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit, bicgstab_info* info);
+
+/* Solve A^T Lambda = G with the same method (the adjoint solve of the
+ * gradient of x = A^{-1} b). Builds the transposed CSR on the device at the
+ * first call. Same argument conventions as bicgstab_solve. */
+int bicgstab_solve_transpose(bicgstab_t h, const double* d_g, double* d_lambda, double tol, int32_t maxit,
+                             bicgstab_info* info);
+
+/* Gradient of a loss with respect to the stored matrix values, given the
+ * adjoint Lambda = A^{-T} dL/dX and the solution X (both n x k): for every
+ * stored entry e = (i, j), d_grad[e] = - sum_c Lambda[i, c] * X[j, c]
+ * (the derivative of A^{-1} B restricted to the sparsity pattern). */
+int bicgstab_grad_values(bicgstab_t h, const double* d_lambda, const double* d_x, double* d_grad);
+
+/* Tell the handle that the values behind A->d_values changed (same pattern):
+ * refreshes the diagonal, the FP32 copy and the transposed values. */
+int bicgstab_update_values(bicgstab_t h);
+
+/* Y = A X (n x k, row-major) with the solver's sparse-product kernel, on the
+ * handle's stream, asynchronous. For kernel-level checks and timing. */
+int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y);
+
+/* Per-iteration history of the last solve: for iteration j < count and column
+ * c, hist[(j*k + c)*4 + {0,1,2,3}] = alpha_j, omega_j, rho_j, stop estimate_j.
+ * Call with hist = NULL to get the count; cap = entries of 4 doubles. */
+int bicgstab_history(bicgstab_t h, double* hist, int32_t cap, int32_t* count);
+
+/* Number of kernel launches and device-to-host polls of the last solve. */
+int bicgstab_last_solve_stats(bicgstab_t h, int32_t* iterations_enqueued, int32_t* launches, int32_t* polls);
+
+/* Kernel-level timing: runs the start-up passes on (d_b, d_x) and then
+ * `iters` iterations with the stop test off, on the handle's stream, recording
+ * a HIP event before and after every launch. For each launch i of one
+ * iteration (nsteps <= cap of them) returns kind (0 sparse product,
+ * 1 preconditioner, 2 vector pass), op (vector-pass id, -1 otherwise), the
+ * vector blocks it reads and writes, and its average duration in ms. d_x is
+ * overwritten. FP64 handles only. */
+int bicgstab_kernel_times(bicgstab_t h, const double* d_b, double* d_x, int32_t iters, int32_t cap, int32_t* kind,
+                          int32_t* op, int32_t* nin, int32_t* nout, double* ms, int32_t* nsteps);
+
+int bicgstab_destroy(bicgstab_t h);
+
+/* Host-only query of the launch plan of one iteration (no device needed):
+ * vector block reads and writes of its vector-operation passes (the counting
+ * of Table 2), preconditioner applications, sparse products and kernel
+ * launches per iteration. */
+int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond, int32_t* reads, int32_t* writes,
+                          int32_t* precond_apps, int32_t* spmms, int32_t* launches);
+
+const char* bicgstab_strerror(int code);
+const char* bicgstab_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BICGSTAB_H */

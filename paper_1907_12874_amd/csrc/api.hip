@@ -1,0 +1,827 @@
+// Host driver and C ABI (see include/bicgstab.h).
+//
+// A solve enqueues: a state set-up kernel, the method's start-up passes, then
+// chunks of iterations (captured once as a hipGraph and replayed) until the
+// device reports that every column has stopped, then an exit pass that
+// recomputes the true residual. The host reads one int per chunk; all scalars
+// stay on the device.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bicgstab.h"
+#include "internal.hpp"
+
+using namespace bcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(BICGSTAB_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+// Extra FP64 blocks of the refinement tier (beyond the plan's vectors).
+enum { R_RES = 0, R_D, R_Z, R_B32, R_NUM };
+
+struct MatDev {
+  SpmmMat spmm;      // FP64 values
+  SpmmMat spmm32;    // FP32 values (refinement tier)
+};
+
+struct GraphEntry {
+  const void* x;
+  const void* b;
+  int mat;
+  int chunk;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct bicgstab_ctx {
+  int64_t n = 0, nnz = 0;
+  int k = 0, kp = 1;
+  int variant = 0, formulation = 0, precond = 0, precision = 0;
+  const int32_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+  hipStream_t user_stream = nullptr;
+  hipStream_t ws = nullptr;  // internal stream (graphs cannot be captured on the null stream)
+  hipEvent_t ev = nullptr;
+  int device = 0;
+  Plan plan;
+  std::vector<int32_t> blk_host;
+  // workspace
+  char* base = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+  bool prepared = false;
+  void* vec[V_NUM] = {};
+  void* ref[R_NUM] = {};
+  double* diag = nullptr;
+  float* diag32 = nullptr;
+  float* val32 = nullptr;
+  int32_t* blk = nullptr;
+  double* partials = nullptr;
+  double* sc = nullptr;
+  int* ist = nullptr;
+  Globals* glob = nullptr;
+  unsigned* counter = nullptr;
+  double* hist = nullptr;
+  int hist_cap = 0;
+  int grid_cap = 1024;
+  int chunk = 8;
+  bool use_graph = true;
+  // pinned host mirrors
+  int* h_nrun = nullptr;
+  double* h_sc = nullptr;
+  int* h_ist = nullptr;
+  Globals* h_glob = nullptr;
+  // transposed matrix (adjoint), library-owned
+  bool have_t = false;
+  int32_t* rp_t = nullptr;
+  int32_t* col_t = nullptr;
+  int32_t* perm_t = nullptr;
+  double* val_t = nullptr;
+  float* val32_t = nullptr;
+  int32_t* blk_t = nullptr;
+  std::vector<int32_t> blk_t_host;
+  std::vector<GraphEntry> graphs;
+  // statistics of the last solve
+  int stat_iters = 0, stat_launches = 0, stat_polls = 0;
+  int hist_count = 0;
+};
+
+namespace {
+
+bool fp32_inner(const bicgstab_ctx* h) { return h->precision == BICGSTAB_FP32_REFINE; }
+
+// Workspace layout; with assign = true, sets the pointers inside h->base.
+size_t layout(bicgstab_ctx* h, bool assign) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += align256(b);
+    return o;
+  };
+  const size_t nk = (size_t)h->n * h->k;
+  const size_t elem = fp32_inner(h) ? 4 : 8;
+  size_t vo[V_NUM];
+  for (int v = 0; v < V_NUM; ++v) vo[v] = (size_t)-1;
+  for (int v : h->plan.vecs) vo[v] = take(nk * elem);
+  size_t ro[R_NUM] = {};
+  if (fp32_inner(h)) {
+    ro[R_RES] = take(nk * 8);
+    ro[R_D] = take(nk * 8);
+    ro[R_Z] = take(nk * 8);
+    ro[R_B32] = take(nk * 4);
+  }
+  const size_t o_diag = take((size_t)h->n * 8);
+  const size_t o_diag32 = take(fp32_inner(h) ? (size_t)h->n * 4 : 0);
+  const size_t o_val32 = take(fp32_inner(h) ? (size_t)h->nnz * 4 : 0);
+  const size_t o_blk = take(h->blk_host.size() * 4);
+  const size_t o_part = take((size_t)h->grid_cap * 7 * kMaxK * 8);
+  const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
+  const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
+  const size_t o_glob = take(sizeof(Globals));
+  const size_t o_cnt = take(64);
+  const size_t o_hist = take((size_t)h->hist_cap * h->k * 4 * 8);
+  if (assign) {
+    char* b = h->base;
+    for (int v = 0; v < V_NUM; ++v) h->vec[v] = vo[v] == (size_t)-1 ? nullptr : b + vo[v];
+    for (int v = 0; v < V_NUM; ++v)
+      if (h->plan.alias_from[v] >= 0) h->vec[v] = h->vec[h->plan.alias_from[v]];
+    for (int r = 0; r < R_NUM; ++r) h->ref[r] = fp32_inner(h) ? b + ro[r] : nullptr;
+    h->diag = (double*)(b + o_diag);
+    h->diag32 = fp32_inner(h) ? (float*)(b + o_diag32) : nullptr;
+    h->val32 = fp32_inner(h) ? (float*)(b + o_val32) : nullptr;
+    h->blk = (int32_t*)(b + o_blk);
+    h->partials = (double*)(b + o_part);
+    h->sc = (double*)(b + o_sc);
+    h->ist = (int*)(b + o_ist);
+    h->glob = (Globals*)(b + o_glob);
+    h->counter = (unsigned*)(b + o_cnt);
+    h->hist = h->hist_cap > 0 ? (double*)(b + o_hist) : nullptr;
+  }
+  return off;
+}
+
+Ctl make_ctl(bicgstab_ctx* h) {
+  Ctl c;
+  c.sc = h->sc;
+  c.ist = h->ist;
+  c.glob = h->glob;
+  c.partials = h->partials;
+  c.counter = h->counter;
+  c.hist = h->hist;
+  c.k = h->k;
+  return c;
+}
+
+void clear_graphs(bicgstab_ctx* h) {
+  for (auto& g : h->graphs) hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
+int prepare(bicgstab_ctx* h) {
+  if (h->prepared) return BICGSTAB_OK;
+  if (!h->base) {
+    h->bytes = layout(h, false);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, h->bytes);
+    if (e != hipSuccess) return fail(BICGSTAB_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
+    h->base = (char*)p;
+    h->owned = true;
+  }
+  layout(h, true);
+  HIPCHK(hipMemcpyAsync(h->blk, h->blk_host.data(), h->blk_host.size() * 4, hipMemcpyHostToDevice, h->ws));
+  if (h->precond == BICGSTAB_PRECOND_JACOBI || fp32_inner(h)) {
+    HIPCHK(hipMemsetAsync(h->glob, 0, sizeof(Globals), h->ws));
+    HIPCHK(launch_extract_diag(h->row_ptr, h->col, h->val, h->diag, h->diag32, (int)h->n, h->glob, h->ws));
+    HIPCHK(hipMemcpyAsync(h->h_glob, h->glob, sizeof(Globals), hipMemcpyDeviceToHost, h->ws));
+    HIPCHK(hipStreamSynchronize(h->ws));
+    if (h->precond == BICGSTAB_PRECOND_JACOBI && h->h_glob->zero_diag > 0)
+      return fail(BICGSTAB_EINVAL, "Jacobi preconditioner: " + std::to_string(h->h_glob->zero_diag) +
+                                       " zero diagonal entries");
+  }
+  if (fp32_inner(h)) HIPCHK(launch_convert_f32(h->val, h->val32, h->nnz, h->ws));
+  HIPCHK(hipStreamSynchronize(h->ws));
+  h->prepared = true;
+  return BICGSTAB_OK;
+}
+
+SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
+  SpmmMat m;
+  m.n = (int)h->n;
+  if (which == 0) {
+    m.row_ptr = h->row_ptr;
+    m.col = h->col;
+    m.val = fp32 ? (const void*)h->val32 : (const void*)h->val;
+    m.blk = h->blk;
+    m.nblk = (int)h->blk_host.size() - 1;
+  } else {
+    m.row_ptr = h->rp_t;
+    m.col = h->col_t;
+    m.val = fp32 ? (const void*)h->val32_t : (const void*)h->val_t;
+    m.blk = h->blk_t;
+    m.nblk = (int)h->blk_t_host.size() - 1;
+  }
+  return m;
+}
+
+hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* const* vp, const Ctl& ctl,
+                       bool fp32, hipStream_t s, bool early_exit = true) {
+  const Globals* g = early_exit ? h->glob : nullptr;
+  switch (st.kind) {
+    case K_SPMM:
+      return launch_spmm(M, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
+    case K_PREC:
+      return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
+                         (int)h->n, h->k, fp32, g, s);
+    case K_GROUP: {
+      const void* in[7] = {};
+      void* out[5] = {};
+      for (int i = 0; i < st.nin; ++i) in[i] = vp[st.in[i]];
+      for (int i = 0; i < st.nout; ++i) out[i] = vp[st.out[i]];
+      return launch_group(st.op, in, out, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->grid_cap, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+int enqueue_steps(bicgstab_ctx* h, const std::vector<Step>& steps, const SpmmMat& M, void* const* vp, const Ctl& ctl,
+                  bool fp32, int* launches) {
+  for (const Step& st : steps) {
+    HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
+    ++*launches;
+  }
+  return BICGSTAB_OK;
+}
+
+// One chunk of iterations: replay a captured graph (captured on first use for
+// this (x, b, matrix) triple) or launch directly.
+int enqueue_chunk(bicgstab_ctx* h, int which, const SpmmMat& M, void* const* vp, const Ctl& ctl, bool fp32,
+                  int* launches) {
+  if (!h->use_graph) {
+    for (int c = 0; c < h->chunk; ++c) {
+      int rc = enqueue_steps(h, h->plan.iter, M, vp, ctl, fp32, launches);
+      if (rc) return rc;
+    }
+    return BICGSTAB_OK;
+  }
+  for (auto& g : h->graphs) {
+    if (g.x == vp[V_X] && g.b == vp[V_B] && g.mat == which && g.chunk == h->chunk) {
+      HIPCHK(hipGraphLaunch(g.exec, h->ws));
+      *launches += h->chunk * (int)h->plan.iter.size();
+      return BICGSTAB_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->ws, hipStreamCaptureModeThreadLocal));
+  int dummy = 0;
+  for (int c = 0; c < h->chunk; ++c) {
+    for (const Step& st : h->plan.iter) {
+      hipError_t e = launch_step(h, st, M, vp, ctl, fp32, h->ws);
+      if (e != hipSuccess) {
+        hipStreamEndCapture(h->ws, &graph);
+        if (graph) hipGraphDestroy(graph);
+        return fail(BICGSTAB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      }
+      ++dummy;
+    }
+  }
+  HIPCHK(hipStreamEndCapture(h->ws, &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(BICGSTAB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  if (h->graphs.size() >= 8) {
+    hipGraphExecDestroy(h->graphs.front().exec);
+    h->graphs.erase(h->graphs.begin());
+  }
+  h->graphs.push_back({vp[V_X], vp[V_B], which, h->chunk, exec});
+  HIPCHK(hipGraphLaunch(exec, h->ws));
+  *launches += dummy;
+  return BICGSTAB_OK;
+}
+
+int begin_on_internal_stream(bicgstab_ctx* h) {
+  HIPCHK(hipEventRecord(h->ev, h->user_stream));
+  HIPCHK(hipStreamWaitEvent(h->ws, h->ev, 0));
+  return BICGSTAB_OK;
+}
+
+// The Krylov iteration on (M, b, x) with the handle's plan. fp32: inner
+// solve of the refinement tier (vectors FP32, x FP64 and zero on entry).
+int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double tol, int maxit, int* launches,
+           int* polls, int* enq) {
+  const Ctl ctl = make_ctl(h);
+  const SpmmMat M = mat_of(h, which, fp32);
+  void* vp[V_NUM];
+  for (int v = 0; v < V_NUM; ++v) vp[v] = h->vec[v];
+  vp[V_X] = x;
+  vp[V_B] = const_cast<void*>(b);
+  HIPCHK(launch_setup_state(ctl, tol, maxit, h->hist_cap, h->ws));
+  ++*launches;
+  for (const Step& st : h->plan.init) {
+    if (fp32 && st.kind == K_SPMM && st.in[0] == V_X) {
+      // inner solves start from d = 0, so A d = 0 without a product
+      const void* in0[7] = {};
+      void* out0[5] = {vp[st.out[0]]};
+      HIPCHK(launch_group(OP_FILL0, in0, out0, (int)h->n, h->k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+    } else {
+      HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
+    }
+    ++*launches;
+  }
+  if (maxit <= 0) {
+    HIPCHK(launch_mark_maxit(ctl, h->ws));
+    ++*launches;
+  } else {
+    int enqueued = 0;
+    const int limit = maxit + 2 * h->chunk;
+    while (true) {
+      int rc = enqueue_chunk(h, which, M, vp, ctl, fp32, launches);
+      if (rc) return rc;
+      enqueued += h->chunk;
+      HIPCHK(hipMemcpyAsync(h->h_nrun, &h->glob->nrun, sizeof(int), hipMemcpyDeviceToHost, h->ws));
+      HIPCHK(hipStreamSynchronize(h->ws));
+      ++*polls;
+      if (*h->h_nrun == 0) break;
+      if (enqueued >= limit) return fail(BICGSTAB_EHIP, "device iteration counter did not reach maxit");
+    }
+    *enq += enqueued;
+  }
+  if (!fp32) {
+    // exit: true residual b - A x and ||r|| for every column
+    void* z = vp[V_V];
+    HIPCHK(launch_spmm(M, x, z, h->k, false, nullptr, h->ws));
+    const void* in[7] = {b, z, vp[V_R]};
+    void* out[5] = {};
+    HIPCHK(launch_group(OP_EXIT, in, out, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->grid_cap, h->ws));
+    *launches += 2;
+  }
+  return BICGSTAB_OK;
+}
+
+int read_info(bicgstab_ctx* h, bicgstab_info* info) {
+  HIPCHK(hipMemcpyAsync(h->h_sc, h->sc, (size_t)S_NSCAL * kMaxK * 8, hipMemcpyDeviceToHost, h->ws));
+  HIPCHK(hipMemcpyAsync(h->h_ist, h->ist, (size_t)I_NINT * kMaxK * 4, hipMemcpyDeviceToHost, h->ws));
+  HIPCHK(hipMemcpyAsync(h->h_glob, h->glob, sizeof(Globals), hipMemcpyDeviceToHost, h->ws));
+  HIPCHK(hipStreamSynchronize(h->ws));
+  h->hist_count = std::min(h->h_glob->it, h->hist_cap);
+  if (!info) return BICGSTAB_OK;
+  for (int c = 0; c < h->k; ++c) {
+    if (info->iters) info->iters[c] = h->h_ist[I_ITERS * kMaxK + c];
+    if (info->status) info->status[c] = h->h_ist[I_STATUS * kMaxK + c];
+    if (info->relres_true) info->relres_true[c] = h->h_sc[S_RELRES_TRUE * kMaxK + c];
+    if (info->relres_recursive) info->relres_recursive[c] = h->h_sc[S_RELRES_REC * kMaxK + c];
+  }
+  return BICGSTAB_OK;
+}
+
+// FP32 inner solves with FP64 iterative refinement: r = b - A64 x, inner
+// solve A32 d = r / ||r_c|| to a loose tolerance, x += ||r_c|| d, until the
+// true FP64 residual meets tol (or maxit inner iterations per column).
+int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int maxit, bicgstab_info* info,
+                  int* launches, int* polls, int* enq) {
+  const Ctl ctl = make_ctl(h);
+  const int k = h->k;
+  const double inner_tol = std::max(1e-6, std::min(1e-3, std::getenv("BICGSTAB_INNER_TOL")
+                                                              ? std::atof(std::getenv("BICGSTAB_INNER_TOL"))
+                                                              : 1e-5));
+  const int max_outer = env_int("BICGSTAB_MAX_OUTER", 30);
+  std::vector<int> iters(k, 0), status(k, ST_RUNNING);
+  std::vector<double> relres(k, 0.0), bnorm(k, 0.0);
+  std::vector<double> scale(k, 0.0);
+  const SpmmMat M64 = mat_of(h, 0, false);
+  double* R = (double*)h->ref[R_RES];
+  double* D = (double*)h->ref[R_D];
+  double* Z = (double*)h->ref[R_Z];
+  void* B32 = h->ref[R_B32];
+  for (int outer = 0; outer <= max_outer; ++outer) {
+    // FP64 residual and norms
+    HIPCHK(launch_setup_state(ctl, tol, maxit, 0, h->ws));
+    HIPCHK(launch_spmm(M64, x, Z, k, false, nullptr, h->ws));
+    {
+      const void* in[7] = {b, Z};
+      void* out[5] = {R};
+      HIPCHK(launch_group(OP_REF_RESID, in, out, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->grid_cap, h->ws));
+    }
+    *launches += 3;
+    HIPCHK(hipMemcpyAsync(h->h_sc, h->sc, (size_t)S_NSCAL * kMaxK * 8, hipMemcpyDeviceToHost, h->ws));
+    HIPCHK(hipStreamSynchronize(h->ws));
+    ++*polls;
+    bool all_done = true;
+    for (int c = 0; c < k; ++c) {
+      const double rr = h->h_sc[(S_D0 + 0) * kMaxK + c], bb = h->h_sc[(S_D0 + 1) * kMaxK + c];
+      bnorm[c] = std::sqrt(bb);
+      relres[c] = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
+      scale[c] = 0.0;
+      if (status[c] != ST_RUNNING) continue;
+      if (!std::isfinite(bb) || !std::isfinite(rr)) {
+        status[c] = ST_NONFINITE;
+      } else if (bb == 0.0) {
+        status[c] = ST_CONVERGED;
+      } else if (rr < tol * tol * bb) {
+        status[c] = ST_CONVERGED;
+      } else if (outer == max_outer || iters[c] >= maxit) {
+        status[c] = ST_MAXIT;
+      } else {
+        scale[c] = std::sqrt(rr);
+        all_done = false;
+      }
+    }
+    // columns whose b is zero get x = 0
+    bool any_zero = false;
+    for (int c = 0; c < k; ++c) any_zero |= (bnorm[c] == 0.0 && std::isfinite(bnorm[c]));
+    if (any_zero && outer == 0) {
+      for (int c = 0; c < k; ++c) h->h_ist[I_ZEROB * kMaxK + c] = bnorm[c] == 0.0 ? 1 : 0;
+      HIPCHK(hipMemcpyAsync(h->ist + I_ZEROB * kMaxK, h->h_ist + I_ZEROB * kMaxK, kMaxK * 4, hipMemcpyHostToDevice,
+                            h->ws));
+      const void* in[7] = {};
+      void* out[5] = {x};
+      HIPCHK(launch_group(OP_ZEROB, in, out, (int)h->n, k, 0, F_NONE, ctl, false, h->grid_cap, h->ws));
+      ++*launches;
+    }
+    if (all_done) break;
+    // scaled FP32 right-hand side and d = 0
+    for (int c = 0; c < k; ++c) h->h_sc[S_SCALE * kMaxK + c] = scale[c];
+    HIPCHK(hipMemcpyAsync(h->sc + S_SCALE * kMaxK, h->h_sc + S_SCALE * kMaxK, kMaxK * 8, hipMemcpyHostToDevice,
+                          h->ws));
+    {
+      const void* in[7] = {R};
+      void* out[5] = {B32, D};
+      HIPCHK(launch_group(OP_REF_SCALE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+      ++*launches;
+    }
+    int rc = krylov(h, 0, true, B32, D, inner_tol, maxit, launches, polls, enq);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(h->h_ist, h->ist, (size_t)I_NINT * kMaxK * 4, hipMemcpyDeviceToHost, h->ws));
+    HIPCHK(hipStreamSynchronize(h->ws));
+    for (int c = 0; c < k; ++c)
+      if (scale[c] > 0) iters[c] += h->h_ist[I_ITERS * kMaxK + c];
+    // x += ||r_c|| d (the inner solve does not touch S_SCALE)
+    {
+      const void* in[7] = {x, D};
+      void* out[5] = {x};
+      HIPCHK(launch_group(OP_REF_UPDATE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+      ++*launches;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(h->ws));
+  if (info) {
+    for (int c = 0; c < k; ++c) {
+      if (info->iters) info->iters[c] = iters[c];
+      if (info->status) info->status[c] = status[c] == ST_RUNNING ? ST_MAXIT : status[c];
+      if (info->relres_true) info->relres_true[c] = relres[c];
+      if (info->relres_recursive) info->relres_recursive[c] = relres[c];
+    }
+  }
+  return BICGSTAB_OK;
+}
+
+int solve_common(bicgstab_ctx* h, int which, const double* b, double* x, double tol, int maxit,
+                 bicgstab_info* info) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (maxit < 0) return fail(BICGSTAB_EINVAL, "maxit < 0");
+  if (h->n > 0 && (!b || !x)) return fail(BICGSTAB_EINVAL, "null b or x");
+  HIPCHK(hipSetDevice(h->device));
+  int rc = prepare(h);
+  if (rc) return rc;
+  rc = begin_on_internal_stream(h);
+  if (rc) return rc;
+  int launches = 0, polls = 0, enq = 0;
+  if (fp32_inner(h)) {
+    if (which != 0) return fail(BICGSTAB_EUNSUPPORTED, "transpose solve in the FP32 tier");
+    rc = solve_refined(h, b, x, tol, maxit, info, &launches, &polls, &enq);
+  } else {
+    rc = krylov(h, which, false, b, x, tol, maxit, &launches, &polls, &enq);
+    if (!rc) rc = read_info(h, info);
+  }
+  h->stat_iters = enq;
+  h->stat_launches = launches;
+  h->stat_polls = polls;
+  return rc;
+}
+
+int build_transpose(bicgstab_ctx* h) {
+  if (h->have_t) return BICGSTAB_OK;
+  const int n = (int)h->n;
+  const int64_t nnz = h->nnz;
+  auto alloc = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 256)); };
+  HIPCHK(alloc((void**)&h->rp_t, (size_t)(n + 1) * 4));
+  HIPCHK(alloc((void**)&h->col_t, (size_t)nnz * 4));
+  HIPCHK(alloc((void**)&h->perm_t, (size_t)nnz * 4));
+  HIPCHK(alloc((void**)&h->val_t, (size_t)nnz * 8));
+  int32_t* counts = nullptr;
+  HIPCHK(alloc((void**)&counts, (size_t)(n + 1) * 4));
+  HIPCHK(hipMemsetAsync(counts, 0, (size_t)(n + 1) * 4, h->ws));
+  HIPCHK(launch_transpose_count(h->col, nnz, counts, h->ws));
+  HIPCHK(launch_scan(counts, h->rp_t, n, h->ws));
+  HIPCHK(hipMemsetAsync(counts, 0, (size_t)(n + 1) * 4, h->ws));
+  HIPCHK(launch_transpose_fill(h->row_ptr, h->col, n, h->rp_t, counts, h->col_t, h->perm_t, h->ws));
+  HIPCHK(launch_transpose_sort_rows(h->rp_t, h->col_t, h->perm_t, n, h->ws));
+  HIPCHK(launch_gather_values(h->val, h->perm_t, h->val_t, nnz, h->ws));
+  std::vector<int32_t> rp((size_t)n + 1);
+  HIPCHK(hipMemcpyAsync(rp.data(), h->rp_t, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, h->ws));
+  HIPCHK(hipStreamSynchronize(h->ws));
+  HIPCHK(hipFree(counts));
+  h->blk_t_host = spmm_partition(rp, h->k);
+  HIPCHK(alloc((void**)&h->blk_t, h->blk_t_host.size() * 4));
+  HIPCHK(hipMemcpyAsync(h->blk_t, h->blk_t_host.data(), h->blk_t_host.size() * 4, hipMemcpyHostToDevice, h->ws));
+  HIPCHK(hipStreamSynchronize(h->ws));
+  h->have_t = true;
+  return BICGSTAB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant, int32_t formulation,
+                    int32_t precond, int32_t precision, void* stream, bicgstab_t* out) {
+  if (!A || !out) return fail(BICGSTAB_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 0 || A->n != n) return fail(BICGSTAB_EINVAL, "matrix size does not match n");
+  if (n >= (int64_t)1 << 31) return fail(BICGSTAB_EINVAL, "n must fit int32");
+  if (k < 1 || k > BICGSTAB_MAX_K) return fail(BICGSTAB_EINVAL, "k must be in [1, 64]");
+  if ((int64_t)n * k >= ((int64_t)1 << 40)) return fail(BICGSTAB_EINVAL, "n*k too large");
+  if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) return fail(BICGSTAB_EINVAL, "nnz must fit int32");
+  if (precision != BICGSTAB_FP64 && precision != BICGSTAB_FP32_REFINE)
+    return fail(BICGSTAB_EINVAL, "unknown precision");
+  if (formulation == BICGSTAB_FUSED) return fail(BICGSTAB_EUNSUPPORTED, "fused formulation not available");
+  if (n > 0 && (!A->d_row_ptr || (A->nnz > 0 && (!A->d_col_idx || !A->d_values))))
+    return fail(BICGSTAB_EINVAL, "null matrix array");
+  bicgstab_ctx* h = new bicgstab_ctx();
+  h->n = n;
+  h->nnz = A->nnz;
+  h->k = k;
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  h->kp = kp;
+  h->variant = variant;
+  h->formulation = formulation;
+  h->precond = precond;
+  h->precision = precision;
+  h->row_ptr = A->d_row_ptr;
+  h->col = A->d_col_idx;
+  h->val = A->d_values;
+  h->user_stream = (hipStream_t)stream;
+  h->hist_cap = std::max(0, env_int("BICGSTAB_HIST_CAP", 1024));
+  h->grid_cap = std::max(8, env_int("BICGSTAB_GRID_CAP", 1024));
+  h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
+  h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;
+  std::string err;
+  if (!build_plan(variant, formulation, precond, &h->plan, &err)) {
+    delete h;
+    return fail(BICGSTAB_EINVAL, err);
+  }
+  auto bail = [&](int code, const std::string& m) {
+    if (h->ws) hipStreamDestroy(h->ws);
+    if (h->ev) hipEventDestroy(h->ev);
+    delete h;
+    return fail(code, m);
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(BICGSTAB_EHIP, "hipGetDevice failed");
+  if (hipStreamCreateWithFlags(&h->ws, hipStreamNonBlocking) != hipSuccess)
+    return bail(BICGSTAB_EHIP, "hipStreamCreate failed");
+  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess)
+    return bail(BICGSTAB_EHIP, "hipEventCreate failed");
+  // Read and validate the pattern once (host copy; also guards every kernel
+  // against out-of-range indices).
+  std::vector<int32_t> rp((size_t)n + 1, 0);
+  if (n > 0) {
+    if (hipStreamSynchronize(h->user_stream) != hipSuccess) return bail(BICGSTAB_EHIP, "stream sync failed");
+    if (hipMemcpy(rp.data(), A->d_row_ptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(BICGSTAB_EHIP, "reading row_ptr failed");
+    if (rp[0] != 0 || rp[n] != A->nnz) return bail(BICGSTAB_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+    for (int64_t i = 0; i < n; ++i)
+      if (rp[i + 1] < rp[i]) return bail(BICGSTAB_EINVAL, "row_ptr is not nondecreasing");
+    if (A->nnz > 0) {
+      std::vector<int32_t> cols((size_t)A->nnz);
+      if (hipMemcpy(cols.data(), A->d_col_idx, (size_t)A->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(BICGSTAB_EHIP, "reading col_idx failed");
+      for (int32_t c : cols)
+        if (c < 0 || c >= n) return bail(BICGSTAB_EINVAL, "column index out of range");
+    }
+  }
+  h->blk_host = spmm_partition(rp, k);
+  if (hipHostMalloc((void**)&h->h_nrun, 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_sc, (size_t)S_NSCAL * kMaxK * 8, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_ist, (size_t)I_NINT * kMaxK * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_glob, sizeof(Globals), hipHostMallocDefault) != hipSuccess)
+    return bail(BICGSTAB_ENOMEM, "pinned host allocation failed");
+  *out = h;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_workspace_bytes(bicgstab_t h, size_t* bytes) {
+  if (!h || !bytes) return fail(BICGSTAB_EINVAL, "null argument");
+  *bytes = layout(h, false);
+  return BICGSTAB_OK;
+}
+
+int bicgstab_set_workspace(bicgstab_t h, void* d_ptr, size_t bytes) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  const size_t need = layout(h, false);
+  if (!d_ptr || bytes < need) return fail(BICGSTAB_ENOMEM, "workspace too small");
+  if (((uintptr_t)d_ptr & 255) != 0) return fail(BICGSTAB_EINVAL, "workspace must be 256-byte aligned");
+  clear_graphs(h);
+  if (h->owned && h->base) hipFree(h->base);
+  h->base = (char*)d_ptr;
+  h->bytes = bytes;
+  h->owned = false;
+  h->prepared = false;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_set_stream(bicgstab_t h, void* stream) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  h->user_stream = (hipStream_t)stream;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_solve(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit, bicgstab_info* info) {
+  return solve_common(h, 0, d_b, d_x, tol, maxit, info);
+}
+
+int bicgstab_solve_transpose(bicgstab_t h, const double* d_g, double* d_lambda, double tol, int32_t maxit,
+                             bicgstab_info* info) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  HIPCHK(hipSetDevice(h->device));
+  int rc = prepare(h);
+  if (rc) return rc;
+  rc = begin_on_internal_stream(h);
+  if (rc) return rc;
+  rc = build_transpose(h);
+  if (rc) return rc;
+  return solve_common(h, 1, d_g, d_lambda, tol, maxit, info);
+}
+
+int bicgstab_grad_values(bicgstab_t h, const double* d_lambda, const double* d_x, double* d_grad) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (h->nnz == 0) return BICGSTAB_OK;
+  if (!d_lambda || !d_x || !d_grad) return fail(BICGSTAB_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(launch_grad_values(h->row_ptr, h->col, d_lambda, d_x, d_grad, (int)h->n, h->k, h->user_stream));
+  return BICGSTAB_OK;
+}
+
+int bicgstab_update_values(bicgstab_t h) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  HIPCHK(hipSetDevice(h->device));
+  int rc = begin_on_internal_stream(h);
+  if (rc) return rc;
+  h->prepared = false;
+  rc = prepare(h);
+  if (rc) return rc;
+  if (h->have_t) {
+    HIPCHK(launch_gather_values(h->val, h->perm_t, h->val_t, h->nnz, h->ws));
+    HIPCHK(hipStreamSynchronize(h->ws));
+  }
+  return BICGSTAB_OK;
+}
+
+int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (h->n == 0) return BICGSTAB_OK;
+  if (!d_x || !d_y) return fail(BICGSTAB_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(h->device));
+  int rc = prepare(h);
+  if (rc) return rc;
+  HIPCHK(launch_spmm(mat_of(h, 0, false), d_x, d_y, h->k, false, nullptr, h->user_stream));
+  return BICGSTAB_OK;
+}
+
+int bicgstab_history(bicgstab_t h, double* hist, int32_t cap, int32_t* count) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (count) *count = h->hist_count;
+  if (!hist || !h->hist || h->hist_count == 0) return BICGSTAB_OK;
+  const int rows = std::min<int>(h->hist_count, cap / std::max(1, h->k));
+  HIPCHK(hipMemcpy(hist, h->hist, (size_t)rows * h->k * 4 * 8, hipMemcpyDeviceToHost));
+  if (count) *count = rows;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_last_solve_stats(bicgstab_t h, int32_t* iterations_enqueued, int32_t* launches, int32_t* polls) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (iterations_enqueued) *iterations_enqueued = h->stat_iters;
+  if (launches) *launches = h->stat_launches;
+  if (polls) *polls = h->stat_polls;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_kernel_times(bicgstab_t h, const double* d_b, double* d_x, int32_t iters, int32_t cap, int32_t* kind,
+                          int32_t* op, int32_t* nin, int32_t* nout, double* ms, int32_t* nsteps) {
+  if (!h || !kind || !op || !nin || !nout || !ms || !nsteps) return fail(BICGSTAB_EINVAL, "null argument");
+  if (fp32_inner(h)) return fail(BICGSTAB_EUNSUPPORTED, "kernel timing of the FP32 tier");
+  if (iters < 1) return fail(BICGSTAB_EINVAL, "iters < 1");
+  HIPCHK(hipSetDevice(h->device));
+  int rc = prepare(h);
+  if (rc) return rc;
+  const int m = (int)h->plan.iter.size();
+  if (m > cap) return fail(BICGSTAB_EINVAL, "cap smaller than the number of launches per iteration");
+  hipStream_t s = h->user_stream;
+  const Ctl ctl = make_ctl(h);
+  const SpmmMat M = mat_of(h, 0, false);
+  void* vp[V_NUM];
+  for (int v = 0; v < V_NUM; ++v) vp[v] = h->vec[v];
+  vp[V_X] = d_x;
+  vp[V_B] = const_cast<double*>(d_b);
+  // fixed iteration count: stop test off, maxit beyond the timed passes
+  HIPCHK(launch_setup_state(ctl, -1.0, iters + 1, 0, s));
+  for (const Step& st : h->plan.init) HIPCHK(launch_step(h, st, M, vp, ctl, false, s));
+  std::vector<hipEvent_t> ev(2 * (size_t)m, nullptr);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  std::vector<double> acc((size_t)m, 0.0);
+  int result = BICGSTAB_OK;
+  for (int it = 0; it < iters && result == BICGSTAB_OK; ++it) {
+    for (int i = 0; i < m; ++i) {
+      hipEventRecord(ev[2 * i], s);
+      hipError_t e = launch_step(h, h->plan.iter[i], M, vp, ctl, false, s);
+      hipEventRecord(ev[2 * i + 1], s);
+      if (e != hipSuccess) {
+        result = fail(BICGSTAB_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        break;
+      }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      result = fail(BICGSTAB_EHIP, "stream synchronize failed");
+      break;
+    }
+    for (int i = 0; i < m && result == BICGSTAB_OK; ++i) {
+      float t = 0.f;
+      hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+      acc[i] += t;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (result) return result;
+  for (int i = 0; i < m; ++i) {
+    const Step& st = h->plan.iter[i];
+    kind[i] = (int)st.kind;
+    op[i] = st.kind == K_GROUP ? st.op : -1;
+    nin[i] = st.nin;
+    nout[i] = st.nout;
+    ms[i] = acc[i] / iters;
+  }
+  *nsteps = m;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_destroy(bicgstab_t h) {
+  if (!h) return BICGSTAB_OK;
+  hipSetDevice(h->device);
+  if (h->ws) hipStreamSynchronize(h->ws);
+  clear_graphs(h);
+  if (h->owned && h->base) hipFree(h->base);
+  for (void* p : {(void*)h->rp_t, (void*)h->col_t, (void*)h->perm_t, (void*)h->val_t, (void*)h->val32_t,
+                  (void*)h->blk_t})
+    if (p) hipFree(p);
+  for (void* p : {(void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
+    if (p) hipHostFree(p);
+  if (h->ws) hipStreamDestroy(h->ws);
+  if (h->ev) hipEventDestroy(h->ev);
+  delete h;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond, int32_t* reads, int32_t* writes,
+                          int32_t* precond_apps, int32_t* spmms, int32_t* launches) {
+  Plan P;
+  std::string err;
+  if (!build_plan(variant, formulation, precond, &P, &err)) return fail(BICGSTAB_EINVAL, err);
+  int r = 0, w = 0, pa = 0, sp = 0;
+  for (const Step& s : P.iter) {
+    if (s.kind == K_GROUP) {
+      r += s.nin;
+      w += s.nout;
+    } else if (s.kind == K_PREC) {
+      ++pa;
+    } else {
+      ++sp;
+    }
+  }
+  if (reads) *reads = r;
+  if (writes) *writes = w;
+  if (precond_apps) *precond_apps = pa;
+  if (spmms) *spmms = sp;
+  if (launches) *launches = (int)P.iter.size();
+  return BICGSTAB_OK;
+}
+
+const char* bicgstab_strerror(int code) {
+  switch (code) {
+    case BICGSTAB_OK: return "ok";
+    case BICGSTAB_EINVAL: return "invalid argument";
+    case BICGSTAB_EHIP: return "HIP runtime error";
+    case BICGSTAB_ENOMEM: return "out of memory / workspace too small";
+    case BICGSTAB_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+const char* bicgstab_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

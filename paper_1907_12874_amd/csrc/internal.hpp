@@ -1,0 +1,188 @@
+// Internal definitions shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace bcg {
+
+constexpr int kBlock = 256;       // threads per workgroup for every kernel
+constexpr int kMaxK = 64;         // columns per handle (one wavefront of lanes)
+constexpr int kSpmmNnzMax = 2048; // CSR entries staged in LDS per SpMM row block
+constexpr int kSpmmRowsMax = 256; // rows per SpMM row block
+
+// ---- per-column device state: scalars sc[slot * kMaxK + c] -----------------
+enum ScalarSlot {
+  S_RHO = 0,
+  S_ALPHA,
+  S_OMEGA,
+  S_BETA,
+  S_EPS2,
+  S_BB,
+  S_EST,
+  S_RELRES_TRUE,
+  S_RELRES_REC,
+  S_RHONEXT,
+  S_SCALE,  // refinement: ||r_c|| of the outer residual
+  S_D0,  // dot results D0..D6 follow
+  S_NSCAL = S_D0 + 7
+};
+// ---- per-column ints ist[slot * kMaxK + c] ------------------------------------
+enum IntSlot { I_STATUS = 0, I_PEND, I_ITERS, I_ZEROB, I_NINT };
+// ---- globals -----------------------------------------------------------------
+struct Globals {
+  int nrun;      // columns with status RUNNING; every iteration kernel exits at once when 0
+  int it;        // passes completed
+  int maxit;
+  int hist_cap;  // history rows available
+  double tol;
+  int zero_diag; // Jacobi setup: number of zero diagonal entries
+  int pad;
+};
+
+constexpr int ST_RUNNING = -1;
+constexpr int ST_CONVERGED = 0;
+constexpr int ST_MAXIT = 1;
+constexpr int ST_BREAKDOWN = 2;
+constexpr int ST_NONFINITE = 3;
+
+// Finalize steps: the scalar recurrence run by the last workgroup of a
+// reduction (or of a dot-free kernel that closes an iteration).
+enum FinStep {
+  F_NONE = 0,
+  F_INIT,           // D0=(r,r) D1=(b,b): eps^2, rho_0, early stops
+  F_ALPHA,          // D0=delta: alpha = rho/delta
+  F_OMEGA_MERGED,   // D0=phi D1=psi D2=theta: omega, theta-omega*phi stop test
+  F_OMEGA_BASIC,    // D0=phi D1=psi: omega
+  F_CONV_BASIC,     // D2=(r,r): explicit stop test
+  F_BETA_END,       // D3=rho': beta, then close the iteration
+  F_RE_OMEGA,       // D0=theta D1=phi D2=psi D3=eta: omega, stop, rho'=-omega psi, beta
+  F_END,            // close the iteration
+  F_PIPE_INIT,      // D0=(r0,w0): alpha_0
+  F_PIPE_OMEGA,     // D0=theta D1=phi D2=pi: omega, pi-omega*theta stop test
+  F_PIPE_BETA_END,  // D3=rho' D4=psi D5=sigma D6=delta: beta, alpha_{j+1}, close
+  F_EXIT,           // D0=||b-Ax||^2 D1=||r||^2: relative residuals
+  F_REFINE_NORM,    // refinement: D0=||r||^2, D1=||b||^2 of the outer residual
+};
+
+// Pointers to the per-solve device state, passed by value to kernels.
+struct Ctl {
+  double* sc;
+  int* ist;
+  Globals* glob;
+  double* partials;
+  unsigned* counter;
+  double* hist;
+  int k;
+};
+
+// ---- vector-operation kernels ("groups") ---------------------------------------
+// Every group is one streaming pass over n x k blocks. Ops are named after the
+// statement(s) they perform; see kernels.hip for their bodies.
+enum OpId {
+  OP_INIT = 0,     // r = b - z; r0 = r; dots (r,r), (b,b)
+  OP_INIT_P,       // same, plus p = r
+  OP_ZEROB,        // x_c = 0 for columns whose b_c = 0
+  OP_COPY,         // out = in
+  OP_FILL0,        // out = 0
+  OP_EXIT,         // dots (b - z, b - z), (r, r)
+  OP_DOT,          // dot (u, w)
+  OP_DOTSELF,      // dot (u, u)
+  OP_SUB_ALPHA,    // out = a - alpha * b
+  OP_SUB_OMEGA,    // out = a - omega * b
+  OP_XUPD,         // x = x + alpha * a + omega * b
+  OP_PUPD,         // out = a + beta * (out - omega * b)   (p-type three-vector update)
+  OP_C_PPT,        // dots (t,s), (t,t), (s,s)
+  OP_C_XR_RHO,     // x += alpha p + omega s; r = s - omega t; dot (r, r0)
+  OP_C_R_RHO,      // r = s - omega t; dot (r, r0)
+  OP_R_G3,         // rt = r - alpha v; dots (t,rt), (t,t), (t,r0), (rt,rt)
+  OP_R_XZV,        // x += alpha vh + omega th; z = th - omega q; vh = z + beta (vh - omega s)
+  OP_P_G1,         // Alg. 4 first group (p, s, z, q, y; theta, phi, pi)
+  OP_P_G2,         // x += alpha p + omega q; r = q - omega y
+  OP_P_G3,         // w = y - omega (t - alpha v); dots (r0,r), (r0,z), (r0,w), (r0,s)
+  OP_PP_G1,        // Alg. 7: ph, sh, qh
+  OP_PP_G2,        // Alg. 7: s, z, q, y; theta, phi, pi
+  OP_PP_G3,        // Alg. 7: x += alpha ph + omega qh; rh = qh - omega (wh - alpha zh)
+  OP_PP_G4,        // Alg. 7: r = q - omega y; w = y - omega (t - alpha v); 4 dots
+  OP_REF_RESID,    // refinement: r = b - z (FP64); dots (r,r), (b,b)
+  OP_REF_SCALE,    // refinement: r32 = r / ||r_c|| (to FP32), d = 0
+  OP_REF_UPDATE,   // refinement: x = x + ||r_c|| * d
+  OP_NUM
+};
+
+// Vector names used by the launch plans (indices into the handle's table).
+enum VecId {
+  V_NONE = -1,
+  V_X = 0,  // user solution / initial guess
+  V_B,      // user right-hand side
+  V_R, V_R0, V_P, V_V, V_S, V_T, V_Z, V_PH, V_SH, V_TH, V_RT, V_Q, V_VH, V_W, V_WH, V_Y, V_QH, V_RH, V_ZH,
+  V_NUM
+};
+
+enum StepKind { K_SPMM = 0, K_PREC, K_GROUP };
+
+struct Step {
+  StepKind kind;
+  int op;        // OpId for K_GROUP
+  int in[6];     // VecIds
+  int out[4];
+  int slot;      // first dot slot written
+  int fin;       // FinStep
+  int nin, nout; // vector reads / writes of the pass (traffic accounting)
+};
+
+struct Plan {
+  std::vector<Step> init;  // before the loop
+  std::vector<Step> iter;  // one iteration
+  std::vector<int> vecs;   // VecIds the plan touches (beside x and b)
+  int alias_from[V_NUM];   // alias_from[v] = u: vector v is the same storage as u
+};
+
+// Builds the launch plan of (variant, formulation, precond). Returns false on
+// an unknown combination.
+bool build_plan(int variant, int formulation, int precond, Plan* plan, std::string* err);
+
+// Static description of every op (for traffic accounting and validation).
+struct OpInfo {
+  int nin, nout, ndot;
+  const char* name;
+};
+const OpInfo& op_info(int op);
+
+// ---- device launchers (kernels.hip) ------------------------------------------
+struct SpmmMat {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const void* val;   // double or float
+  const int32_t* blk;  // row-block starts, nblk + 1 entries
+  int nblk;
+  int n;
+};
+
+hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
+                       hipStream_t s);
+hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k, bool fp32, const Globals* glob,
+                       hipStream_t s);
+hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
+                        const Ctl& ctl, bool fp32, int grid_cap, hipStream_t s);
+hipError_t launch_setup_state(const Ctl& ctl, double tol, int maxit, int hist_cap, hipStream_t s);
+hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
+hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,
+                               float* diag32, int n, Globals* glob, hipStream_t s);
+hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t s);
+hipError_t launch_grad_values(const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
+                              double* grad, int n, int k, hipStream_t s);
+hipError_t launch_transpose_count(const int32_t* col, int64_t nnz, int32_t* counts, hipStream_t s);
+hipError_t launch_scan(const int32_t* counts, int32_t* row_ptr_t, int n, hipStream_t s);
+hipError_t launch_transpose_fill(const int32_t* row_ptr, const int32_t* col, int n, const int32_t* row_ptr_t,
+                                 int32_t* cursor, int32_t* col_t, int32_t* perm, hipStream_t s);
+hipError_t launch_transpose_sort_rows(const int32_t* row_ptr_t, int32_t* col_t, int32_t* perm, int n, hipStream_t s);
+hipError_t launch_gather_values(const double* val, const int32_t* perm, double* val_t, int64_t nnz, hipStream_t s);
+
+// Row-block partition for the CSR-stream SpMM (host).
+std::vector<int32_t> spmm_partition(const std::vector<int32_t>& row_ptr, int k);
+
+}  // namespace bcg

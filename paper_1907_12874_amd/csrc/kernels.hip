@@ -1,0 +1,1165 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// Everything on the BiCGStab path is bound by HBM bandwidth (a sparse product
+// and streaming vector passes of 0.1-0.75 flop per byte), so nothing here uses
+// the matrix cores. The kernels are written for memory traffic:
+//   * n x k blocks are row-major; a workgroup of 256 lanes covers 256/kp rows
+//     x kp columns (kp = k rounded up to a power of two, at most 64), so each
+//     load instruction of a wave reads whole contiguous rows;
+//   * the sparse product stages a row block's CSR entries in LDS with
+//     coalesced loads (a CSR-stream layout), then gathers X rows;
+//   * a vector pass computes all its dot products (one per column) while it
+//     streams, reduces them inside the wave with xor shuffles between lanes of
+//     the same column, across waves through LDS, and across workgroups in the
+//     last workgroup to finish (a fixed summation order, so results are
+//     bitwise repeatable), which then runs the per-column scalar recurrence;
+//   * all arithmetic is IEEE with no contraction (the library is built with
+//     -ffp-contract=off) and Jacobi divides by a_ii, so the vector updates and
+//     the products round exactly like a plain sequential evaluation.
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace bcg {
+
+// ------------------------------------------------------------------ helpers ---
+
+template <class T>
+__device__ __forceinline__ double ldv(const void* p, size_t e) {
+  return (double)static_cast<const T*>(p)[e];
+}
+template <class T>
+__device__ __forceinline__ void stv(void* p, size_t e, double v) {
+  static_cast<T*>(p)[e] = (T)v;
+}
+
+__device__ __forceinline__ int log2_pow2(int kp) { return 31 - __clz(kp); }
+
+__host__ __device__ inline int pad_k(int k) {
+  int kp = 1;
+  while (kp < k) kp <<= 1;
+  return kp;
+}
+
+struct Coef {
+  double alpha, omega, beta, scale;
+};
+
+// ------------------------------------------------------------ op bodies ---
+// Each op: NIN inputs, NOUT outputs, NDOT dot products per column. XIN / XOUT
+// are bitmasks of inputs / outputs that are always FP64 (the solution block);
+// the others have the Krylov type T. PART says which columns take part:
+// running columns, every column, or the columns whose right-hand side is zero.
+enum Part { PART_RUN = 0, PART_ALL = 1, PART_ZEROB = 2 };
+
+#define OP_HEAD(NI, NO, ND, XI, XO, PT, EARLY_)          \
+  static constexpr int NIN = NI, NOUT = NO, NDOT = ND;   \
+  static constexpr unsigned XIN = XI, XOUT = XO;         \
+  static constexpr int PART = PT;                        \
+  static constexpr bool EARLY = EARLY_;
+#define OP_F                                                                                  \
+  __device__ __forceinline__ static void f(const double* v, const Coef& c, double* o, double* a)
+
+struct KInit {  // r = b - z; r0 = r; (r, r), (b, b)
+  OP_HEAD(2, 2, 2, 0, 0, PART_RUN, true)
+  OP_F {
+    double r = v[0] - v[1];
+    o[0] = r;
+    o[1] = r;
+    a[0] += r * r;
+    a[1] += v[0] * v[0];
+  }
+};
+struct KInitP {  // r = b - z; r0 = r; p = r; (r, r), (b, b)
+  OP_HEAD(2, 3, 2, 0, 0, PART_RUN, true)
+  OP_F {
+    double r = v[0] - v[1];
+    o[0] = r;
+    o[1] = r;
+    o[2] = r;
+    a[0] += r * r;
+    a[1] += v[0] * v[0];
+  }
+};
+struct KZeroB {  // x = 0 where b = 0
+  OP_HEAD(0, 1, 0, 0, 1, PART_ZEROB, false)
+  OP_F { o[0] = 0.0; }
+};
+struct KCopy {
+  OP_HEAD(1, 1, 0, 0, 0, PART_ALL, true)
+  OP_F { o[0] = v[0]; }
+};
+struct KFill0 {
+  OP_HEAD(0, 1, 0, 0, 0, PART_ALL, true)
+  OP_F { o[0] = 0.0; }
+};
+struct KExit {  // in: b, z = A x, r ; dots (b - z, b - z), (r, r)
+  OP_HEAD(3, 0, 2, 0, 0, PART_ALL, false)
+  OP_F {
+    double d = v[0] - v[1];
+    a[0] += d * d;
+    a[1] += v[2] * v[2];
+  }
+};
+struct KDot {
+  OP_HEAD(2, 0, 1, 0, 0, PART_RUN, true)
+  OP_F { a[0] += v[0] * v[1]; }
+};
+struct KDotSelf {
+  OP_HEAD(1, 0, 1, 0, 0, PART_RUN, true)
+  OP_F { a[0] += v[0] * v[0]; }
+};
+struct KSubAlpha {  // out = a - alpha b
+  OP_HEAD(2, 1, 0, 0, 0, PART_RUN, true)
+  OP_F { o[0] = v[0] - c.alpha * v[1]; }
+};
+struct KSubOmega {  // out = a - omega b
+  OP_HEAD(2, 1, 0, 0, 0, PART_RUN, true)
+  OP_F { o[0] = v[0] - c.omega * v[1]; }
+};
+struct KXUpd {  // x = x + alpha a + omega b
+  OP_HEAD(3, 1, 0, 1, 1, PART_RUN, true)
+  OP_F { o[0] = v[0] + c.alpha * v[1] + c.omega * v[2]; }
+};
+struct KPUpd {  // in: a, u, b ; out = a + beta (u - omega b)
+  OP_HEAD(3, 1, 0, 0, 0, PART_RUN, true)
+  OP_F { o[0] = v[0] + c.beta * (v[1] - c.omega * v[2]); }
+};
+struct KCPpt {  // in: t, s ; (t, s), (t, t), (s, s)
+  OP_HEAD(2, 0, 3, 0, 0, PART_RUN, true)
+  OP_F {
+    a[0] += v[0] * v[1];
+    a[1] += v[0] * v[0];
+    a[2] += v[1] * v[1];
+  }
+};
+struct KCXrRho {  // in: x, p, s, t, r0 ; out: x, r
+  OP_HEAD(5, 2, 1, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    double r = v[2] - c.omega * v[3];
+    o[1] = r;
+    a[0] += r * v[4];
+  }
+};
+struct KCRRho {  // in: s, t, r0 ; out: r
+  OP_HEAD(3, 1, 1, 0, 0, PART_RUN, true)
+  OP_F {
+    double r = v[0] - c.omega * v[1];
+    o[0] = r;
+    a[0] += r * v[2];
+  }
+};
+struct KRG3 {  // in: r, v, t, r0 ; out: rt ; (t, rt), (t, t), (t, r0), (rt, rt)
+  OP_HEAD(4, 1, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    double rt = v[0] - c.alpha * v[1];
+    o[0] = rt;
+    a[0] += v[2] * rt;
+    a[1] += v[2] * v[2];
+    a[2] += v[2] * v[3];
+    a[3] += rt * rt;
+  }
+};
+struct KRXzv {  // in: x, vh, th, q, s ; out: x, z, vh
+  OP_HEAD(5, 3, 0, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    double z = v[2] - c.omega * v[3];
+    o[1] = z;
+    o[2] = z + c.beta * (v[1] - c.omega * v[4]);
+  }
+};
+struct KPG1 {  // in: r, p, s, w, z, t, v ; out: p, s, z, q, y ; (q, y), (y, y), (q, q)
+  OP_HEAD(7, 5, 3, 0, 0, PART_RUN, true)
+  OP_F {
+    double p = v[0] + c.beta * (v[1] - c.omega * v[2]);
+    double s = v[3] + c.beta * (v[2] - c.omega * v[4]);
+    double z = v[5] + c.beta * (v[4] - c.omega * v[6]);
+    double q = v[0] - c.alpha * s;
+    double y = v[3] - c.alpha * z;
+    o[0] = p;
+    o[1] = s;
+    o[2] = z;
+    o[3] = q;
+    o[4] = y;
+    a[0] += q * y;
+    a[1] += y * y;
+    a[2] += q * q;
+  }
+};
+struct KPG2 {  // in: x, p, q, y ; out: x, r
+  OP_HEAD(4, 2, 0, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    o[1] = v[2] - c.omega * v[3];
+  }
+};
+struct KPG3 {  // in: y, t, v, r0, r, z, s ; out: w ; (r0,r), (r0,z), (r0,w), (r0,s)
+  OP_HEAD(7, 1, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    double w = v[0] - c.omega * (v[1] - c.alpha * v[2]);
+    o[0] = w;
+    a[0] += v[3] * v[4];
+    a[1] += v[3] * v[5];
+    a[2] += v[3] * w;
+    a[3] += v[3] * v[6];
+  }
+};
+struct KPPG1 {  // in: rh, ph, sh, wh, zh ; out: ph, sh, qh
+  OP_HEAD(5, 3, 0, 0, 0, PART_RUN, true)
+  OP_F {
+    double ph = v[0] + c.beta * (v[1] - c.omega * v[2]);
+    double sh = v[3] + c.beta * (v[2] - c.omega * v[4]);
+    o[0] = ph;
+    o[1] = sh;
+    o[2] = v[0] - c.alpha * sh;
+  }
+};
+struct KPPG2 {  // in: w, s, z, t, v, r ; out: s, z, q, y ; (q, y), (y, y), (q, q)
+  OP_HEAD(6, 4, 3, 0, 0, PART_RUN, true)
+  OP_F {
+    double s = v[0] + c.beta * (v[1] - c.omega * v[2]);
+    double z = v[3] + c.beta * (v[2] - c.omega * v[4]);
+    double q = v[5] - c.alpha * s;
+    double y = v[0] - c.alpha * z;
+    o[0] = s;
+    o[1] = z;
+    o[2] = q;
+    o[3] = y;
+    a[0] += q * y;
+    a[1] += y * y;
+    a[2] += q * q;
+  }
+};
+struct KPPG3 {  // in: x, ph, qh, wh, zh ; out: x, rh
+  OP_HEAD(5, 2, 0, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    o[1] = v[2] - c.omega * (v[3] - c.alpha * v[4]);
+  }
+};
+struct KPPG4 {  // in: q, y, t, v, r0, z, s ; out: r, w ; (r0,r), (r0,z), (r0,w), (r0,s)
+  OP_HEAD(7, 2, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    double r = v[0] - c.omega * v[1];
+    double w = v[1] - c.omega * (v[2] - c.alpha * v[3]);
+    o[0] = r;
+    o[1] = w;
+    a[0] += v[4] * r;
+    a[1] += v[4] * v[5];
+    a[2] += v[4] * w;
+    a[3] += v[4] * v[6];
+  }
+};
+// Refinement passes (outer loop of the FP32 tier). Inputs/outputs marked in
+// XIN/XOUT are FP64; the rest are the inner (FP32) Krylov type.
+struct KRefResid {  // in: b, z (FP64) ; out: r (FP64) ; (r, r), (b, b)
+  OP_HEAD(2, 1, 2, 3, 1, PART_ALL, false)
+  OP_F {
+    double r = v[0] - v[1];
+    o[0] = r;
+    a[0] += r * r;
+    a[1] += v[0] * v[0];
+  }
+};
+struct KRefScale {  // in: r (FP64) ; out: rs = r / ||r_c|| (T), d = 0 (FP64)
+  OP_HEAD(1, 2, 0, 1, 2, PART_ALL, false)
+  OP_F {
+    o[0] = c.scale > 0.0 ? v[0] / c.scale : 0.0;
+    o[1] = 0.0;
+  }
+};
+struct KRefUpdate {  // in: x, d (FP64) ; out: x = x + ||r_c|| d
+  OP_HEAD(2, 1, 0, 3, 1, PART_ALL, false)
+  OP_F { o[0] = v[0] + c.scale * v[1]; }
+};
+
+// ------------------------------------------------------- scalar recurrence ---
+
+__device__ __forceinline__ double& SC(const Ctl& C, int slot, int c) { return C.sc[slot * kMaxK + c]; }
+__device__ __forceinline__ int& IS(const Ctl& C, int slot, int c) { return C.ist[slot * kMaxK + c]; }
+
+__device__ void record_history(const Ctl& C, int c, double alpha, double omega, double rho, double est) {
+  const int it = C.glob->it;
+  if (C.hist && it < C.glob->hist_cap) {
+    double* h = C.hist + ((size_t)it * C.k + c) * 4;
+    h[0] = alpha;
+    h[1] = omega;
+    h[2] = rho;
+    h[3] = est;
+  }
+}
+
+// Close an iteration for column c: a pending stop takes effect, or maxit.
+__device__ void end_column(const Ctl& C, int c) {
+  const int it1 = C.glob->it + 1;
+  int& st = IS(C, I_STATUS, c);
+  int& pend = IS(C, I_PEND, c);
+  if (pend >= 0) {
+    st = pend;
+    IS(C, I_ITERS, c) = it1;
+  } else if (it1 >= C.glob->maxit) {
+    st = ST_MAXIT;
+    IS(C, I_ITERS, c) = it1;
+  }
+}
+
+// Per-column scalar work of a finalize step (see the FinStep list).
+__device__ void finalize_column(int step, int c, const Ctl& C) {
+  int& st = IS(C, I_STATUS, c);
+  const double D0 = SC(C, S_D0 + 0, c), D1 = SC(C, S_D0 + 1, c), D2 = SC(C, S_D0 + 2, c);
+  const double D3 = SC(C, S_D0 + 3, c);
+  if (step == F_INIT) {
+    const double rr = D0, bb = D1;
+    SC(C, S_BB, c) = bb;
+    IS(C, I_PEND, c) = -1;
+    IS(C, I_ITERS, c) = 0;
+    IS(C, I_ZEROB, c) = 0;
+    SC(C, S_ALPHA, c) = 0.0;
+    SC(C, S_OMEGA, c) = 1.0;
+    SC(C, S_BETA, c) = 0.0;
+    SC(C, S_EST, c) = rr;
+    if (!isfinite(bb)) {
+      st = ST_NONFINITE;
+      return;
+    }
+    if (bb == 0.0) {
+      st = ST_CONVERGED;
+      IS(C, I_ZEROB, c) = 1;
+      return;
+    }
+    const double tol = C.glob->tol;
+    const double eps2 = tol > 0.0 ? tol * tol * bb : -INFINITY;
+    SC(C, S_EPS2, c) = eps2;
+    if (!isfinite(rr)) {
+      st = ST_NONFINITE;
+      return;
+    }
+    if (rr < eps2) {
+      st = ST_CONVERGED;
+      return;
+    }
+    SC(C, S_RHO, c) = rr;
+    return;
+  }
+  if (step == F_EXIT) {
+    const double bb = SC(C, S_BB, c);
+    if (bb == 0.0) {
+      SC(C, S_RELRES_TRUE, c) = 0.0;
+      SC(C, S_RELRES_REC, c) = 0.0;
+    } else {
+      SC(C, S_RELRES_TRUE, c) = sqrt(D0) / sqrt(bb);
+      SC(C, S_RELRES_REC, c) = sqrt(D1) / sqrt(bb);
+    }
+    return;
+  }
+  if (step == F_REFINE_NORM) {
+    // outer residual of the refinement loop: D0 = ||r||^2, D1 = ||b||^2
+    SC(C, S_EST, c) = D0;
+    SC(C, S_SCALE, c) = sqrt(D0);
+    return;
+  }
+  if (st != ST_RUNNING) return;
+  const int it1 = C.glob->it + 1;
+  int& pend = IS(C, I_PEND, c);
+  auto stop = [&](int s) {
+    st = s;
+    IS(C, I_ITERS, c) = it1;
+  };
+  const double eps2 = SC(C, S_EPS2, c);
+  switch (step) {
+    case F_ALPHA: {
+      const double delta = D0;
+      if (delta == 0.0) {
+        stop(ST_BREAKDOWN);
+        return;
+      }
+      const double alpha = SC(C, S_RHO, c) / delta;
+      if (!isfinite(alpha)) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_ALPHA, c) = alpha;
+      return;
+    }
+    case F_OMEGA_MERGED: {
+      const double phi = D0, psi = D1, theta = D2;
+      const double omega = psi != 0.0 ? phi / psi : 0.0;
+      const double est = theta - omega * phi;
+      if (!(isfinite(omega) && isfinite(est))) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_OMEGA, c) = omega;
+      SC(C, S_EST, c) = est;
+      if (est < eps2)
+        pend = ST_CONVERGED;
+      else if (omega == 0.0)
+        pend = ST_BREAKDOWN;
+      return;
+    }
+    case F_OMEGA_BASIC: {
+      const double phi = D0, psi = D1;
+      const double omega = psi != 0.0 ? phi / psi : 0.0;
+      if (!isfinite(omega)) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_OMEGA, c) = omega;
+      return;
+    }
+    case F_CONV_BASIC: {
+      const double rr = D2;
+      SC(C, S_EST, c) = rr;
+      if (!isfinite(rr)) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      if (rr < eps2) {
+        record_history(C, c, SC(C, S_ALPHA, c), SC(C, S_OMEGA, c), SC(C, S_RHO, c), rr);
+        stop(ST_CONVERGED);
+        return;
+      }
+      if (SC(C, S_OMEGA, c) == 0.0) stop(ST_BREAKDOWN);
+      return;
+    }
+    case F_BETA_END: {
+      const double alpha = SC(C, S_ALPHA, c), omega = SC(C, S_OMEGA, c), rho = SC(C, S_RHO, c);
+      if (pend < 0) {
+        const double rho1 = D3;
+        if (rho1 == 0.0) {
+          stop(ST_BREAKDOWN);
+          return;
+        }
+        const double beta = (rho1 / rho) * (alpha / omega);
+        if (!isfinite(beta)) {
+          stop(ST_NONFINITE);
+          return;
+        }
+        SC(C, S_BETA, c) = beta;
+        SC(C, S_RHO, c) = rho1;
+      }
+      record_history(C, c, alpha, omega, rho, SC(C, S_EST, c));
+      end_column(C, c);
+      return;
+    }
+    case F_RE_OMEGA: {
+      const double theta = D0, phi = D1, psi = D2, eta = D3;
+      const double omega = phi != 0.0 ? theta / phi : 0.0;
+      const double est = eta - omega * theta;
+      if (!(isfinite(omega) && isfinite(est))) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_OMEGA, c) = omega;
+      SC(C, S_EST, c) = est;
+      if (est < eps2) {
+        pend = ST_CONVERGED;
+        return;
+      }
+      const double rho1 = -omega * psi;
+      if (omega == 0.0 || rho1 == 0.0) {
+        pend = ST_BREAKDOWN;
+        return;
+      }
+      const double beta = (rho1 / SC(C, S_RHO, c)) * (SC(C, S_ALPHA, c) / omega);
+      if (!isfinite(beta)) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_BETA, c) = beta;
+      SC(C, S_RHONEXT, c) = rho1;
+      return;
+    }
+    case F_END: {
+      record_history(C, c, SC(C, S_ALPHA, c), SC(C, S_OMEGA, c), SC(C, S_RHO, c), SC(C, S_EST, c));
+      if (pend < 0) SC(C, S_RHO, c) = SC(C, S_RHONEXT, c);
+      end_column(C, c);
+      return;
+    }
+    case F_PIPE_INIT: {
+      const double rw = D0;
+      if (rw == 0.0) {
+        st = ST_BREAKDOWN;
+        IS(C, I_ITERS, c) = 0;
+        return;
+      }
+      const double alpha = SC(C, S_RHO, c) / rw;
+      if (!isfinite(alpha)) {
+        st = ST_NONFINITE;
+        IS(C, I_ITERS, c) = 0;
+        return;
+      }
+      SC(C, S_ALPHA, c) = alpha;
+      return;
+    }
+    case F_PIPE_OMEGA: {
+      const double theta = D0, phi = D1, pi = D2;
+      const double omega = phi != 0.0 ? theta / phi : 0.0;
+      const double est = pi - omega * theta;
+      if (!(isfinite(omega) && isfinite(est))) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_OMEGA, c) = omega;
+      SC(C, S_EST, c) = est;
+      if (est < eps2)
+        pend = ST_CONVERGED;
+      else if (omega == 0.0)
+        pend = ST_BREAKDOWN;
+      return;
+    }
+    case F_PIPE_BETA_END: {
+      const double alpha = SC(C, S_ALPHA, c), omega = SC(C, S_OMEGA, c), rho = SC(C, S_RHO, c);
+      if (pend < 0) {
+        const double rho1 = D3, psi = SC(C, S_D0 + 4, c), sigma = SC(C, S_D0 + 5, c), delta = SC(C, S_D0 + 6, c);
+        if (rho1 == 0.0) {
+          stop(ST_BREAKDOWN);
+          return;
+        }
+        const double beta = (alpha / omega) * (rho1 / rho);
+        const double denom = sigma + beta * delta - beta * omega * psi;
+        if (denom == 0.0) {
+          stop(ST_BREAKDOWN);
+          return;
+        }
+        const double alpha1 = rho1 / denom;
+        if (!(isfinite(beta) && isfinite(alpha1))) {
+          stop(ST_NONFINITE);
+          return;
+        }
+        SC(C, S_BETA, c) = beta;
+        SC(C, S_ALPHA, c) = alpha1;
+        SC(C, S_RHO, c) = rho1;
+      }
+      record_history(C, c, alpha, omega, rho, SC(C, S_EST, c));
+      end_column(C, c);
+      return;
+    }
+    default:
+      return;
+  }
+}
+
+__device__ __forceinline__ bool closes_iteration(int step) {
+  return step == F_BETA_END || step == F_END || step == F_PIPE_BETA_END;
+}
+
+// Run by thread 0 of the last workgroup after finalize_column.
+__device__ void finalize_global(int step, const Ctl& C) {
+  if (closes_iteration(step)) C.glob->it += 1;
+  int nrun = 0;
+  for (int c = 0; c < C.k; ++c) nrun += IS(C, I_STATUS, c) == ST_RUNNING;
+  C.glob->nrun = nrun;
+}
+
+// ---------------------------------------------------- cross-block reduction ---
+
+struct GArgs {
+  const void* in[7];
+  void* out[5];
+  long n;
+  int k, kpl, slot, fin;
+  Ctl ctl;
+};
+
+// Sum the per-workgroup partials (P = ndot * k values per workgroup) in the
+// last workgroup to arrive, write the results to the dot slots, then run the
+// finalize step. The order of every sum is fixed by the grid, not by timing.
+__device__ void last_block_finish(const GArgs& a, int ndot) {
+  __shared__ int s_last;
+  __shared__ double s_g[kBlock];
+  const int k = a.k;
+  const int P = ndot * k;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(a.ctl.counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  const double* part = a.ctl.partials;
+  const int t = threadIdx.x;
+  if (P > 0) {
+    if (P <= kBlock) {
+      const int G = kBlock / P;
+      double v = 0.0;
+      if (t < G * P) {
+        const int p = t % P, g = t / P;
+        for (int b = g; b < nb; b += G) v += __builtin_nontemporal_load(&part[(size_t)b * P + p]);
+      }
+      s_g[t] = v;
+      __syncthreads();
+      if (t < P) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += s_g[g * P + t];
+        const int d = t / k, c = t - d * k;
+        SC(a.ctl, S_D0 + a.slot + d, c) = s;
+      }
+    } else {
+      for (int p = t; p < P; p += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += __builtin_nontemporal_load(&part[(size_t)b * P + p]);
+        const int d = p / k, c = p - d * k;
+        SC(a.ctl, S_D0 + a.slot + d, c) = s;
+      }
+    }
+  }
+  __syncthreads();
+  if (a.fin != F_NONE && t < k) finalize_column(a.fin, t, a.ctl);
+  __syncthreads();
+  if (t == 0) {
+    if (a.fin != F_NONE) finalize_global(a.fin, a.ctl);
+    *a.ctl.counter = 0u;
+  }
+}
+
+template <int ND>
+__device__ void block_reduce_and_finish(const double* acc, const GArgs& a) {
+  __shared__ double s_w[kBlock / 64][ND][kMaxK];
+  const int kp = 1 << a.kpl;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double v = acc[d];
+    for (int off = kp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    if (lane < kp) s_w[wave][d][lane] = v;
+  }
+  __syncthreads();
+  const int k = a.k, P = ND * k;
+  double* part = a.ctl.partials + (size_t)blockIdx.x * P;
+  for (int t = threadIdx.x; t < P; t += kBlock) {
+    const int d = t / k, c = t - d * k;
+    double v = s_w[0][d][c];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) v += s_w[w][d][c];
+    part[t] = v;
+  }
+  last_block_finish(a, ND);
+}
+
+// ---------------------------------------------------------- group kernel ---
+
+template <class Op, class T, int U>
+__global__ __launch_bounds__(kBlock) void group_kernel(GArgs a) {
+  if (Op::EARLY && a.ctl.glob->nrun == 0) return;
+  const int kpl = a.kpl;
+  const int kp = 1 << kpl;
+  const int k = a.k;
+  const int c = threadIdx.x & (kp - 1);
+  bool on = c < k;
+  if (on) {
+    if (Op::PART == PART_RUN)
+      on = IS(a.ctl, I_STATUS, c) == ST_RUNNING;
+    else if (Op::PART == PART_ZEROB)
+      on = IS(a.ctl, I_ZEROB, c) != 0;
+  }
+  constexpr int NI = Op::NIN > 0 ? Op::NIN : 1;
+  constexpr int NO = Op::NOUT > 0 ? Op::NOUT : 1;
+  constexpr int ND = Op::NDOT > 0 ? Op::NDOT : 1;
+  double acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+  if (on) {
+    Coef cf;
+    cf.alpha = SC(a.ctl, S_ALPHA, c);
+    cf.omega = SC(a.ctl, S_OMEGA, c);
+    cf.beta = SC(a.ctl, S_BETA, c);
+    cf.scale = SC(a.ctl, S_SCALE, c);
+    const int rpb = kBlock >> kpl;
+    const long n = a.n;
+    const long stride = (long)gridDim.x * rpb;
+    long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl);
+    for (; row + (U - 1) * stride < n; row += U * stride) {
+      double v[U][NI];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t e = (size_t)(row + u * stride) * k + c;
+#pragma unroll
+        for (int i = 0; i < Op::NIN; ++i)
+          v[u][i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t e = (size_t)(row + u * stride) * k + c;
+        double o[NO];
+        Op::f(v[u], cf, o, acc);
+#pragma unroll
+        for (int j = 0; j < Op::NOUT; ++j) {
+          if ((Op::XOUT >> j) & 1)
+            stv<double>(a.out[j], e, o[j]);
+          else
+            stv<T>(a.out[j], e, o[j]);
+        }
+      }
+    }
+    for (; row < n; row += stride) {
+      const size_t e = (size_t)row * k + c;
+      double v1[NI];
+#pragma unroll
+      for (int i = 0; i < Op::NIN; ++i) v1[i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
+      double o[NO];
+      Op::f(v1, cf, o, acc);
+#pragma unroll
+      for (int j = 0; j < Op::NOUT; ++j) {
+        if ((Op::XOUT >> j) & 1)
+          stv<double>(a.out[j], e, o[j]);
+        else
+          stv<T>(a.out[j], e, o[j]);
+      }
+    }
+  }
+  if constexpr (Op::NDOT > 0) {
+    block_reduce_and_finish<Op::NDOT>(acc, a);
+  } else {
+    if (a.fin != F_NONE) last_block_finish(a, 0);
+  }
+}
+
+template <class Op, class T>
+hipError_t launch_op(const GArgs& a0, int grid_cap, hipStream_t s) {
+  GArgs a = a0;
+  const int rpb = kBlock >> a.kpl;
+  long blocks = (a.n + rpb - 1) / rpb;
+  if (blocks > grid_cap) blocks = grid_cap;
+  if (blocks < 1) blocks = 1;
+  constexpr int U = Op::NIN <= 4 ? 4 : 2;
+  hipLaunchKernelGGL((group_kernel<Op, T, U>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t dispatch_op(int op, const GArgs& a, int grid_cap, hipStream_t s) {
+  switch (op) {
+    case OP_INIT: return launch_op<KInit, T>(a, grid_cap, s);
+    case OP_INIT_P: return launch_op<KInitP, T>(a, grid_cap, s);
+    case OP_ZEROB: return launch_op<KZeroB, T>(a, grid_cap, s);
+    case OP_COPY: return launch_op<KCopy, T>(a, grid_cap, s);
+    case OP_FILL0: return launch_op<KFill0, T>(a, grid_cap, s);
+    case OP_EXIT: return launch_op<KExit, T>(a, grid_cap, s);
+    case OP_DOT: return launch_op<KDot, T>(a, grid_cap, s);
+    case OP_DOTSELF: return launch_op<KDotSelf, T>(a, grid_cap, s);
+    case OP_SUB_ALPHA: return launch_op<KSubAlpha, T>(a, grid_cap, s);
+    case OP_SUB_OMEGA: return launch_op<KSubOmega, T>(a, grid_cap, s);
+    case OP_XUPD: return launch_op<KXUpd, T>(a, grid_cap, s);
+    case OP_PUPD: return launch_op<KPUpd, T>(a, grid_cap, s);
+    case OP_C_PPT: return launch_op<KCPpt, T>(a, grid_cap, s);
+    case OP_C_XR_RHO: return launch_op<KCXrRho, T>(a, grid_cap, s);
+    case OP_C_R_RHO: return launch_op<KCRRho, T>(a, grid_cap, s);
+    case OP_R_G3: return launch_op<KRG3, T>(a, grid_cap, s);
+    case OP_R_XZV: return launch_op<KRXzv, T>(a, grid_cap, s);
+    case OP_P_G1: return launch_op<KPG1, T>(a, grid_cap, s);
+    case OP_P_G2: return launch_op<KPG2, T>(a, grid_cap, s);
+    case OP_P_G3: return launch_op<KPG3, T>(a, grid_cap, s);
+    case OP_PP_G1: return launch_op<KPPG1, T>(a, grid_cap, s);
+    case OP_PP_G2: return launch_op<KPPG2, T>(a, grid_cap, s);
+    case OP_PP_G3: return launch_op<KPPG3, T>(a, grid_cap, s);
+    case OP_PP_G4: return launch_op<KPPG4, T>(a, grid_cap, s);
+    case OP_REF_RESID: return launch_op<KRefResid, T>(a, grid_cap, s);
+    case OP_REF_SCALE: return launch_op<KRefScale, T>(a, grid_cap, s);
+    case OP_REF_UPDATE: return launch_op<KRefUpdate, T>(a, grid_cap, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
+                        const Ctl& ctl, bool fp32, int grid_cap, hipStream_t s) {
+  GArgs a;
+  for (int i = 0; i < 7; ++i) a.in[i] = in[i];
+  for (int i = 0; i < 5; ++i) a.out[i] = out[i];
+  a.n = n;
+  a.k = k;
+  int kp = pad_k(k);
+  int kpl = 0;
+  while ((1 << kpl) < kp) ++kpl;
+  a.kpl = kpl;
+  a.slot = slot;
+  a.fin = fin;
+  a.ctl = ctl;
+  return fp32 ? dispatch_op<float>(op, a, grid_cap, s) : dispatch_op<double>(op, a, grid_cap, s);
+}
+
+// --------------------------------------------------------------- SpMM ---
+
+// Row blocks for the CSR-stream product: contiguous rows whose entries fit in
+// LDS, with about 256 * 2 outputs per block. A row longer than the LDS budget
+// gets a block of its own and is processed in chunks.
+std::vector<int32_t> spmm_partition(const std::vector<int32_t>& row_ptr, int k) {
+  const int n = (int)row_ptr.size() - 1;
+  const int kp = pad_k(k);
+  int rows_target = (kBlock / kp) * 2;
+  if (rows_target > kSpmmRowsMax) rows_target = kSpmmRowsMax;
+  if (rows_target < 1) rows_target = 1;
+  std::vector<int32_t> blk;
+  blk.push_back(0);
+  int r0 = 0;
+  while (r0 < n) {
+    int r = r0 + 1;  // always take at least one row
+    while (r < n && r - r0 < rows_target && row_ptr[r + 1] - row_ptr[r0] <= kSpmmNnzMax) ++r;
+    blk.push_back(r);
+    r0 = r;
+  }
+  return blk;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; remap so each XCD walks a
+// contiguous range of row blocks and the neighbouring X rows a stencil
+// re-reads stay in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  const int per = (nblk + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <class T, int KPL>
+__global__ __launch_bounds__(kBlock) void spmm_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y, int k,
+                                                      const Globals* glob) {
+  if (glob && glob->nrun == 0) return;
+  const int L = xcd_remap(blockIdx.x, A.nblk);
+  if (L >= A.nblk) return;
+  __shared__ int s_col[kSpmmNnzMax];
+  __shared__ T s_val[kSpmmNnzMax];
+  __shared__ int s_rp[kSpmmRowsMax + 1];
+  __shared__ T s_red[kBlock];
+  const int r0 = A.blk[L], r1 = A.blk[L + 1];
+  const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
+  const int ne = e1 - e0;
+  const T* __restrict__ val = static_cast<const T*>(A.val);
+  constexpr int kp = 1 << KPL;
+  const int c = threadIdx.x & (kp - 1);
+  const int rsub = threadIdx.x >> KPL;
+  constexpr int rpp = kBlock >> KPL;
+  if (ne <= kSpmmNnzMax) {
+    for (int i = threadIdx.x; i < ne; i += kBlock) {
+      s_col[i] = A.col[e0 + i];
+      s_val[i] = val[e0 + i];
+    }
+    for (int i = threadIdx.x; i <= r1 - r0; i += kBlock) s_rp[i] = A.row_ptr[r0 + i] - e0;
+    __syncthreads();
+    if (c < k) {
+      for (int r = rsub; r < r1 - r0; r += rpp) {
+        T sum = (T)0;
+        const int eb = s_rp[r], ee = s_rp[r + 1];
+        for (int e = eb; e < ee; ++e) sum += s_val[e] * X[(size_t)s_col[e] * k + c];
+        Y[(size_t)(r0 + r) * k + c] = sum;
+      }
+    }
+  } else {
+    // one long row (r1 == r0 + 1): lanes of the same column split its entries
+    T sum = (T)0;
+    for (int base = 0; base < ne; base += kSpmmNnzMax) {
+      const int m = min(kSpmmNnzMax, ne - base);
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += kBlock) {
+        s_col[i] = A.col[e0 + base + i];
+        s_val[i] = val[e0 + base + i];
+      }
+      __syncthreads();
+      if (c < k)
+        for (int e = rsub; e < m; e += rpp) sum += s_val[e] * X[(size_t)s_col[e] * k + c];
+    }
+    s_red[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x < kp && c < k) {
+      T s = (T)0;
+      for (int g = 0; g < rpp; ++g) s += s_red[g * kp + c];
+      Y[(size_t)r0 * k + c] = s;
+    }
+  }
+}
+
+template <class T>
+hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
+  const int kp = pad_k(k);
+  const unsigned grid = (unsigned)(((A.nblk + 7) / 8) * 8);
+  const T* x = static_cast<const T*>(X);
+  T* y = static_cast<T*>(Y);
+  switch (kp) {
+#define SPMM_CASE(KP, KPL) \
+  case KP: hipLaunchKernelGGL((spmm_kernel<T, KPL>), dim3(grid), dim3(kBlock), 0, s, A, x, y, k, glob); break;
+    SPMM_CASE(1, 0)
+    SPMM_CASE(2, 1)
+    SPMM_CASE(4, 2)
+    SPMM_CASE(8, 3)
+    SPMM_CASE(16, 4)
+    SPMM_CASE(32, 5)
+    SPMM_CASE(64, 6)
+#undef SPMM_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
+                       hipStream_t s) {
+  if (A.nblk <= 0) return hipSuccess;
+  return fp32 ? spmm_dispatch<float>(A, X, Y, k, glob, s) : spmm_dispatch<double>(A, X, Y, k, glob, s);
+}
+
+// ------------------------------------------------------- preconditioner ---
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void prec_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                      const T* __restrict__ diag, long n, int k, int kpl,
+                                                      const Globals* glob) {
+  if (glob && glob->nrun == 0) return;
+  const int kp = 1 << kpl;
+  const int c = threadIdx.x & (kp - 1);
+  if (c >= k) return;
+  const int rpb = kBlock >> kpl;
+  const long stride = (long)gridDim.x * rpb;
+  for (long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl); row < n; row += stride) {
+    const size_t e = (size_t)row * k + c;
+    out[e] = in[e] / diag[row];
+  }
+}
+
+hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k, bool fp32, const Globals* glob,
+                       hipStream_t s) {
+  const int kp = pad_k(k);
+  int kpl = 0;
+  while ((1 << kpl) < kp) ++kpl;
+  const int rpb = kBlock >> kpl;
+  long blocks = (n + rpb - 1) / rpb;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  if (fp32)
+    hipLaunchKernelGGL(prec_kernel<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const float*)in, (float*)out,
+                       (const float*)diag, (long)n, k, kpl, glob);
+  else
+    hipLaunchKernelGGL(prec_kernel<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const double*)in,
+                       (double*)out, (const double*)diag, (long)n, k, kpl, glob);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- set-up ---
+
+__global__ void setup_state_kernel(Ctl C, double tol, int maxit, int hist_cap) {
+  const int c = threadIdx.x;
+  if (c < C.k) {
+    IS(C, I_STATUS, c) = ST_RUNNING;
+    IS(C, I_PEND, c) = -1;
+    IS(C, I_ITERS, c) = 0;
+    IS(C, I_ZEROB, c) = 0;
+  }
+  if (c == 0) {
+    C.glob->nrun = C.k;
+    C.glob->it = 0;
+    C.glob->maxit = maxit;
+    C.glob->hist_cap = hist_cap;
+    C.glob->tol = tol;
+    *C.counter = 0u;
+  }
+}
+
+hipError_t launch_setup_state(const Ctl& ctl, double tol, int maxit, int hist_cap, hipStream_t s) {
+  hipLaunchKernelGGL(setup_state_kernel, dim3(1), dim3(kMaxK), 0, s, ctl, tol, maxit, hist_cap);
+  return hipGetLastError();
+}
+
+__global__ void mark_maxit_kernel(Ctl C) {
+  const int c = threadIdx.x;
+  if (c < C.k && IS(C, I_STATUS, c) == ST_RUNNING) {
+    IS(C, I_STATUS, c) = ST_MAXIT;
+    IS(C, I_ITERS, c) = 0;
+  }
+  __syncthreads();
+  if (c == 0) C.glob->nrun = 0;
+}
+
+hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s) {
+  hipLaunchKernelGGL(mark_maxit_kernel, dim3(1), dim3(kMaxK), 0, s, ctl);
+  return hipGetLastError();
+}
+
+__global__ void extract_diag_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    const double* __restrict__ val, double* diag, float* diag32, int n,
+                                    Globals* glob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+    if (col[e] == i) d += val[e];
+  diag[i] = d;
+  if (diag32) diag32[i] = (float)d;
+  if (d == 0.0) atomicAdd(&glob->zero_diag, 1);
+}
+
+hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,
+                               float* diag32, int n, Globals* glob, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_diag_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, row_ptr, col, val,
+                     diag, diag32, n, glob);
+  return hipGetLastError();
+}
+
+__global__ void convert_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(convert_f32_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, in, out, count);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- adjoint ---
+
+// grad[e] = - sum_c lam[i, c] * x[j, c] for every stored entry e = (i, j).
+// kp lanes per row: lane c reads column c of the contiguous rows lam[i, :] and
+// x[j, :]; the k products are summed by xor shuffles inside each lane group.
+__global__ __launch_bounds__(kBlock) void grad_values_kernel(const int32_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ lam,
+                                                            const double* __restrict__ x, double* __restrict__ grad,
+                                                            long n, int k, int kpl) {
+  const int kp = 1 << kpl;
+  const int c = threadIdx.x & (kp - 1);
+  const int rpb = kBlock >> kpl;
+  const long stride = (long)gridDim.x * rpb;
+  // every lane of a group runs the same trip count (row bounds are per group)
+  for (long i = (long)blockIdx.x * rpb + (threadIdx.x >> kpl); i < n; i += stride) {
+    const double li = c < k ? lam[(size_t)i * k + c] : 0.0;
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int j = col[e];
+      double v = c < k ? li * x[(size_t)j * k + c] : 0.0;
+      for (int off = 1; off < kp; off <<= 1) v += __shfl_xor(v, off, kp);
+      if (c == 0) grad[e] = -v;
+    }
+  }
+}
+
+hipError_t launch_grad_values(const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
+                              double* grad, int n, int k, hipStream_t s) {
+  const int kp = pad_k(k);
+  int kpl = 0;
+  while ((1 << kpl) < kp) ++kpl;
+  const int rpb = kBlock >> kpl;
+  long blocks = (n + rpb - 1) / rpb;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(grad_values_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, lam, x, grad,
+                     (long)n, k, kpl);
+  return hipGetLastError();
+}
+
+// Transposed CSR: count entries per column, exclusive scan, scatter, then
+// sort every row of the transpose by original row index so the result (and
+// every product with it) does not depend on the order of the atomics.
+__global__ void transpose_count_kernel(const int32_t* __restrict__ col, int64_t nnz, int32_t* counts) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&counts[col[e]], 1);
+}
+
+hipError_t launch_transpose_count(const int32_t* col, int64_t nnz, int32_t* counts, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  int64_t blocks = (nnz + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(transpose_count_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, col, nnz, counts);
+  return hipGetLastError();
+}
+
+// Single-workgroup exclusive scan: row_ptr_t[0] = 0, row_ptr_t[i+1] = sum of
+// counts[0..i]. Each thread scans a contiguous chunk; chunk totals are scanned
+// in LDS.
+__global__ __launch_bounds__(1024) void scan_kernel(const int32_t* __restrict__ counts, int32_t* __restrict__ out,
+                                                    int n) {
+  __shared__ int32_t s_tot[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int b = t * chunk, e = min(n, b + chunk);
+  int32_t sum = 0;
+  for (int i = b; i < e; ++i) sum += counts[i];
+  s_tot[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int32_t v = s_tot[i];
+      s_tot[i] = acc;
+      acc += v;
+    }
+    out[0] = 0;
+  }
+  __syncthreads();
+  int32_t acc = s_tot[t];
+  for (int i = b; i < e; ++i) {
+    acc += counts[i];
+    out[i + 1] = acc;
+  }
+}
+
+hipError_t launch_scan(const int32_t* counts, int32_t* row_ptr_t, int n, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, row_ptr_t, n);
+  return hipGetLastError();
+}
+
+__global__ void transpose_fill_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int n,
+                                      const int32_t* __restrict__ row_ptr_t, int32_t* cursor, int32_t* col_t,
+                                      int32_t* perm) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int j = col[e];
+      const int pos = row_ptr_t[j] + atomicAdd(&cursor[j], 1);
+      col_t[pos] = i;
+      perm[pos] = e;
+    }
+  }
+}
+
+hipError_t launch_transpose_fill(const int32_t* row_ptr, const int32_t* col, int n, const int32_t* row_ptr_t,
+                                 int32_t* cursor, int32_t* col_t, int32_t* perm, hipStream_t s) {
+  int blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(transpose_fill_kernel, dim3(blocks), dim3(kBlock), 0, s, row_ptr, col, n, row_ptr_t, cursor,
+                     col_t, perm);
+  return hipGetLastError();
+}
+
+__global__ void transpose_sort_kernel(const int32_t* __restrict__ row_ptr_t, int32_t* col_t, int32_t* perm, int n) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int b = row_ptr_t[j], e = row_ptr_t[j + 1];
+    for (int a = b + 1; a < e; ++a) {  // insertion sort (rows are short)
+      const int key = col_t[a], pv = perm[a];
+      int q = a - 1;
+      while (q >= b && col_t[q] > key) {
+        col_t[q + 1] = col_t[q];
+        perm[q + 1] = perm[q];
+        --q;
+      }
+      col_t[q + 1] = key;
+      perm[q + 1] = pv;
+    }
+  }
+}
+
+hipError_t launch_transpose_sort_rows(const int32_t* row_ptr_t, int32_t* col_t, int32_t* perm, int n, hipStream_t s) {
+  int blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(transpose_sort_kernel, dim3(blocks), dim3(kBlock), 0, s, row_ptr_t, col_t, perm, n);
+  return hipGetLastError();
+}
+
+__global__ void gather_values_kernel(const double* __restrict__ val, const int32_t* __restrict__ perm,
+                                     double* __restrict__ val_t, int64_t nnz) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+    val_t[p] = val[perm[p]];
+}
+
+hipError_t launch_gather_values(const double* val, const int32_t* perm, double* val_t, int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  int64_t blocks = (nnz + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(gather_values_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, val, perm, val_t, nnz);
+  return hipGetLastError();
+}
+
+}  // namespace bcg

@@ -1,0 +1,319 @@
+// Launch plans: the sequence of kernels that makes up the start and one
+// iteration of every method, in basic and merged form.
+//
+// Merged plans give one streaming pass per line of the paper's merged
+// listings (Appendix B: Alg. 2 and 5 classical, Alg. 6 Reordered, Alg. 4 and 7
+// Pipelined). Basic plans give one pass per statement: a three-vector update
+// is one pass, a four-vector update w = y - omega (t - alpha v) is two, and a
+// dot product is its own pass reading each distinct vector once (the counting
+// rule of Table 2 and its footnotes). Sparse products and preconditioner
+// applications are separate launches in both forms (Section 2.3 counts them
+// apart from Table 2).
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace bcg {
+
+namespace {
+
+const OpInfo kOps[OP_NUM] = {
+    {2, 2, 2, "init"},        // OP_INIT
+    {2, 3, 2, "init_p"},      // OP_INIT_P
+    {0, 1, 0, "zerob"},       // OP_ZEROB
+    {1, 1, 0, "copy"},        // OP_COPY
+    {0, 1, 0, "fill0"},       // OP_FILL0
+    {3, 0, 2, "exit"},        // OP_EXIT
+    {2, 0, 1, "dot"},         // OP_DOT
+    {1, 0, 1, "dotself"},     // OP_DOTSELF
+    {2, 1, 0, "sub_alpha"},   // OP_SUB_ALPHA
+    {2, 1, 0, "sub_omega"},   // OP_SUB_OMEGA
+    {3, 1, 0, "xupd"},        // OP_XUPD
+    {3, 1, 0, "pupd"},        // OP_PUPD
+    {2, 0, 3, "c_ppt"},       // OP_C_PPT
+    {5, 2, 1, "c_xr_rho"},    // OP_C_XR_RHO
+    {3, 1, 1, "c_r_rho"},     // OP_C_R_RHO
+    {4, 1, 4, "r_g3"},        // OP_R_G3
+    {5, 3, 0, "r_xzv"},       // OP_R_XZV
+    {7, 5, 3, "p_g1"},        // OP_P_G1
+    {4, 2, 0, "p_g2"},        // OP_P_G2
+    {7, 1, 4, "p_g3"},        // OP_P_G3
+    {5, 3, 0, "pp_g1"},       // OP_PP_G1
+    {6, 4, 3, "pp_g2"},       // OP_PP_G2
+    {5, 2, 0, "pp_g3"},       // OP_PP_G3
+    {7, 2, 4, "pp_g4"},       // OP_PP_G4
+    {2, 1, 2, "ref_resid"},   // OP_REF_RESID
+    {1, 2, 0, "ref_scale"},   // OP_REF_SCALE
+    {2, 1, 0, "ref_update"},  // OP_REF_UPDATE
+};
+
+Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
+  Step s;
+  std::memset(&s, 0, sizeof(s));
+  s.kind = K_GROUP;
+  s.op = op;
+  for (int i = 0; i < 6; ++i) s.in[i] = V_NONE;
+  for (int i = 0; i < 4; ++i) s.out[i] = V_NONE;
+  int i = 0;
+  for (int v : in) s.in[i++] = v;
+  int o = 0;
+  for (int v : out) s.out[o++] = v;
+  s.nin = i;
+  s.nout = o;
+  s.slot = slot;
+  s.fin = fin;
+  return s;
+}
+
+Step SPMM(int in, int out) {
+  Step s = G(OP_COPY, {in}, {out});
+  s.kind = K_SPMM;
+  s.op = -1;
+  return s;
+}
+
+Step PREC(int in, int out) {
+  Step s = G(OP_COPY, {in}, {out});
+  s.kind = K_PREC;
+  s.op = -1;
+  return s;
+}
+
+// ------------------------------------------------------------- classical ---
+void classical(int formulation, int precond, Plan* P) {
+  const bool jac = precond == 1;
+  const int ph = jac ? V_PH : V_P;  // p-hat (= p without preconditioner)
+  const int sh = jac ? V_SH : V_S;  // s-hat
+  P->init = {SPMM(V_X, V_V), G(OP_INIT_P, {V_B, V_V}, {V_R, V_R0, V_P}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
+  auto& it = P->iter;
+  if (jac) it.push_back(PREC(V_P, V_PH));
+  it.push_back(SPMM(ph, V_V));
+  it.push_back(G(OP_DOT, {V_V, V_R0}, {}, 0, F_ALPHA));           // delta = (v, r0)
+  it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_S}));                // s = r - alpha v
+  if (jac) it.push_back(PREC(V_S, V_SH));
+  it.push_back(SPMM(sh, V_T));
+  if (formulation == 0) {
+    // Alg. 2 / Alg. 5 merged lines
+    it.push_back(G(OP_C_PPT, {V_T, V_S}, {}, 0, F_OMEGA_MERGED));  // phi, psi, theta
+    if (!jac) {
+      it.push_back(G(OP_C_XR_RHO, {V_X, V_P, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
+    } else {
+      // Alg. 5 keeps x += alpha ph + omega sh apart from {r, rho}; it does not
+      // depend on beta, so it runs first and the rho pass closes the iteration.
+      it.push_back(G(OP_XUPD, {V_X, V_PH, V_SH}, {V_X}));
+      it.push_back(G(OP_C_R_RHO, {V_S, V_T, V_R0}, {V_R}, 3, F_BETA_END));
+    }
+  } else {
+    // Alg. 1 one statement per pass; explicit (r, r) stop test
+    it.push_back(G(OP_DOT, {V_T, V_S}, {}, 0, F_NONE));             // phi
+    it.push_back(G(OP_DOTSELF, {V_T}, {}, 1, F_OMEGA_BASIC));      // psi -> omega
+    it.push_back(G(OP_XUPD, {V_X, ph, sh}, {V_X}));
+    it.push_back(G(OP_SUB_OMEGA, {V_S, V_T}, {V_R}));               // r = s - omega t
+    it.push_back(G(OP_DOTSELF, {V_R}, {}, 2, F_CONV_BASIC));       // (r, r)
+    it.push_back(G(OP_DOT, {V_R, V_R0}, {}, 3, F_BETA_END));        // rho'
+  }
+  it.push_back(G(OP_PUPD, {V_R, V_P, V_V}, {V_P}));                 // p = r + beta (p - omega v)
+  P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T};
+  if (jac) {
+    P->vecs.push_back(V_PH);
+    P->vecs.push_back(V_SH);
+  }
+}
+
+// ------------------------------------------------------------- reordered ---
+void reordered(int formulation, int precond, Plan* P) {
+  const bool jac = precond == 1;
+  P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
+  if (jac)
+    P->init.push_back(PREC(V_R, V_Z));
+  else
+    P->init.push_back(G(OP_COPY, {V_R}, {V_Z}));
+  P->init.push_back(G(OP_COPY, {V_Z}, {V_VH}));  // v-hat_0 = z_0
+  auto& it = P->iter;
+  it.push_back(SPMM(V_VH, V_V));
+  it.push_back(G(OP_DOT, {V_V, V_R0}, {}, 0, F_ALPHA));  // delta
+  if (jac) it.push_back(PREC(V_V, V_S));                 // s = M^{-1} v (alias of v when M = I)
+  it.push_back(G(OP_SUB_ALPHA, {V_Z, V_S}, {V_TH}));     // t-hat = z - alpha s
+  it.push_back(SPMM(V_TH, V_T));
+  if (formulation == 0) {
+    it.push_back(G(OP_R_G3, {V_R, V_V, V_T, V_R0}, {V_RT}, 0, F_RE_OMEGA));
+    if (jac) it.push_back(PREC(V_T, V_Q));
+    it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));   // r = rt - omega t
+    it.push_back(G(OP_R_XZV, {V_X, V_VH, V_TH, V_Q, V_S}, {V_X, V_Z, V_VH}, 0, F_END));
+  } else {
+    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));   // rt = r - alpha v
+    it.push_back(G(OP_DOT, {V_T, V_RT}, {}, 0));         // theta
+    it.push_back(G(OP_DOTSELF, {V_T}, {}, 1));           // phi
+    it.push_back(G(OP_DOT, {V_T, V_R0}, {}, 2));         // psi
+    it.push_back(G(OP_DOTSELF, {V_RT}, {}, 3, F_RE_OMEGA));  // eta
+    if (jac) it.push_back(PREC(V_T, V_Q));
+    it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));
+    it.push_back(G(OP_XUPD, {V_X, V_VH, V_TH}, {V_X}));
+    it.push_back(G(OP_SUB_OMEGA, {V_TH, V_Q}, {V_Z}));   // z = th - omega q
+    Step s = G(OP_PUPD, {V_Z, V_VH, V_S}, {V_VH}, 0, F_END);  // vh = z + beta (vh - omega s)
+    it.push_back(s);
+  }
+  P->vecs = {V_R, V_R0, V_V, V_T, V_Z, V_TH, V_RT, V_VH};
+  if (jac) {
+    P->vecs.push_back(V_S);
+    P->vecs.push_back(V_Q);
+  } else {
+    P->alias_from[V_S] = V_V;
+    P->alias_from[V_Q] = V_T;
+  }
+}
+
+// ------------------------------------------------------------- pipelined ---
+void pipelined(int formulation, int precond, Plan* P) {
+  const bool jac = precond == 1;
+  auto& in = P->init;
+  in = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
+  if (!jac) {
+    in.push_back(SPMM(V_R, V_W));
+    in.push_back(SPMM(V_W, V_T));
+  } else {
+    in.push_back(PREC(V_R, V_RH));
+    in.push_back(SPMM(V_RH, V_W));
+    in.push_back(PREC(V_W, V_WH));
+    in.push_back(SPMM(V_WH, V_T));
+  }
+  in.push_back(G(OP_DOT, {V_R, V_W}, {}, 0, F_PIPE_INIT));
+  // previous-iteration vectors start at zero (beta_{-1} = 0)
+  for (int v : {V_S, V_Z, V_V}) in.push_back(G(OP_FILL0, {}, {v}));
+  if (!jac)
+    in.push_back(G(OP_FILL0, {}, {V_P}));
+  else
+    for (int v : {V_PH, V_SH, V_ZH}) in.push_back(G(OP_FILL0, {}, {v}));
+
+  auto& it = P->iter;
+  if (!jac) {
+    if (formulation == 0) {
+      it.push_back(G(OP_P_G1, {V_R, V_P, V_S, V_W, V_Z, V_T, V_V}, {V_P, V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
+      it.push_back(SPMM(V_Z, V_V));
+      it.push_back(G(OP_P_G2, {V_X, V_P, V_Q, V_Y}, {V_X, V_R}));
+      it.push_back(G(OP_P_G3, {V_Y, V_T, V_V, V_R0, V_R, V_Z, V_S}, {V_W}, 3, F_PIPE_BETA_END));
+      it.push_back(SPMM(V_W, V_T));
+    } else {
+      it.push_back(G(OP_PUPD, {V_R, V_P, V_S}, {V_P}));     // p = r + beta (p - omega s)
+      it.push_back(G(OP_PUPD, {V_W, V_S, V_Z}, {V_S}));     // s = w + beta (s - omega z)
+      it.push_back(G(OP_PUPD, {V_T, V_Z, V_V}, {V_Z}));     // z = t + beta (z - omega v)
+      it.push_back(G(OP_SUB_ALPHA, {V_R, V_S}, {V_Q}));     // q = r - alpha s
+      it.push_back(G(OP_SUB_ALPHA, {V_W, V_Z}, {V_Y}));     // y = w - alpha z
+      it.push_back(G(OP_DOT, {V_Q, V_Y}, {}, 0));           // theta
+      it.push_back(G(OP_DOTSELF, {V_Y}, {}, 1));            // phi
+      it.push_back(G(OP_DOTSELF, {V_Q}, {}, 2, F_PIPE_OMEGA));  // pi
+      it.push_back(SPMM(V_Z, V_V));
+      it.push_back(G(OP_XUPD, {V_X, V_P, V_Q}, {V_X}));
+      it.push_back(G(OP_SUB_OMEGA, {V_Q, V_Y}, {V_R}));     // r = q - omega y
+      it.push_back(G(OP_SUB_ALPHA, {V_T, V_V}, {V_W}));     // w = t - alpha v
+      it.push_back(G(OP_SUB_OMEGA, {V_Y, V_W}, {V_W}));     // w = y - omega w
+      it.push_back(G(OP_DOT, {V_R0, V_R}, {}, 3));          // rho'
+      it.push_back(G(OP_DOT, {V_R0, V_Z}, {}, 4));          // psi
+      it.push_back(G(OP_DOT, {V_R0, V_W}, {}, 5));          // sigma
+      it.push_back(G(OP_DOT, {V_R0, V_S}, {}, 6, F_PIPE_BETA_END));  // delta
+      it.push_back(SPMM(V_W, V_T));
+    }
+    P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T, V_Z, V_Q, V_W, V_Y};
+  } else {
+    if (formulation == 0) {
+      it.push_back(G(OP_PP_G1, {V_RH, V_PH, V_SH, V_WH, V_ZH}, {V_PH, V_SH, V_QH}));
+      it.push_back(G(OP_PP_G2, {V_W, V_S, V_Z, V_T, V_V, V_R}, {V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
+      it.push_back(PREC(V_Z, V_ZH));
+      it.push_back(SPMM(V_ZH, V_V));
+      it.push_back(G(OP_PP_G3, {V_X, V_PH, V_QH, V_WH, V_ZH}, {V_X, V_RH}));
+      it.push_back(G(OP_PP_G4, {V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_R, V_W}, 3, F_PIPE_BETA_END));
+      it.push_back(PREC(V_W, V_WH));
+      it.push_back(SPMM(V_WH, V_T));
+    } else {
+      it.push_back(G(OP_PUPD, {V_RH, V_PH, V_SH}, {V_PH}));  // ph = rh + beta (ph - omega sh)
+      it.push_back(G(OP_PUPD, {V_WH, V_SH, V_ZH}, {V_SH}));  // sh = wh + beta (sh - omega zh)
+      it.push_back(G(OP_SUB_ALPHA, {V_RH, V_SH}, {V_QH}));   // qh = rh - alpha sh
+      it.push_back(G(OP_PUPD, {V_W, V_S, V_Z}, {V_S}));
+      it.push_back(G(OP_PUPD, {V_T, V_Z, V_V}, {V_Z}));
+      it.push_back(G(OP_SUB_ALPHA, {V_R, V_S}, {V_Q}));
+      it.push_back(G(OP_SUB_ALPHA, {V_W, V_Z}, {V_Y}));
+      it.push_back(G(OP_DOT, {V_Q, V_Y}, {}, 0));
+      it.push_back(G(OP_DOTSELF, {V_Y}, {}, 1));
+      it.push_back(G(OP_DOTSELF, {V_Q}, {}, 2, F_PIPE_OMEGA));
+      it.push_back(PREC(V_Z, V_ZH));
+      it.push_back(SPMM(V_ZH, V_V));
+      it.push_back(G(OP_XUPD, {V_X, V_PH, V_QH}, {V_X}));
+      it.push_back(G(OP_SUB_ALPHA, {V_WH, V_ZH}, {V_RH}));   // rh = wh - alpha zh
+      it.push_back(G(OP_SUB_OMEGA, {V_QH, V_RH}, {V_RH}));   // rh = qh - omega rh
+      it.push_back(G(OP_SUB_OMEGA, {V_Q, V_Y}, {V_R}));
+      it.push_back(G(OP_SUB_ALPHA, {V_T, V_V}, {V_W}));
+      it.push_back(G(OP_SUB_OMEGA, {V_Y, V_W}, {V_W}));
+      it.push_back(G(OP_DOT, {V_R0, V_R}, {}, 3));
+      it.push_back(G(OP_DOT, {V_R0, V_Z}, {}, 4));
+      it.push_back(G(OP_DOT, {V_R0, V_W}, {}, 5));
+      it.push_back(G(OP_DOT, {V_R0, V_S}, {}, 6, F_PIPE_BETA_END));
+      it.push_back(PREC(V_W, V_WH));
+      it.push_back(SPMM(V_WH, V_T));
+    }
+    P->vecs = {V_R, V_R0, V_V, V_S, V_T, V_Z, V_Q, V_W, V_Y, V_PH, V_SH, V_QH, V_RH, V_WH, V_ZH};
+  }
+}
+
+}  // namespace
+
+const OpInfo& op_info(int op) { return kOps[op]; }
+
+bool build_plan(int variant, int formulation, int precond, Plan* P, std::string* err) {
+  P->init.clear();
+  P->iter.clear();
+  P->vecs.clear();
+  for (int v = 0; v < V_NUM; ++v) P->alias_from[v] = -1;
+  if (precond != 0 && precond != 1) {
+    *err = "unknown preconditioner";
+    return false;
+  }
+  if (formulation != 0 && formulation != 1) {
+    *err = "unknown or unsupported formulation";
+    return false;
+  }
+  switch (variant) {
+    case 0: classical(formulation, precond, P); break;
+    case 1: reordered(formulation, precond, P); break;
+    case 2: pipelined(formulation, precond, P); break;
+    default: *err = "unknown variant"; return false;
+  }
+  // Every operand must be a vector the plan allocates (or x, b, or an alias),
+  // and every vector pass must get exactly the operands its kernel reads and
+  // writes: a plan error is caught here, on the host, never on the device.
+  bool have[V_NUM] = {};
+  have[V_X] = have[V_B] = true;
+  for (int v : P->vecs) have[v] = true;
+  for (int v = 0; v < V_NUM; ++v)
+    if (P->alias_from[v] >= 0) have[v] = have[P->alias_from[v]];
+  for (const auto* list : {&P->init, &P->iter}) {
+    for (const Step& s : *list) {
+      if (s.kind == K_GROUP) {
+        const OpInfo& oi = op_info(s.op);
+        if (s.nin != oi.nin || s.nout != oi.nout) {
+          *err = std::string("plan step ") + oi.name + ": operand count mismatch";
+          return false;
+        }
+        if (oi.ndot > 0 && s.slot + oi.ndot > 7) {
+          *err = std::string("plan step ") + oi.name + ": dot slots out of range";
+          return false;
+        }
+      } else if (s.nin != 1 || s.nout != 1) {
+        *err = "plan step: product/preconditioner needs one input and one output";
+        return false;
+      }
+      for (int i = 0; i < s.nin; ++i)
+        if (s.in[i] < 0 || s.in[i] >= V_NUM || !have[s.in[i]]) {
+          *err = "plan step reads a vector the plan does not allocate";
+          return false;
+        }
+      for (int i = 0; i < s.nout; ++i)
+        if (s.out[i] < 0 || s.out[i] >= V_NUM || !have[s.out[i]] || s.out[i] == V_B) {
+          *err = "plan step writes a vector the plan does not allocate";
+          return false;
+        }
+    }
+  }
+  return true;
+}
+
+}  // namespace bcg

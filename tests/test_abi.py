@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every function the header declares, and its launch plans move exactly the
+vector traffic of Table 2."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
+
+
+def header_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(bicgstab_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1907_12874_amd import _lib
+
+    return _lib.lib()
+
+
+def test_header_declares_functions():
+    names = header_functions()
+    assert "bicgstab_create" in names and "bicgstab_solve" in names and len(names) >= 15
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in header_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header(L):
+    from paper_1907_12874_amd import _lib
+
+    assert set(_lib.exported_symbols()) <= set(header_functions())
+
+
+# Table 2 names -> (variant, preconditioner) of this library
+TABLE2 = {
+    "BiCGStab": ("classical", "none"),
+    "PipeBiCGStab": ("pipelined", "none"),
+    "PBiCGStab": ("classical", "jacobi"),
+    "RBiCGStab": ("reordered", "jacobi"),
+    "PPipeBiCGStab": ("pipelined", "jacobi"),
+}
+
+
+@pytest.mark.parametrize("method", sorted(TABLE2))
+def test_launch_plans_match_table2(L, method):
+    from paper_1907_12874_amd import plan_traffic
+
+    g = json.load(open(GOLDEN))["table2_vector_traffic"]["rows"][method]
+    variant, precond = TABLE2[method]
+    basic = plan_traffic(variant, "basic", precond)
+    merged = plan_traffic(variant, "merged", precond)
+    assert (basic["reads"], basic["writes"]) == (g[0], g[1])
+    assert (merged["reads"], merged["writes"]) == (g[2], g[3])
+    for p in (basic, merged):
+        assert p["spmms"] == 2
+        assert p["precond_apps"] == (2 if precond == "jacobi" else 0)
+
+
+def test_reordered_without_preconditioner_aliases(L):
+    """With M = I the Reordered plan needs no copies: s and q alias v and t."""
+    from paper_1907_12874_amd import plan_traffic
+
+    for f in ("basic", "merged"):
+        a = plan_traffic("reordered", f, "none")
+        b = plan_traffic("reordered", f, "jacobi")
+        assert (a["reads"], a["writes"]) == (b["reads"], b["writes"])
+        assert a["precond_apps"] == 0
+
+
+def test_merging_reduces_launches(L):
+    from paper_1907_12874_amd import plan_traffic
+
+    for v in ("classical", "reordered", "pipelined"):
+        for p in ("none", "jacobi"):
+            assert plan_traffic(v, "merged", p)["launches"] < plan_traffic(v, "basic", p)["launches"]
+
+
+def test_invalid_arguments_are_errors(L):
+    from paper_1907_12874_amd import _lib
+
+    r = ctypes.c_int32()
+    assert L.bicgstab_plan_traffic(7, 0, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
+    assert L.bicgstab_plan_traffic(0, 5, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
+    assert L.bicgstab_plan_traffic(0, 0, 9, *[ctypes.byref(r)] * 5) == _lib.EINVAL
+    desc = _lib.CSRDesc(4, 0, None, None, None)
+    h = ctypes.c_void_p()
+    # k out of range, size mismatch: rejected before any device work
+    assert L.bicgstab_create(ctypes.byref(desc), 4, 0, 0, 0, 0, 0, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.bicgstab_create(ctypes.byref(desc), 4, 65, 0, 0, 0, 0, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.bicgstab_create(ctypes.byref(desc), 5, 1, 0, 0, 0, 0, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.bicgstab_create(ctypes.byref(desc), 4, 1, 0, 0, 0, 0, None, ctypes.byref(h)) == _lib.EINVAL  # null arrays
+    assert b"null" in L.bicgstab_last_error()
+    assert L.bicgstab_strerror(_lib.EINVAL) == b"invalid argument"

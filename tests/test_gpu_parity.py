@@ -1,0 +1,310 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Tolerances. The library evaluates every vector update and sparse product in
+the same order as the oracle with no fused multiply-add, and divides by a_ii
+for Jacobi, so those steps round identically; only the dot products sum in a
+different order (a fixed tree on the GPU, BLAS on the CPU). Hence:
+  * sparse products: bitwise equal to SciPy's CSR product;
+  * fixed-iteration trajectories: scalars and iterates agree to 1e-10
+    relative over 20 passes (the dot-product rounding, amplified);
+  * converged solves: x within 1e-8 relative of the oracle's x per column
+    (the spec FP64 bound), iteration counts within +-2, true relative
+    residual <= 1.1 tol.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from workloads import conv_diff, config_problem, manufactured_rhs, random_sparse, CSR
+
+pytestmark = pytest.mark.gpu
+
+METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_solver(lib, A: CSR, k, variant="classical", formulation="merged", precond="none", precision="fp64"):
+    return lib.Solver.from_csr(A, k, variant=variant, formulation=formulation, precond=precond, precision=precision)
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------ SpMM ---
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 13, 16, 32, 64])
+def test_spmm_bitwise(lib, k):
+    import torch
+
+    say(f"spmm k={k}")
+    A = random_sparse(3001, 9, seed=k)
+    S = A.to_scipy()
+    rng = np.random.default_rng(100 + k)
+    X = rng.uniform(-1, 1, (A.n, k))
+    s = gpu_solver(lib, A, k)
+    Y = to_np(s.spmm(torch.from_numpy(X).cuda()))
+    torch.cuda.synchronize()
+    assert np.array_equal(Y, S @ X)
+
+
+def test_spmm_long_rows_and_empty_rows(lib):
+    """Rows longer than the LDS budget take the split path (different
+    summation order: a few ulp); empty rows give zeros."""
+    import torch
+
+    say("spmm long rows")
+    n = 5000
+    rng = np.random.default_rng(7)
+    rows = []
+    for i in range(n):
+        if i in (3, 4000):
+            cols = np.sort(rng.choice(n, 4500, replace=False))
+        elif i % 97 == 0:
+            cols = np.array([], dtype=np.int64)
+        else:
+            cols = np.sort(rng.choice(n, 5, replace=False))
+        rows.append(cols)
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(c) for c in rows])
+    A = CSR(n, rp.astype(np.int32), np.concatenate(rows).astype(np.int32), rng.uniform(-1, 1, int(rp[-1])))
+    S = A.to_scipy()
+    for k in (1, 6, 32):
+        X = rng.uniform(-1, 1, (n, k))
+        s = gpu_solver(lib, A, k)
+        Y = to_np(s.spmm(torch.from_numpy(X).cuda()))
+        R = S @ X
+        scale = (abs(S) @ abs(X)) + 1e-300
+        assert np.all(np.abs(Y - R) <= 64 * np.finfo(float).eps * scale)
+        short = np.array([len(c) <= 2048 for c in rows])
+        assert np.array_equal(Y[short], R[short])
+
+
+# --------------------------------------------------------- trajectories ---
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+@pytest.mark.parametrize("k", [1, 5])
+def test_trajectory_fixed_iterations(lib, variant, formulation, precond, k):
+    """20 passes with the stop test off: per-pass alpha, omega, rho and the
+    final iterate match the oracle."""
+    import torch
+
+    say(f"trajectory {variant}/{formulation}/{precond} k={k}")
+    A = conv_diff(17, 3, (1.0, 0.7, 0.3))
+    b, _ = manufactured_rhs(A, k, seed=21)
+    nit = 20
+    s = gpu_solver(lib, A, k, variant, formulation, precond)
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=0.0, maxit=nit)
+    hist = s.history()
+    ref = oracle.solve(A.to_scipy(), b, variant=variant, formulation=formulation, precond=precond, tol=0.0,
+                       maxit=nit, trace=True)
+    assert np.all(info.status == oracle.MAXIT) and np.all(info.iters == nit)
+    X = to_np(x)
+    for c in range(k):
+        err = np.linalg.norm(X[:, c] - ref.x[:, c]) / np.linalg.norm(ref.x[:, c])
+        assert err < 1e-10, (c, err)
+        tr = ref.traces[c]
+        for j in range(nit):
+            for idx, key in ((0, "alpha"), (1, "omega"), (2, "rho")):
+                g, o = hist[j, c, idx], tr[j][key]
+                assert abs(g - o) <= 1e-10 * abs(o), (c, j, key, g, o)
+
+
+# --------------------------------------------------------------- solves ---
+
+def _check_solve(lib, A, b, variant, formulation, precond, tol, maxit=3000, x0=None, it_tol=2):
+    import torch
+
+    s = gpu_solver(lib, A, b.shape[1], variant, formulation, precond)
+    x, info = s.solve(torch.from_numpy(b).cuda(), None if x0 is None else torch.from_numpy(x0).cuda(), tol=tol,
+                      maxit=maxit)
+    ref = oracle.solve(A.to_scipy(), b, x0, variant=variant, formulation=formulation, precond=precond, tol=tol,
+                       maxit=maxit)
+    X = to_np(x)
+    assert np.all(info.status == oracle.CONVERGED), info.status
+    assert np.all(np.abs(info.iters - ref.iters) <= it_tol), (info.iters, ref.iters)
+    assert np.all(info.relres_true <= 1.1 * tol), info.relres_true
+    err = np.linalg.norm(X - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+    assert np.all(err <= 1e-8), err
+    # the library's own true residual agrees with one recomputed on the host
+    rt = np.linalg.norm(b - A.to_scipy() @ X, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.allclose(info.relres_true, rt, rtol=1e-6, atol=1e-16)
+    return info, ref
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_solve_small_2d(lib, variant, formulation, precond):
+    """The 2D 5-point convection-diffusion recipe at 64 x 64, one RHS,
+    tol 1e-10."""
+    say(f"solve 2d {variant}/{formulation}/{precond}")
+    cfg = config_problem(0, seed=0)
+    _check_solve(lib, cfg["A"], cfg["b"], variant, formulation, precond, cfg["tol"])
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+@pytest.mark.parametrize("k", [3, 8])
+def test_solve_3d_multi_rhs(lib, variant, formulation, precond, k):
+    """The 3D 7-point recipe at 21^3 (several row blocks and a ragged tail),
+    Jacobi or not, tol 1e-8."""
+    say(f"solve 3d {variant}/{formulation}/{precond} k={k}")
+    cfg = config_problem(1, seed=1, k=k, scale=21)
+    _check_solve(lib, cfg["A"], cfg["b"], variant, formulation, precond, cfg["tol"])
+
+
+def test_solve_random_sparse(lib):
+    say("solve random sparse")
+    A = random_sparse(20000, 15, seed=4)
+    b, _ = manufactured_rhs(A, 4, seed=5)
+    for m in METHODS:
+        _check_solve(lib, A, b, *m, tol=1e-10)
+
+
+def test_solve_k32_and_k64(lib):
+    say("solve k=32, k=64")
+    A = conv_diff(12, 3, (1.0, 0.7, 0.3))
+    for k in (32, 64):
+        b, _ = manufactured_rhs(A, k, seed=k)
+        _check_solve(lib, A, b, "classical", "merged", "jacobi", 1e-9)
+        _check_solve(lib, A, b, "pipelined", "merged", "none", 1e-9)
+
+
+# ---------------------------------------------------------------- edges ---
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_edge_columns(lib, variant, formulation, precond):
+    """Zero column, NaN column, maxit = 1, exact initial guess, identical
+    columns: same statuses and counts as the oracle."""
+    import torch
+
+    say(f"edges {variant}/{formulation}/{precond}")
+    A = conv_diff(6, 2, (1.0, 0.5))
+    S = A.to_scipy()
+    n = A.n
+    rng = np.random.default_rng(15)
+    xs = rng.uniform(-1, 1, n)
+    B = np.stack([np.zeros(n), S @ xs, S @ xs, S @ xs, S @ xs], axis=1)
+    B[3, 1] = np.nan
+    X0 = np.zeros_like(B)
+    X0[:, 3] = xs
+    X0[:, 0] = 1.0
+    s = gpu_solver(lib, A, 5, variant, formulation, precond)
+    x, info = s.solve(torch.from_numpy(B).cuda(), torch.from_numpy(X0).cuda(), tol=1e-10, maxit=1)
+    ref = oracle.solve(S, B, X0, variant, formulation, precond, 1e-10, 1)
+    assert list(info.status) == list(ref.status)
+    assert list(info.iters) == list(ref.iters)
+    X = to_np(x)
+    assert np.all(X[:, 0] == 0) and np.array_equal(X[:, 3], xs)
+    assert np.array_equal(X[:, 2], X[:, 4])  # identical columns, identical results
+
+
+def test_breakdown_and_scaled_identity(lib):
+    import torch
+
+    say("breakdown / cI")
+    skew = CSR(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, -1.0]))
+    b = np.array([[1.0], [2.0]])
+    for v, f, p in METHODS:
+        if p == "jacobi":
+            continue
+        s = gpu_solver(lib, skew, 1, v, f, p)
+        x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=10)
+        assert info.status[0] == oracle.BREAKDOWN
+        assert info.iters[0] == (0 if v == "pipelined" else 1)
+    n = 33
+    for c in (2.0, 3.0):
+        A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, c))
+        b = np.random.default_rng(3).uniform(-1, 1, (n, 2))
+        for v, f, p in METHODS:
+            s = gpu_solver(lib, A, 2, v, f, p)
+            x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-12, maxit=10)
+            assert np.all(info.status == 0) and np.all(info.iters == 1)
+            assert np.allclose(to_np(x), b / c, rtol=1e-15, atol=0)
+
+
+def test_jacobi_zero_diagonal_is_error(lib):
+    import torch
+
+    say("jacobi zero diagonal")
+    skew = CSR(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, -1.0]))
+    s = gpu_solver(lib, skew, 1, "classical", "merged", "jacobi")
+    with pytest.raises(lib.BicgstabError):
+        s.solve(torch.ones(2, 1, dtype=torch.float64).cuda())
+
+
+def test_empty_system(lib):
+    import torch
+
+    say("n = 0")
+    A = CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    s = gpu_solver(lib, A, 3)
+    x, info = s.solve(torch.zeros(0, 3, dtype=torch.float64).cuda(), tol=1e-8, maxit=10)
+    assert x.shape == (0, 3) and np.all(info.status == 0) and np.all(info.iters == 0)
+
+
+def test_bad_column_index_rejected(lib):
+    say("bad column index")
+    A = CSR(3, np.array([0, 1, 2, 3], np.int32), np.array([0, 5, 2], np.int32), np.ones(3))
+    with pytest.raises(lib.BicgstabError):
+        gpu_solver(lib, A, 1)
+
+
+def test_deterministic_and_graph_equals_direct(lib, monkeypatch):
+    import torch
+
+    say("determinism")
+    cfg = config_problem(1, seed=3, k=4, scale=16)
+    b = torch.from_numpy(cfg["b"]).cuda()
+    s = gpu_solver(lib, cfg["A"], 4, "pipelined", "merged", "jacobi")
+    x1, i1 = s.solve(b, tol=1e-8, maxit=500)
+    x2, i2 = s.solve(b, tol=1e-8, maxit=500)
+    assert torch.equal(x1, x2) and np.array_equal(i1.iters, i2.iters)
+    monkeypatch.setenv("BICGSTAB_GRAPH", "0")
+    monkeypatch.setenv("BICGSTAB_CHUNK", "3")
+    s2 = gpu_solver(lib, cfg["A"], 4, "pipelined", "merged", "jacobi")
+    x3, i3 = s2.solve(b, tol=1e-8, maxit=500)
+    assert torch.equal(x1, x3) and np.array_equal(i1.iters, i3.iters)
+
+
+# ---------------------------------------------------- full-size checks ---
+
+def test_full_size_cfg1_sampled(lib):
+    """The 128^3 7-point Jacobi workload at k = 32 (the benchmark's launch
+    configuration): SpMM rows sampled against the oracle's product, three
+    passes of every merged method against the oracle on columns 0 and 31, and
+    a converged classical solve checked by its recomputed residual and the
+    manufactured solution."""
+    import torch
+
+    say("full size 128^3 k=32")
+    cfg = config_problem(1, seed=0, k=32)
+    A, b, xs = cfg["A"], cfg["b"], cfg["x_star"]
+    S = A.to_scipy()
+    bt = torch.from_numpy(b).cuda()
+    s = gpu_solver(lib, A, 32, "classical", "merged", "jacobi")
+    Y = to_np(s.spmm(bt))
+    rows = np.random.default_rng(0).choice(A.n, 2000, replace=False)
+    assert np.array_equal(Y[rows], S[rows] @ b)
+    for v in ("classical", "reordered", "pipelined"):
+        say(f"  3 passes {v}")
+        s3 = gpu_solver(lib, A, 32, v, "merged", "jacobi")
+        x, info = s3.solve(bt, tol=0.0, maxit=3)
+        X = to_np(x)
+        ref = oracle.solve(S, b, variant=v, formulation="merged", precond="jacobi", tol=0.0, maxit=3, columns=[0, 31])
+        for c in (0, 31):
+            assert np.linalg.norm(X[:, c] - ref.x[:, c]) / np.linalg.norm(ref.x[:, c]) < 1e-12
+        del s3
+    say("  converged solve")
+    x, info = s.solve(bt, tol=1e-8, maxit=2000)
+    X = to_np(x)
+    assert np.all(info.status == 0)
+    rt = np.linalg.norm(b - S @ X, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rt <= 1.1e-8) and np.allclose(rt, info.relres_true, rtol=1e-6)
+    assert np.all(np.linalg.norm(X - xs, axis=0) / np.linalg.norm(xs, axis=0) < 1e-4)
