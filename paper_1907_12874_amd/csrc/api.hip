@@ -369,7 +369,11 @@ int read_info(bicgstab_ctx* h, bicgstab_info* info) {
   HIPCHK(hipMemcpyAsync(h->h_ist, h->ist, (size_t)I_NINT * kMaxK * 4, hipMemcpyDeviceToHost, h->ws));
   HIPCHK(hipMemcpyAsync(h->h_glob, h->glob, sizeof(Globals), hipMemcpyDeviceToHost, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
-  h->hist_count = std::min(h->h_glob->it, h->hist_cap);
+  // history rows = the most passes any column ran (a column can stop inside
+  // a pass after the last column's iteration counter was advanced)
+  int most = h->h_glob->it;
+  for (int c = 0; c < h->k; ++c) most = std::max(most, h->h_ist[I_ITERS * kMaxK + c]);
+  h->hist_count = std::min(most, h->hist_cap);
   if (!info) return BICGSTAB_OK;
   for (int c = 0; c < h->k; ++c) {
     if (info->iters) info->iters[c] = h->h_ist[I_ITERS * kMaxK + c];

@@ -127,8 +127,8 @@ enum StepKind { K_SPMM = 0, K_PREC, K_GROUP };
 struct Step {
   StepKind kind;
   int op;        // OpId for K_GROUP
-  int in[6];     // VecIds
-  int out[4];
+  int in[8];     // VecIds (a vector pass reads at most 7 blocks)
+  int out[6];    // (and writes at most 5)
   int slot;      // first dot slot written
   int fin;       // FinStep
   int nin, nout; // vector reads / writes of the pass (traffic accounting)

@@ -9,6 +9,7 @@
 // rule of Table 2 and its footnotes). Sparse products and preconditioner
 // applications are separate launches in both forms (Section 2.3 counts them
 // apart from Table 2).
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.hpp"
@@ -52,8 +53,9 @@ Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, in
   std::memset(&s, 0, sizeof(s));
   s.kind = K_GROUP;
   s.op = op;
-  for (int i = 0; i < 6; ++i) s.in[i] = V_NONE;
-  for (int i = 0; i < 4; ++i) s.out[i] = V_NONE;
+  for (int i = 0; i < 8; ++i) s.in[i] = V_NONE;
+  for (int i = 0; i < 6; ++i) s.out[i] = V_NONE;
+  if (in.size() > 7 || out.size() > 5) std::abort();  // a plan bug; kernels take at most 7 in / 5 out
   int i = 0;
   for (int v : in) s.in[i++] = v;
   int o = 0;
