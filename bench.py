@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-RHS BiCGStab on one MI355X.
+
+Workload: 3D 7-point convection-diffusion on a 128^3 grid (n = 2,097,152,
+14,581,760 nonzeros, FP64 CSR), velocity (1, 0.7, 0.3), Jacobi
+preconditioner, k right-hand sides b = A x* with x* ~ U[-1,1], tol 1e-8.
+
+A step is one full solve of all k right-hand sides (start-up passes,
+iterations until every column meets the tolerance, exit residual check),
+with the matrix, b and x0 already in HBM. The headline is the classical merged
+form at k = 32, in RHS-iterations per second (sum over columns of the passes
+each column ran, divided by the step time).
+
+The JSON line also carries:
+  roofline      the dominant kernel of one iteration, timed with HIP events
+                around each launch on the stream it runs on, against 8 TB/s;
+  cpu_baseline  the CPU oracle, timed on a bounded sample (one column, fixed
+                passes) on the host;
+  sweep         merged vs basic for every method at k = 1..32: fixed-pass
+                throughput (RHS-iterations/s, algorithmic GB/s) and solves to
+                the same tolerance (equal accuracy, checked per column).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+OP_NAMES = [
+    "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
+    "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g1", "pp_g2", "pp_g3", "pp_g4",
+    "ref_resid", "ref_scale", "ref_update",
+]
+
+
+def spmm_bytes(n, nnz, k, elem=8):
+    """Compulsory bytes of one sparse product: values + column indices, row
+    pointers, X read once, Y written once."""
+    return (elem + 4) * nnz + 4 * (n + 1) + 2 * elem * n * k
+
+
+def iteration_bytes(n, nnz, k, traffic, elem=8):
+    """Algorithmic bytes of one iteration: two products, the vector passes'
+    block reads and writes (Table 2 counting) and the Jacobi applications
+    (block in, block out, diagonal)."""
+    blk = elem * n * k
+    return (traffic["spmms"] * spmm_bytes(n, nnz, k, elem) + (traffic["reads"] + traffic["writes"]) * blk
+            + traffic["precond_apps"] * (2 * blk + elem * n))
+
+
+def step_bytes(step, n, nnz, k):
+    blk = 8 * n * k
+    if step["kind"] == "spmm":
+        return spmm_bytes(n, nnz, k)
+    if step["kind"] == "prec":
+        return 2 * blk + 8 * n
+    return (step["nin"] + step["nout"]) * blk
+
+
+def kernel_name(step):
+    if step["kind"] == "spmm":
+        return "spmm_kernel"
+    if step["kind"] == "prec":
+        return "prec_kernel"
+    return "group_kernel<" + OP_NAMES[step["op"]] + ">"
+
+
+def roofline_of(solver, b, n, nnz, k, iters=10):
+    import torch
+
+    xs = torch.zeros_like(b)
+    steps = solver.kernel_times(b, xs, iters=iters)
+    agg = {}
+    for st in steps:
+        name = kernel_name(st)
+        a = agg.setdefault(name, {"ms": 0.0, "launches": 0, "bytes": 0.0})
+        a["ms"] += st["ms"]
+        a["launches"] += 1
+        a["bytes"] += step_bytes(st, n, nnz, k)
+    total_ms = sum(a["ms"] for a in agg.values())
+    total_bytes = sum(a["bytes"] for a in agg.values())
+    dom = max(agg, key=lambda nm: agg[nm]["ms"])
+    d = agg[dom]
+    per_launch_bytes = d["bytes"] / d["launches"]
+    per_launch_ms = d["ms"] / d["launches"]
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    kernels = {nm: {"avg_ms": a["ms"] / a["launches"], "launches_per_iter": a["launches"],
+                    "GBps": (a["bytes"] / a["launches"]) / (a["ms"] / a["launches"] * 1e-3) / 1e9,
+                    "share": a["ms"] / total_ms} for nm, a in agg.items()}
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel": dom,
+            "bytes_per_launch": per_launch_bytes, "avg_launch_ms": per_launch_ms}
+    it_summary = {"kernel_ms_per_iter": total_ms, "kernel_GBps_per_iter": total_bytes / (total_ms * 1e-3) / 1e9}
+    return roof, kernels, it_summary
+
+
+def cpu_baseline(A, b, variant, formulation, precond, budget_s=15.0):
+    """The oracle as it stands, one column, fixed passes, single thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+
+    S = A.to_scipy()
+    col = np.ascontiguousarray(b[:, 0])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.solve_column(S, col, None, variant, formulation, precond, 0.0, 2)
+        t_probe = (time.perf_counter() - t0) / 2
+        m = int(max(3, min(200, budget_s / max(t_probe, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.solve_column(S, col, None, variant, formulation, precond, 0.0, m)
+        t = time.perf_counter() - t0
+    return {"value": round(m / t, 3), "unit": "RHS-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{variant}/{formulation}/{precond}, column 0 of the same workload, {m} fixed passes "
+                      f"(stop test off), {t:.1f} s; NumPy/SciPy FP64 limited to 1 thread "
+                      f"(host has {os.cpu_count()} logical CPUs)",
+            "seconds": round(t, 2), "passes": m}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--variant", default="classical")
+    ap.add_argument("--formulation", default="merged")
+    ap.add_argument("--precond", default="jacobi")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--sweep-passes", type=int, default=20)
+    ap.add_argument("--sweep-k", default="1,2,4,8,16,32")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it would shard); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1907_12874_amd as pk
+    from workloads import config_problem
+
+    pk.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    cfg = config_problem(1, seed=0, k=args.k, scale=args.grid)
+    A = cfg["A"]
+    n, nnz, k = A.n, A.nnz, args.k
+    print(f"# workload 3D 7-point {args.grid}^3: n={n} nnz={nnz} k={k} (generated in {time.perf_counter() - t_gen:.1f} s)",
+          file=sys.stderr, flush=True)
+    b = torch.from_numpy(cfg["b"]).to(dev)
+    x0 = torch.zeros_like(b)
+    x = torch.empty_like(b)
+
+    # ---------------------------------------------------------- headline
+    s = pk.Solver.from_csr(A, k, variant=args.variant, formulation=args.formulation, precond=args.precond,
+                           device=dev)
+    for _ in range(args.warmup):
+        s.solve(b, x0, tol=args.tol, maxit=5000, out=x)
+    torch.cuda.synchronize()
+    iters_total = 0
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = s.solve(b, x0, tol=args.tol, maxit=5000, out=x)
+        infos.append(info)
+        iters_total += int(info.iters.sum())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    info = infos[-1]
+    if not np.all(info.status == 0) or not np.all(info.relres_true <= 1.1 * args.tol):
+        print(f"# WARNING: not every column converged: status {info.status}", file=sys.stderr)
+    traffic = pk.plan_traffic(args.variant, args.formulation, args.precond)
+    it_bytes = iteration_bytes(n, nnz, k, traffic)
+    value = iters_total / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+    max_iters = int(info.iters.max())
+    solve_gbps = max_iters * it_bytes / (ms_per_step * 1e-3) / 1e9
+    print(f"# headline: {ms_per_step:.1f} ms/solve, iters {int(info.iters.min())}..{max_iters}, "
+          f"{value:.0f} RHS-it/s, {solve_gbps:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "RHS-iterations/s + HBM GB/s, merged vs plain BiCGStab, k=1..32, equal accuracy",
+        "value": round(value, 1),
+        "unit": "RHS-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D 7-point convection-diffusion {args.grid}^3, velocity (1,0.7,0.3), Jacobi, "
+                               f"k={k} RHS, tol {args.tol:g}, {args.variant} {args.formulation} BiCGStab",
+                   "n": n, "nnz": nnz, "k": k, "variant": args.variant, "formulation": args.formulation,
+                   "precond": args.precond, "tol": args.tol},
+        "solve": {"iters_min": int(info.iters.min()), "iters_max": max_iters,
+                  "relres_true_max": float(info.relres_true.max()), "all_converged": bool(np.all(info.status == 0)),
+                  "bytes_per_iteration": it_bytes, "algorithmic_GBps": round(solve_gbps, 1),
+                  "frac_of_peak": round(solve_gbps / PEAK_HBM_GBPS, 4), "stats": s.stats()},
+    }
+
+    if not args.no_roofline:
+        roof, kernels, it_summary = roofline_of(s, b, n, nnz, k)
+        out["roofline"] = roof
+        out["kernels"] = kernels
+        out["iteration"] = it_summary
+        print(f"# roofline: {roof['kernel']} {roof['achieved']:.0f} GB/s ({roof['frac']:.1%})", file=sys.stderr,
+              flush=True)
+
+    # ------------------------------------------------------------- sweep
+    if not args.no_sweep:
+        sweep = []
+        ks = [int(v) for v in args.sweep_k.split(",") if v]
+        for kk in ks:
+            bk = b[:, :kk].contiguous() if kk <= k else None
+            if bk is None:
+                continue
+            x0k = torch.zeros_like(bk)
+            xk = torch.empty_like(bk)
+            for variant in ("classical", "reordered", "pipelined"):
+                for form in ("merged", "basic"):
+                    sv = pk.Solver.from_csr(A, kk, variant=variant, formulation=form, precond=args.precond, device=dev)
+                    tr = pk.plan_traffic(variant, form, args.precond)
+                    ib = iteration_bytes(n, nnz, kk, tr)
+                    # fixed passes (stop test off): pure per-iteration throughput
+                    sv.solve(bk, x0k, tol=0.0, maxit=2, out=xk)
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                    sv.solve(bk, x0k, tol=0.0, maxit=args.sweep_passes, out=xk)
+                    torch.cuda.synchronize()
+                    tt = time.perf_counter() - ta
+                    # solve to the tolerance: equal accuracy
+                    ta = time.perf_counter()
+                    _, inf = sv.solve(bk, x0k, tol=args.tol, maxit=5000, out=xk)
+                    torch.cuda.synchronize()
+                    ts = time.perf_counter() - ta
+                    row = {"k": kk, "variant": variant, "formulation": form, "launches_per_iter": tr["launches"],
+                           "bytes_per_iter": ib,
+                           "fixed_rhs_it_per_s": round(kk * args.sweep_passes / tt, 1),
+                           "fixed_GBps": round(args.sweep_passes * ib / tt / 1e9, 1),
+                           "fixed_ms_per_iter": round(tt / args.sweep_passes * 1e3, 4),
+                           "solve_ms": round(ts * 1e3, 2), "solve_iters_max": int(inf.iters.max()),
+                           "solve_rhs_it_per_s": round(float(inf.iters.sum()) / ts, 1),
+                           "equal_accuracy": bool(np.all(inf.status == 0) and np.all(inf.relres_true <= 1.1 * args.tol)),
+                           "relres_true_max": float(inf.relres_true.max())}
+                    sweep.append(row)
+                    print(f"# sweep k={kk:2d} {variant:9s} {form:6s}: {row['fixed_ms_per_iter']:.3f} ms/it "
+                          f"{row['fixed_GBps']:.0f} GB/s | solve {row['solve_ms']:.0f} ms, "
+                          f"{row['solve_iters_max']} it", file=sys.stderr, flush=True)
+                    sv.close()
+                    del sv
+        out["sweep"] = sweep
+        gains = {}
+        for kk in ks:
+            for variant in ("classical", "reordered", "pipelined"):
+                m = [r for r in sweep if r["k"] == kk and r["variant"] == variant]
+                if len(m) == 2:
+                    mb = {r["formulation"]: r for r in m}
+                    gains[f"{variant}_k{kk}"] = round(1 - mb["merged"]["fixed_ms_per_iter"] / mb["basic"]["fixed_ms_per_iter"], 4)
+        out["merging_time_reduction"] = gains
+
+    # ------------------------------------------------------- CPU baseline
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(A, cfg["b"], args.variant, args.formulation, args.precond)
+        print(f"# cpu baseline: {out['cpu_baseline']['value']} RHS-it/s", file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

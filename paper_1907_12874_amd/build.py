@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbicgstab.so")
-SOURCES = ["kernels.hip", "batched.hip", "api.hip", "plans.cpp"]
+SOURCES = ["kernels.hip", "spmm.hip", "batched.hip", "api.hip", "plans.cpp"]
 
 # -ffp-contract=off: no fused multiply-add contraction, so the vector updates
 # and products round like their plain definitions. The packed-FP32 feature is

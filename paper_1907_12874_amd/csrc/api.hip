@@ -70,7 +70,7 @@ struct bicgstab_ctx {
   hipEvent_t ev = nullptr;
   int device = 0;
   Plan plan;
-  std::vector<int32_t> blk_host;
+  SpmmPartition part;  // row blocks of the product with A
   // workspace
   char* base = nullptr;
   size_t bytes = 0;
@@ -89,8 +89,9 @@ struct bicgstab_ctx {
   unsigned* counter = nullptr;
   double* hist = nullptr;
   int hist_cap = 0;
-  int grid_cap = 1024;
+  GridCaps caps{512, 512};  // workgroup caps: streaming passes, passes with dots
   int chunk = 8;
+  int spmm_opl = 0;     // SpMM rows per lane per row block (0: default for the width)
   bool use_graph = true;
   // pinned host mirrors
   int* h_nrun = nullptr;
@@ -105,7 +106,7 @@ struct bicgstab_ctx {
   double* val_t = nullptr;
   float* val32_t = nullptr;
   int32_t* blk_t = nullptr;
-  std::vector<int32_t> blk_t_host;
+  SpmmPartition part_t;  // row blocks of the product with A^T
   std::vector<GraphEntry> graphs;
   // statistics of the last solve
   int stat_iters = 0, stat_launches = 0, stat_polls = 0;
@@ -139,8 +140,8 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_diag = take((size_t)h->n * 8);
   const size_t o_diag32 = take(fp32_inner(h) ? (size_t)h->n * 4 : 0);
   const size_t o_val32 = take(fp32_inner(h) ? (size_t)h->nnz * 4 : 0);
-  const size_t o_blk = take(h->blk_host.size() * 4);
-  const size_t o_part = take((size_t)h->grid_cap * 7 * kMaxK * 8);
+  const size_t o_blk = take(h->part.blk.size() * 4);
+  const size_t o_part = take((size_t)h->caps.dot_blocks * 7 * kMaxK * 8);
   const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
   const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
   const size_t o_glob = take(sizeof(Globals));
@@ -194,7 +195,7 @@ int prepare(bicgstab_ctx* h) {
     h->owned = true;
   }
   layout(h, true);
-  HIPCHK(hipMemcpyAsync(h->blk, h->blk_host.data(), h->blk_host.size() * 4, hipMemcpyHostToDevice, h->ws));
+  HIPCHK(hipMemcpyAsync(h->blk, h->part.blk.data(), h->part.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
   if (h->precond == BICGSTAB_PRECOND_JACOBI || fp32_inner(h)) {
     HIPCHK(hipMemsetAsync(h->glob, 0, sizeof(Globals), h->ws));
     HIPCHK(launch_extract_diag(h->row_ptr, h->col, h->val, h->diag, h->diag32, (int)h->n, h->glob, h->ws));
@@ -218,13 +219,17 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
     m.col = h->col;
     m.val = fp32 ? (const void*)h->val32 : (const void*)h->val;
     m.blk = h->blk;
-    m.nblk = (int)h->blk_host.size() - 1;
+    m.nblk = (int)h->part.blk.size() - 1;
+    m.nnz_cap = h->part.nnz_cap;
+    m.rows_cap = h->part.rows_cap;
   } else {
     m.row_ptr = h->rp_t;
     m.col = h->col_t;
     m.val = fp32 ? (const void*)h->val32_t : (const void*)h->val_t;
     m.blk = h->blk_t;
-    m.nblk = (int)h->blk_t_host.size() - 1;
+    m.nblk = (int)h->part_t.blk.size() - 1;
+    m.nnz_cap = h->part_t.nnz_cap;
+    m.rows_cap = h->part_t.rows_cap;
   }
   return m;
 }
@@ -243,7 +248,7 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* 
       void* out[5] = {};
       for (int i = 0; i < st.nin; ++i) in[i] = vp[st.in[i]];
       for (int i = 0; i < st.nout; ++i) out[i] = vp[st.out[i]];
-      return launch_group(st.op, in, out, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->grid_cap, s);
+      return launch_group(st.op, in, out, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->caps, s);
     }
   }
   return hipErrorInvalidValue;
@@ -328,7 +333,7 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
       // inner solves start from d = 0, so A d = 0 without a product
       const void* in0[7] = {};
       void* out0[5] = {vp[st.out[0]]};
-      HIPCHK(launch_group(OP_FILL0, in0, out0, (int)h->n, h->k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+      HIPCHK(launch_group(OP_FILL0, in0, out0, (int)h->n, h->k, 0, F_NONE, ctl, true, h->caps, h->ws));
     } else {
       HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
     }
@@ -358,7 +363,7 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
     HIPCHK(launch_spmm(M, x, z, h->k, false, nullptr, h->ws));
     const void* in[7] = {b, z, vp[V_R]};
     void* out[5] = {};
-    HIPCHK(launch_group(OP_EXIT, in, out, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->grid_cap, h->ws));
+    HIPCHK(launch_group(OP_EXIT, in, out, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->caps, h->ws));
     *launches += 2;
   }
   return BICGSTAB_OK;
@@ -410,7 +415,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {b, Z};
       void* out[5] = {R};
-      HIPCHK(launch_group(OP_REF_RESID, in, out, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->grid_cap, h->ws));
+      HIPCHK(launch_group(OP_REF_RESID, in, out, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->caps, h->ws));
     }
     *launches += 3;
     HIPCHK(hipMemcpyAsync(h->h_sc, h->sc, (size_t)S_NSCAL * kMaxK * 8, hipMemcpyDeviceToHost, h->ws));
@@ -445,7 +450,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
                             h->ws));
       const void* in[7] = {};
       void* out[5] = {x};
-      HIPCHK(launch_group(OP_ZEROB, in, out, (int)h->n, k, 0, F_NONE, ctl, false, h->grid_cap, h->ws));
+      HIPCHK(launch_group(OP_ZEROB, in, out, (int)h->n, k, 0, F_NONE, ctl, false, h->caps, h->ws));
       ++*launches;
     }
     if (all_done) break;
@@ -456,7 +461,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {R};
       void* out[5] = {B32, D};
-      HIPCHK(launch_group(OP_REF_SCALE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+      HIPCHK(launch_group(OP_REF_SCALE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
     int rc = krylov(h, 0, true, B32, D, inner_tol, maxit, launches, polls, enq);
@@ -469,7 +474,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {x, D};
       void* out[5] = {x};
-      HIPCHK(launch_group(OP_REF_UPDATE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->grid_cap, h->ws));
+      HIPCHK(launch_group(OP_REF_UPDATE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
   }
@@ -531,9 +536,9 @@ int build_transpose(bicgstab_ctx* h) {
   HIPCHK(hipMemcpyAsync(rp.data(), h->rp_t, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   HIPCHK(hipFree(counts));
-  h->blk_t_host = spmm_partition(rp, h->k);
-  HIPCHK(alloc((void**)&h->blk_t, h->blk_t_host.size() * 4));
-  HIPCHK(hipMemcpyAsync(h->blk_t, h->blk_t_host.data(), h->blk_t_host.size() * 4, hipMemcpyHostToDevice, h->ws));
+  h->part_t = spmm_partition(rp, h->k, h->spmm_opl);
+  HIPCHK(alloc((void**)&h->blk_t, h->part_t.blk.size() * 4));
+  HIPCHK(hipMemcpyAsync(h->blk_t, h->part_t.blk.data(), h->part_t.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   h->have_t = true;
   return BICGSTAB_OK;
@@ -573,7 +578,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   h->val = A->d_values;
   h->user_stream = (hipStream_t)stream;
   h->hist_cap = std::max(0, env_int("BICGSTAB_HIST_CAP", 1024));
-  h->grid_cap = std::max(8, env_int("BICGSTAB_GRID_CAP", 1024));
+  h->caps.blocks = std::max(8, env_int("BICGSTAB_GRID_CAP", 512));
+  h->caps.dot_blocks = std::max(1, std::min(4096, env_int("BICGSTAB_DOT_GRID", 512)));
   h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
   h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;
   std::string err;
@@ -610,7 +616,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
         if (c < 0 || c >= n) return bail(BICGSTAB_EINVAL, "column index out of range");
     }
   }
-  h->blk_host = spmm_partition(rp, k);
+  h->spmm_opl = std::max(0, std::min(64, env_int("BICGSTAB_SPMM_RPL", 0)));
+  h->part = spmm_partition(rp, k, h->spmm_opl);
   if (hipHostMalloc((void**)&h->h_nrun, 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_sc, (size_t)S_NSCAL * kMaxK * 8, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_ist, (size_t)I_NINT * kMaxK * 4, hipHostMallocDefault) != hipSuccess ||
@@ -797,10 +804,12 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
   std::string err;
   if (!build_plan(variant, formulation, precond, &P, &err)) return fail(BICGSTAB_EINVAL, err);
   int r = 0, w = 0, pa = 0, sp = 0;
+  int fin_kernels = 0;
   for (const Step& s : P.iter) {
     if (s.kind == K_GROUP) {
       r += s.nin;
       w += s.nout;
+      if (op_info(s.op).ndot > 0 || s.fin != F_NONE) ++fin_kernels;  // its finalize kernel
     } else if (s.kind == K_PREC) {
       ++pa;
     } else {
@@ -811,7 +820,7 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
   if (writes) *writes = w;
   if (precond_apps) *precond_apps = pa;
   if (spmms) *spmms = sp;
-  if (launches) *launches = (int)P.iter.size();
+  if (launches) *launches = (int)P.iter.size() + fin_kernels;
   return BICGSTAB_OK;
 }
 

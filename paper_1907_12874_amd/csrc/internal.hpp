@@ -11,8 +11,8 @@ namespace bcg {
 
 constexpr int kBlock = 256;       // threads per workgroup for every kernel
 constexpr int kMaxK = 64;         // columns per handle (one wavefront of lanes)
-constexpr int kSpmmNnzMax = 2048; // CSR entries staged in LDS per SpMM row block
-constexpr int kSpmmRowsMax = 256; // rows per SpMM row block
+constexpr int kSpmmNnzMax = 4096; // CSR entries staged in LDS per SpMM row block
+constexpr int kSpmmRowsMax = 1024; // rows per SpMM row block
 
 // ---- per-column device state: scalars sc[slot * kMaxK + c] -----------------
 enum ScalarSlot {
@@ -160,14 +160,29 @@ struct SpmmMat {
   const int32_t* blk;  // row-block starts, nblk + 1 entries
   int nblk;
   int n;
+  int nnz_cap;   // entries staged in LDS per row block (largest block, <= kSpmmNnzMax)
+  int rows_cap;  // rows of the largest row block
+};
+
+struct SpmmPartition {
+  std::vector<int32_t> blk;
+  int nnz_cap;
+  int rows_cap;
 };
 
 hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
 hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
+// Workgroup-count caps: plain streaming passes (256 lanes per workgroup) and
+// passes with dot products (1024 lanes per workgroup). The dot cap also sizes
+// the reduction partials buffer.
+struct GridCaps {
+  int blocks;
+  int dot_blocks;
+};
 hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
-                        const Ctl& ctl, bool fp32, int grid_cap, hipStream_t s);
+                        const Ctl& ctl, bool fp32, const GridCaps& caps, hipStream_t s);
 hipError_t launch_setup_state(const Ctl& ctl, double tol, int maxit, int hist_cap, hipStream_t s);
 hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
 hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,
@@ -183,6 +198,7 @@ hipError_t launch_transpose_sort_rows(const int32_t* row_ptr_t, int32_t* col_t, 
 hipError_t launch_gather_values(const double* val, const int32_t* perm, double* val_t, int64_t nnz, hipStream_t s);
 
 // Row-block partition for the CSR-stream SpMM (host).
-std::vector<int32_t> spmm_partition(const std::vector<int32_t>& row_ptr, int k);
+// rows_per_lane_override <= 0 picks the default for the width.
+SpmmPartition spmm_partition(const std::vector<int32_t>& row_ptr, int k, int rows_per_lane_override);
 
 }  // namespace bcg

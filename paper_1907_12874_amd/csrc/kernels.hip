@@ -10,13 +10,16 @@
 //     coalesced loads (a CSR-stream layout), then gathers X rows;
 //   * a vector pass computes all its dot products (one per column) while it
 //     streams, reduces them inside the wave with xor shuffles between lanes of
-//     the same column, across waves through LDS, and across workgroups in the
-//     last workgroup to finish (a fixed summation order, so results are
-//     bitwise repeatable), which then runs the per-column scalar recurrence;
+//     the same column and across waves through LDS, and stores one partial per
+//     workgroup; a one-workgroup finalize kernel sums the partials in a fixed
+//     order (results are bitwise repeatable) and runs the per-column scalar
+//     recurrence, so no streaming workgroup needs a device-scope fence;
 //   * all arithmetic is IEEE with no contraction (the library is built with
 //     -ffp-contract=off) and Jacobi divides by a_ii, so the vector updates and
 //     the products round exactly like a plain sequential evaluation.
 #include <math.h>
+
+#include <algorithm>
 
 #include "internal.hpp"
 
@@ -564,63 +567,18 @@ struct GArgs {
   Ctl ctl;
 };
 
-// Sum the per-workgroup partials (P = ndot * k values per workgroup) in the
-// last workgroup to arrive, write the results to the dot slots, then run the
-// finalize step. The order of every sum is fixed by the grid, not by timing.
-__device__ void last_block_finish(const GArgs& a, int ndot) {
-  __shared__ int s_last;
-  __shared__ double s_g[kBlock];
-  const int k = a.k;
-  const int P = ndot * k;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(a.ctl.counter, 1u);
-    s_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  const double* part = a.ctl.partials;
-  const int t = threadIdx.x;
-  if (P > 0) {
-    if (P <= kBlock) {
-      const int G = kBlock / P;
-      double v = 0.0;
-      if (t < G * P) {
-        const int p = t % P, g = t / P;
-        for (int b = g; b < nb; b += G) v += __builtin_nontemporal_load(&part[(size_t)b * P + p]);
-      }
-      s_g[t] = v;
-      __syncthreads();
-      if (t < P) {
-        double s = 0.0;
-        for (int g = 0; g < G; ++g) s += s_g[g * P + t];
-        const int d = t / k, c = t - d * k;
-        SC(a.ctl, S_D0 + a.slot + d, c) = s;
-      }
-    } else {
-      for (int p = t; p < P; p += kBlock) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += __builtin_nontemporal_load(&part[(size_t)b * P + p]);
-        const int d = p / k, c = p - d * k;
-        SC(a.ctl, S_D0 + a.slot + d, c) = s;
-      }
-    }
-  }
-  __syncthreads();
-  if (a.fin != F_NONE && t < k) finalize_column(a.fin, t, a.ctl);
-  __syncthreads();
-  if (t == 0) {
-    if (a.fin != F_NONE) finalize_global(a.fin, a.ctl);
-    *a.ctl.counter = 0u;
-  }
-}
+// Dot products leave the streaming pass as one partial sum per workgroup and
+// pair (dot d, column c), stored pair-major: partials[p * nb + b]. A separate
+// one-workgroup finalize kernel then sums them and runs the scalar step: the
+// kernel boundary orders the partial stores before their reads, so no
+// workgroup of a pass needs a device-scope fence or atomic (on this
+// multi-XCD part a device-scope release writes back the L2, and one per
+// workgroup serialises the whole pass).
+constexpr int kFinBlock = 1024;
 
-template <int ND>
-__device__ void block_reduce_and_finish(const double* acc, const GArgs& a) {
-  __shared__ double s_w[kBlock / 64][ND][kMaxK];
+template <int ND, int BS>
+__device__ void block_reduce_store(const double* acc, const GArgs& a) {
+  __shared__ double s_w[BS / 64][ND][kMaxK];
   const int kp = 1 << a.kpl;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -631,21 +589,56 @@ __device__ void block_reduce_and_finish(const double* acc, const GArgs& a) {
   }
   __syncthreads();
   const int k = a.k, P = ND * k;
-  double* part = a.ctl.partials + (size_t)blockIdx.x * P;
-  for (int t = threadIdx.x; t < P; t += kBlock) {
+  const int nb = gridDim.x;
+  for (int t = threadIdx.x; t < P; t += BS) {
     const int d = t / k, c = t - d * k;
     double v = s_w[0][d][c];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) v += s_w[w][d][c];
-    part[t] = v;
+    for (int w = 1; w < BS / 64; ++w) v += s_w[w][d][c];
+    a.ctl.partials[(size_t)t * nb + blockIdx.x] = v;
   }
-  last_block_finish(a, ND);
+}
+
+// One workgroup: sum the nb partials of each of the P pairs (G lanes per pair
+// read consecutive workgroups' values, coalesced, then the G sums are added in
+// lane order), write the dot slots, run the finalize step. Every sum has a
+// fixed order, so results are bitwise repeatable.
+__global__ __launch_bounds__(kFinBlock) void finalize_kernel(Ctl ctl, int P, int nb, int slot, int fin, int early) {
+  if (early && ctl.glob->nrun == 0) return;
+  __shared__ double s_g[kFinBlock];
+  const int k = ctl.k;
+  const int t = threadIdx.x;
+  if (P > 0) {
+    const int G = P <= kFinBlock ? kFinBlock / P : 1;  // lanes per pair
+    const int PP = kFinBlock / G;                        // pairs per round
+    for (int p0 = 0; p0 < P; p0 += PP) {
+      const int p = p0 + t / G, g = t % G;
+      double v = 0.0;
+      if (t < PP * G && p < P) {
+        const double* q = ctl.partials + (size_t)p * nb;
+#pragma unroll 8
+        for (int b = g; b < nb; b += G) v += q[b];
+      }
+      s_g[t] = v;
+      __syncthreads();
+      if (t < PP && p0 + t < P) {
+        double sum = 0.0;
+        for (int j = 0; j < G; ++j) sum += s_g[t * G + j];
+        const int pp = p0 + t, d = pp / k, c = pp - d * k;
+        SC(ctl, S_D0 + slot + d, c) = sum;
+      }
+      __syncthreads();
+    }
+  }
+  if (fin != F_NONE && t < k) finalize_column(fin, t, ctl);
+  __syncthreads();
+  if (t == 0 && fin != F_NONE) finalize_global(fin, ctl);
 }
 
 // ---------------------------------------------------------- group kernel ---
 
-template <class Op, class T, int U>
-__global__ __launch_bounds__(kBlock) void group_kernel(GArgs a) {
+template <class Op, class T, int U, int BS>
+__global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
   if (Op::EARLY && a.ctl.glob->nrun == 0) return;
   const int kpl = a.kpl;
   const int kp = 1 << kpl;
@@ -670,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void group_kernel(GArgs a) {
     cf.omega = SC(a.ctl, S_OMEGA, c);
     cf.beta = SC(a.ctl, S_BETA, c);
     cf.scale = SC(a.ctl, S_SCALE, c);
-    const int rpb = kBlock >> kpl;
+    const int rpb = BS >> kpl;
     const long n = a.n;
     const long stride = (long)gridDim.x * rpb;
     long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl);
@@ -713,27 +706,32 @@ __global__ __launch_bounds__(kBlock) void group_kernel(GArgs a) {
       }
     }
   }
-  if constexpr (Op::NDOT > 0) {
-    block_reduce_and_finish<Op::NDOT>(acc, a);
-  } else {
-    if (a.fin != F_NONE) last_block_finish(a, 0);
-  }
+  if constexpr (Op::NDOT > 0) block_reduce_store<Op::NDOT, BS>(acc, a);
 }
 
 template <class Op, class T>
-hipError_t launch_op(const GArgs& a0, int grid_cap, hipStream_t s) {
+hipError_t launch_op(const GArgs& a0, const GridCaps& caps, hipStream_t s) {
   GArgs a = a0;
-  const int rpb = kBlock >> a.kpl;
+  constexpr int BS = kBlock;
+  const int cap = Op::NDOT > 0 ? caps.dot_blocks : caps.blocks;
+  const int rpb = BS >> a.kpl;
   long blocks = (a.n + rpb - 1) / rpb;
-  if (blocks > grid_cap) blocks = grid_cap;
+  if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   constexpr int U = Op::NIN <= 4 ? 4 : 2;
-  hipLaunchKernelGGL((group_kernel<Op, T, U>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+  hipLaunchKernelGGL((group_kernel<Op, T, U, BS>), dim3((unsigned)blocks), dim3(BS), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (Op::NDOT > 0 || a.fin != F_NONE) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, a.ctl, Op::NDOT * a.k, (int)blocks, a.slot,
+                       a.fin, Op::EARLY ? 1 : 0);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <class T>
-hipError_t dispatch_op(int op, const GArgs& a, int grid_cap, hipStream_t s) {
+hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStream_t s) {
   switch (op) {
     case OP_INIT: return launch_op<KInit, T>(a, grid_cap, s);
     case OP_INIT_P: return launch_op<KInitP, T>(a, grid_cap, s);
@@ -767,7 +765,7 @@ hipError_t dispatch_op(int op, const GArgs& a, int grid_cap, hipStream_t s) {
 }
 
 hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
-                        const Ctl& ctl, bool fp32, int grid_cap, hipStream_t s) {
+                        const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s) {
   GArgs a;
   for (int i = 0; i < 7; ++i) a.in[i] = in[i];
   for (int i = 0; i < 5; ++i) a.out[i] = out[i];
@@ -781,122 +779,6 @@ hipError_t launch_group(int op, const void* const* in, void* const* out, int n, 
   a.fin = fin;
   a.ctl = ctl;
   return fp32 ? dispatch_op<float>(op, a, grid_cap, s) : dispatch_op<double>(op, a, grid_cap, s);
-}
-
-// --------------------------------------------------------------- SpMM ---
-
-// Row blocks for the CSR-stream product: contiguous rows whose entries fit in
-// LDS, with about 256 * 2 outputs per block. A row longer than the LDS budget
-// gets a block of its own and is processed in chunks.
-std::vector<int32_t> spmm_partition(const std::vector<int32_t>& row_ptr, int k) {
-  const int n = (int)row_ptr.size() - 1;
-  const int kp = pad_k(k);
-  int rows_target = (kBlock / kp) * 2;
-  if (rows_target > kSpmmRowsMax) rows_target = kSpmmRowsMax;
-  if (rows_target < 1) rows_target = 1;
-  std::vector<int32_t> blk;
-  blk.push_back(0);
-  int r0 = 0;
-  while (r0 < n) {
-    int r = r0 + 1;  // always take at least one row
-    while (r < n && r - r0 < rows_target && row_ptr[r + 1] - row_ptr[r0] <= kSpmmNnzMax) ++r;
-    blk.push_back(r);
-    r0 = r;
-  }
-  return blk;
-}
-
-// Workgroups are handed to the 8 XCDs round-robin; remap so each XCD walks a
-// contiguous range of row blocks and the neighbouring X rows a stencil
-// re-reads stay in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nblk) {
-  const int per = (nblk + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
-template <class T, int KPL>
-__global__ __launch_bounds__(kBlock) void spmm_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y, int k,
-                                                      const Globals* glob) {
-  if (glob && glob->nrun == 0) return;
-  const int L = xcd_remap(blockIdx.x, A.nblk);
-  if (L >= A.nblk) return;
-  __shared__ int s_col[kSpmmNnzMax];
-  __shared__ T s_val[kSpmmNnzMax];
-  __shared__ int s_rp[kSpmmRowsMax + 1];
-  __shared__ T s_red[kBlock];
-  const int r0 = A.blk[L], r1 = A.blk[L + 1];
-  const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
-  const int ne = e1 - e0;
-  const T* __restrict__ val = static_cast<const T*>(A.val);
-  constexpr int kp = 1 << KPL;
-  const int c = threadIdx.x & (kp - 1);
-  const int rsub = threadIdx.x >> KPL;
-  constexpr int rpp = kBlock >> KPL;
-  if (ne <= kSpmmNnzMax) {
-    for (int i = threadIdx.x; i < ne; i += kBlock) {
-      s_col[i] = A.col[e0 + i];
-      s_val[i] = val[e0 + i];
-    }
-    for (int i = threadIdx.x; i <= r1 - r0; i += kBlock) s_rp[i] = A.row_ptr[r0 + i] - e0;
-    __syncthreads();
-    if (c < k) {
-      for (int r = rsub; r < r1 - r0; r += rpp) {
-        T sum = (T)0;
-        const int eb = s_rp[r], ee = s_rp[r + 1];
-        for (int e = eb; e < ee; ++e) sum += s_val[e] * X[(size_t)s_col[e] * k + c];
-        Y[(size_t)(r0 + r) * k + c] = sum;
-      }
-    }
-  } else {
-    // one long row (r1 == r0 + 1): lanes of the same column split its entries
-    T sum = (T)0;
-    for (int base = 0; base < ne; base += kSpmmNnzMax) {
-      const int m = min(kSpmmNnzMax, ne - base);
-      __syncthreads();
-      for (int i = threadIdx.x; i < m; i += kBlock) {
-        s_col[i] = A.col[e0 + base + i];
-        s_val[i] = val[e0 + base + i];
-      }
-      __syncthreads();
-      if (c < k)
-        for (int e = rsub; e < m; e += rpp) sum += s_val[e] * X[(size_t)s_col[e] * k + c];
-    }
-    s_red[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x < kp && c < k) {
-      T s = (T)0;
-      for (int g = 0; g < rpp; ++g) s += s_red[g * kp + c];
-      Y[(size_t)r0 * k + c] = s;
-    }
-  }
-}
-
-template <class T>
-hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
-  const int kp = pad_k(k);
-  const unsigned grid = (unsigned)(((A.nblk + 7) / 8) * 8);
-  const T* x = static_cast<const T*>(X);
-  T* y = static_cast<T*>(Y);
-  switch (kp) {
-#define SPMM_CASE(KP, KPL) \
-  case KP: hipLaunchKernelGGL((spmm_kernel<T, KPL>), dim3(grid), dim3(kBlock), 0, s, A, x, y, k, glob); break;
-    SPMM_CASE(1, 0)
-    SPMM_CASE(2, 1)
-    SPMM_CASE(4, 2)
-    SPMM_CASE(8, 3)
-    SPMM_CASE(16, 4)
-    SPMM_CASE(32, 5)
-    SPMM_CASE(64, 6)
-#undef SPMM_CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
-                       hipStream_t s) {
-  if (A.nblk <= 0) return hipSuccess;
-  return fp32 ? spmm_dispatch<float>(A, X, Y, k, glob, s) : spmm_dispatch<double>(A, X, Y, k, glob, s);
 }
 
 // ------------------------------------------------------- preconditioner ---

@@ -147,21 +147,22 @@ def test_trajectory_fixed_iterations(lib, variant, formulation, precond, k):
     hist = s.history()
     kw = dict(variant=variant, formulation=formulation, precond=precond, tol=0.0, maxit=nit, trace=True)
     ref = oracle.solve(A.to_scipy(), b, **kw)
-    alt = oracle_with_exact_dots(A.to_scipy(), b, **kw)
+    alts = [oracle_with_dots(o, A.to_scipy(), b, **kw) for o in DOT_ORDERS]
     assert np.all(info.status == oracle.MAXIT) and np.all(info.iters == nit)
     X = to_np(x)
+    keys = ((0, "alpha"), (1, "omega"), (2, "rho"))
     for c in range(k):
-        spread = np.linalg.norm(alt.x[:, c] - ref.x[:, c]) / np.linalg.norm(ref.x[:, c])
-        err = np.linalg.norm(X[:, c] - ref.x[:, c]) / np.linalg.norm(ref.x[:, c])
-        assert err < 1e-12 + 50 * spread, (c, err, spread)
-        tr, ta = ref.traces[c], alt.traces[c]
+        nref = np.linalg.norm(ref.x[:, c])
+        spread = max(np.linalg.norm(a.x[:, c] - ref.x[:, c]) / nref for a in alts)
+        err = np.linalg.norm(X[:, c] - ref.x[:, c]) / nref
+        assert err < 1e-12 + 20 * spread, (c, err, spread)
+        tr = ref.traces[c]
         env = 0.0  # running maximum of the relative summation-order spread
         for j in range(nit):
-            keys = ((0, "alpha"), (1, "omega"), (2, "rho"))
-            env = max([env] + [abs(ta[j][key] - tr[j][key]) / abs(tr[j][key]) for _, key in keys])
+            env = max([env] + [abs(a.traces[c][j][key] - tr[j][key]) / abs(tr[j][key]) for a in alts for _, key in keys])
             for idx, key in keys:
                 g, o = hist[j, c, idx], tr[j][key]
-                assert abs(g - o) <= (1e-12 + 50 * env) * abs(o), (c, j, key, g, o, env)
+                assert abs(g - o) <= (1e-12 + 20 * env) * abs(o), (c, j, key, g, o, env)
 
 
 # --------------------------------------------------------------- solves ---
