@@ -102,6 +102,46 @@ def roofline_of(solver, b, n, nnz, k, iters=10):
     return roof, kernels, it_summary
 
 
+def kernel_source_sha():
+    """Hash of the kernel sources; counter-derived traffic is reported only for
+    the source it was measured on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for fn in ("spmm.hip", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1907_12874_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, k):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
+    copy of known size), or None if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha") != kernel_source_sha() or d.get("k") != k:
+        return None
+    ent = d.get("kernels", {}).get(kernel)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def copy_probe():
+    """A plain 1 GiB device copy (torch), three times: the known-size kernel
+    that calibrates the HBM byte counters."""
+    import torch
+
+    x = torch.ones(2**27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def cpu_baseline(A, b, variant, formulation, precond, budget_s=15.0):
     """The oracle as it stands, one column, fixed passes, single thread."""
     import oracle
@@ -140,6 +180,8 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--sweep-k", default="1,2,4,8,16,32")
+    ap.add_argument("--maxit", type=int, default=5000, help="pass cap (lower it for profiled runs)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB copy first (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -156,6 +198,8 @@ def main():
     pk.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        copy_probe()
     t_gen = time.perf_counter()
     cfg = config_problem(1, seed=0, k=args.k, scale=args.grid)
     A = cfg["A"]
@@ -170,13 +214,13 @@ def main():
     s = pk.Solver.from_csr(A, k, variant=args.variant, formulation=args.formulation, precond=args.precond,
                            device=dev)
     for _ in range(args.warmup):
-        s.solve(b, x0, tol=args.tol, maxit=5000, out=x)
+        s.solve(b, x0, tol=args.tol, maxit=args.maxit, out=x)
     torch.cuda.synchronize()
     iters_total = 0
     infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, info = s.solve(b, x0, tol=args.tol, maxit=5000, out=x)
+        _, info = s.solve(b, x0, tol=args.tol, maxit=args.maxit, out=x)
         infos.append(info)
         iters_total += int(info.iters.sum())
     torch.cuda.synchronize()
@@ -219,6 +263,8 @@ def main():
 
     if not args.no_roofline:
         roof, kernels, it_summary = roofline_of(s, b, n, nnz, k)
+        roof["traffic"] = measured_traffic(roof["kernel"], k)
+        roof["source_sha"] = kernel_source_sha()
         out["roofline"] = roof
         out["kernels"] = kernels
         out["iteration"] = it_summary
@@ -249,7 +295,7 @@ def main():
                     tt = time.perf_counter() - ta
                     # solve to the tolerance: equal accuracy
                     ta = time.perf_counter()
-                    _, inf = sv.solve(bk, x0k, tol=args.tol, maxit=5000, out=xk)
+                    _, inf = sv.solve(bk, x0k, tol=args.tol, maxit=min(args.maxit, 2000), out=xk)
                     torch.cuda.synchronize()
                     ts = time.perf_counter() - ta
                     row = {"k": kk, "variant": variant, "formulation": form, "launches_per_iter": tr["launches"],
