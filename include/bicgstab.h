@@ -152,6 +152,11 @@ int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y);
  * Call with hist = NULL to get the count; cap = entries of 4 doubles. */
 int bicgstab_history(bicgstab_t h, double* hist, int32_t cap, int32_t* count);
 
+/* FP32-refinement handles: for each column, the number of FP64 residual
+ * corrections (inner FP32 solves) the last solve applied. outer: HOST array
+ * of length k. */
+int bicgstab_refine_outer(bicgstab_t h, int32_t* outer);
+
 /* Number of kernel launches and device-to-host polls of the last solve. */
 int bicgstab_last_solve_stats(bicgstab_t h, int32_t* iterations_enqueued, int32_t* launches, int32_t* polls);
 

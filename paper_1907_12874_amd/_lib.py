@@ -79,6 +79,7 @@ def lib():
     L.bicgstab_spmm.argtypes = [H, vp, vp]
     L.bicgstab_history.argtypes = [H, C.POINTER(dbl), i32, C.POINTER(i32)]
     L.bicgstab_last_solve_stats.argtypes = [H, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.bicgstab_refine_outer.argtypes = [H, C.POINTER(i32)]
     L.bicgstab_destroy.argtypes = [H]
     L.bicgstab_plan_traffic.argtypes = [i32, i32, i32] + [C.POINTER(i32)] * 5
     L.bicgstab_strerror.argtypes = [C.c_int]
@@ -114,4 +115,5 @@ def exported_symbols():
         "bicgstab_solve", "bicgstab_solve_transpose", "bicgstab_grad_values", "bicgstab_update_values",
         "bicgstab_spmm", "bicgstab_history", "bicgstab_last_solve_stats", "bicgstab_destroy",
         "bicgstab_plan_traffic", "bicgstab_strerror", "bicgstab_last_error", "bicgstab_kernel_times",
+        "bicgstab_refine_outer",
     ]

@@ -111,6 +111,7 @@ struct bicgstab_ctx {
   // statistics of the last solve
   int stat_iters = 0, stat_launches = 0, stat_polls = 0;
   int hist_count = 0;
+  std::vector<int> refine_outer;  // refinement tier: corrections applied per column
 };
 
 namespace {
@@ -403,6 +404,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
   std::vector<int> iters(k, 0), status(k, ST_RUNNING);
   std::vector<double> relres(k, 0.0), bnorm(k, 0.0);
   std::vector<double> scale(k, 0.0);
+  h->refine_outer.assign(k, 0);
   const SpmmMat M64 = mat_of(h, 0, false);
   double* R = (double*)h->ref[R_RES];
   double* D = (double*)h->ref[R_D];
@@ -469,7 +471,10 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     HIPCHK(hipMemcpyAsync(h->h_ist, h->ist, (size_t)I_NINT * kMaxK * 4, hipMemcpyDeviceToHost, h->ws));
     HIPCHK(hipStreamSynchronize(h->ws));
     for (int c = 0; c < k; ++c)
-      if (scale[c] > 0) iters[c] += h->h_ist[I_ITERS * kMaxK + c];
+      if (scale[c] > 0) {
+        iters[c] += h->h_ist[I_ITERS * kMaxK + c];
+        h->refine_outer[c] += 1;
+      }
     // x += ||r_c|| d (the inner solve does not touch S_SCALE)
     {
       const void* in[7] = {x, D};
@@ -712,6 +717,12 @@ int bicgstab_history(bicgstab_t h, double* hist, int32_t cap, int32_t* count) {
   const int rows = std::min<int>(h->hist_count, cap / std::max(1, h->k));
   HIPCHK(hipMemcpy(hist, h->hist, (size_t)rows * h->k * 4 * 8, hipMemcpyDeviceToHost));
   if (count) *count = rows;
+  return BICGSTAB_OK;
+}
+
+int bicgstab_refine_outer(bicgstab_t h, int32_t* outer) {
+  if (!h || !outer) return fail(BICGSTAB_EINVAL, "null argument");
+  for (int c = 0; c < h->k; ++c) outer[c] = c < (int)h->refine_outer.size() ? h->refine_outer[c] : 0;
   return BICGSTAB_OK;
 }
 

@@ -60,13 +60,18 @@ enum Part { PART_RUN = 0, PART_ALL = 1, PART_ZEROB = 2 };
   static constexpr unsigned XIN = XI, XOUT = XO;         \
   static constexpr int PART = PT;                        \
   static constexpr bool EARLY = EARLY_;
+// Op bodies compute in FP64 from operands of storage type T; a value that is
+// both stored and used again in the same op is first rounded to T (R(.)), so
+// dots and later terms see exactly the stored vector (a no-op when T is FP64).
 #define OP_F                                                                                  \
+  template <class T>                                                                          \
   __device__ __forceinline__ static void f(const double* v, const Coef& c, double* o, double* a)
+#define R(x) ((double)(T)(x))
 
 struct KInit {  // r = b - z; r0 = r; (r, r), (b, b)
   OP_HEAD(2, 2, 2, 0, 0, PART_RUN, true)
   OP_F {
-    double r = v[0] - v[1];
+    double r = R(v[0] - v[1]);
     o[0] = r;
     o[1] = r;
     a[0] += r * r;
@@ -140,7 +145,7 @@ struct KCXrRho {  // in: x, p, s, t, r0 ; out: x, r
   OP_HEAD(5, 2, 1, 1, 1, PART_RUN, true)
   OP_F {
     o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
-    double r = v[2] - c.omega * v[3];
+    double r = R(v[2] - c.omega * v[3]);
     o[1] = r;
     a[0] += r * v[4];
   }
@@ -148,7 +153,7 @@ struct KCXrRho {  // in: x, p, s, t, r0 ; out: x, r
 struct KCRRho {  // in: s, t, r0 ; out: r
   OP_HEAD(3, 1, 1, 0, 0, PART_RUN, true)
   OP_F {
-    double r = v[0] - c.omega * v[1];
+    double r = R(v[0] - c.omega * v[1]);
     o[0] = r;
     a[0] += r * v[2];
   }
@@ -156,7 +161,7 @@ struct KCRRho {  // in: s, t, r0 ; out: r
 struct KRG3 {  // in: r, v, t, r0 ; out: rt ; (t, rt), (t, t), (t, r0), (rt, rt)
   OP_HEAD(4, 1, 4, 0, 0, PART_RUN, true)
   OP_F {
-    double rt = v[0] - c.alpha * v[1];
+    double rt = R(v[0] - c.alpha * v[1]);
     o[0] = rt;
     a[0] += v[2] * rt;
     a[1] += v[2] * v[2];
@@ -168,7 +173,7 @@ struct KRXzv {  // in: x, vh, th, q, s ; out: x, z, vh
   OP_HEAD(5, 3, 0, 1, 1, PART_RUN, true)
   OP_F {
     o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
-    double z = v[2] - c.omega * v[3];
+    double z = R(v[2] - c.omega * v[3]);
     o[1] = z;
     o[2] = z + c.beta * (v[1] - c.omega * v[4]);
   }
@@ -176,11 +181,11 @@ struct KRXzv {  // in: x, vh, th, q, s ; out: x, z, vh
 struct KPG1 {  // in: r, p, s, w, z, t, v ; out: p, s, z, q, y ; (q, y), (y, y), (q, q)
   OP_HEAD(7, 5, 3, 0, 0, PART_RUN, true)
   OP_F {
-    double p = v[0] + c.beta * (v[1] - c.omega * v[2]);
-    double s = v[3] + c.beta * (v[2] - c.omega * v[4]);
-    double z = v[5] + c.beta * (v[4] - c.omega * v[6]);
-    double q = v[0] - c.alpha * s;
-    double y = v[3] - c.alpha * z;
+    double p = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
+    double s = R(v[3] + c.beta * (v[2] - c.omega * v[4]));
+    double z = R(v[5] + c.beta * (v[4] - c.omega * v[6]));
+    double q = R(v[0] - c.alpha * s);
+    double y = R(v[3] - c.alpha * z);
     o[0] = p;
     o[1] = s;
     o[2] = z;
@@ -201,7 +206,7 @@ struct KPG2 {  // in: x, p, q, y ; out: x, r
 struct KPG3 {  // in: y, t, v, r0, r, z, s ; out: w ; (r0,r), (r0,z), (r0,w), (r0,s)
   OP_HEAD(7, 1, 4, 0, 0, PART_RUN, true)
   OP_F {
-    double w = v[0] - c.omega * (v[1] - c.alpha * v[2]);
+    double w = R(v[0] - c.omega * (v[1] - c.alpha * v[2]));
     o[0] = w;
     a[0] += v[3] * v[4];
     a[1] += v[3] * v[5];
@@ -212,8 +217,8 @@ struct KPG3 {  // in: y, t, v, r0, r, z, s ; out: w ; (r0,r), (r0,z), (r0,w), (r
 struct KPPG1 {  // in: rh, ph, sh, wh, zh ; out: ph, sh, qh
   OP_HEAD(5, 3, 0, 0, 0, PART_RUN, true)
   OP_F {
-    double ph = v[0] + c.beta * (v[1] - c.omega * v[2]);
-    double sh = v[3] + c.beta * (v[2] - c.omega * v[4]);
+    double ph = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
+    double sh = R(v[3] + c.beta * (v[2] - c.omega * v[4]));
     o[0] = ph;
     o[1] = sh;
     o[2] = v[0] - c.alpha * sh;
@@ -222,10 +227,10 @@ struct KPPG1 {  // in: rh, ph, sh, wh, zh ; out: ph, sh, qh
 struct KPPG2 {  // in: w, s, z, t, v, r ; out: s, z, q, y ; (q, y), (y, y), (q, q)
   OP_HEAD(6, 4, 3, 0, 0, PART_RUN, true)
   OP_F {
-    double s = v[0] + c.beta * (v[1] - c.omega * v[2]);
-    double z = v[3] + c.beta * (v[2] - c.omega * v[4]);
-    double q = v[5] - c.alpha * s;
-    double y = v[0] - c.alpha * z;
+    double s = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
+    double z = R(v[3] + c.beta * (v[2] - c.omega * v[4]));
+    double q = R(v[5] - c.alpha * s);
+    double y = R(v[0] - c.alpha * z);
     o[0] = s;
     o[1] = z;
     o[2] = q;
@@ -245,8 +250,8 @@ struct KPPG3 {  // in: x, ph, qh, wh, zh ; out: x, rh
 struct KPPG4 {  // in: q, y, t, v, r0, z, s ; out: r, w ; (r0,r), (r0,z), (r0,w), (r0,s)
   OP_HEAD(7, 2, 4, 0, 0, PART_RUN, true)
   OP_F {
-    double r = v[0] - c.omega * v[1];
-    double w = v[1] - c.omega * (v[2] - c.alpha * v[3]);
+    double r = R(v[0] - c.omega * v[1]);
+    double w = R(v[1] - c.omega * (v[2] - c.alpha * v[3]));
     o[0] = r;
     o[1] = w;
     a[0] += v[4] * r;
@@ -680,7 +685,7 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
       for (int u = 0; u < U; ++u) {
         const size_t e = (size_t)(row + u * stride) * k + c;
         double o[NO];
-        Op::f(v[u], cf, o, acc);
+        Op::template f<T>(v[u], cf, o, acc);
 #pragma unroll
         for (int j = 0; j < Op::NOUT; ++j) {
           if ((Op::XOUT >> j) & 1)
@@ -696,7 +701,7 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
 #pragma unroll
       for (int i = 0; i < Op::NIN; ++i) v1[i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
       double o[NO];
-      Op::f(v1, cf, o, acc);
+      Op::template f<T>(v1, cf, o, acc);
 #pragma unroll
       for (int j = 0; j < Op::NOUT; ++j) {
         if ((Op::XOUT >> j) & 1)

@@ -168,6 +168,12 @@ class Solver:
               "bicgstab_history")
         return buf[: cnt.value * self.k * 4].reshape(cnt.value, self.k, 4)
 
+    def refine_outer(self):
+        """FP32-refinement handles: FP64 corrections applied per column."""
+        out = np.zeros(self.k, np.int32)
+        check(lib().bicgstab_refine_outer(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))), "bicgstab_refine_outer")
+        return out
+
     def stats(self):
         a, b_, c = C.c_int32(), C.c_int32(), C.c_int32()
         check(lib().bicgstab_last_solve_stats(self._h, C.byref(a), C.byref(b_), C.byref(c)), "stats")

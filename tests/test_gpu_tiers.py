@@ -1,0 +1,232 @@
+"""GPU tests of the precision tier (FP32 inner solves + FP64 refinement) and
+the differentiation tier (adjoint solve with A^T, pattern-restricted
+gradient, torch.autograd chaining), against the CPU oracle, dense autograd
+and finite differences."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint as oad
+from oracle import refine as orf
+from workloads import conv_diff, manufactured_rhs, random_27pt
+from workloads import generators as wg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------- precision ---
+
+@pytest.mark.parametrize("variant,precond", [("classical", "none"), ("classical", "jacobi"), ("pipelined", "none"),
+                                             ("reordered", "jacobi")])
+def test_precision_tier_matches_refinement_oracle(lib, variant, precond):
+    """27-point random matrix (the precision-tier recipe at 20^3), k = 8,
+    tol 1e-10: every column converges in FP64 terms, the number of FP64
+    corrections matches the NumPy FP32-refinement oracle within 1, and the
+    error against a tight FP64 solve is within the conditioning bound."""
+    import torch
+
+    say(f"precision tier {variant}/{precond}")
+    A = random_27pt(20, seed=3)
+    S = A.to_scipy()
+    b, xs = manufactured_rhs(A, 8, seed=4)
+    s = lib.Solver.from_csr(A, 8, variant=variant, formulation="merged", precond=precond, precision="fp32_refine")
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=5000)
+    X = x.cpu().numpy()
+    outer = s.refine_outer()
+    assert np.all(info.status == 0), info.status
+    rt = np.linalg.norm(b - S @ X, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rt < 1e-10) and np.allclose(rt, info.relres_true, rtol=1e-6)
+    tight = oracle.solve(S, b, tol=1e-13, maxit=5000)
+    nt = np.linalg.norm(tight.x, axis=0)
+    err = np.linalg.norm(X - tight.x, axis=0) / nt
+    # equal accuracy: the FP64 solve to the same tolerance on the same GPU
+    s64 = lib.Solver.from_csr(A, 8, variant=variant, formulation="merged", precond=precond)
+    x64, info64 = s64.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=5000)
+    err64 = np.linalg.norm(x64.cpu().numpy() - tight.x, axis=0) / nt
+    say(f"  outer {list(outer)}, max rel error vs FP64 tight solve {err.max():.2e} (FP64 solve at the same tol "
+        f"{err64.max():.2e})")
+    assert np.all(err <= 5 * err64 + 1e-10), (err, err64)
+    # refined further, the solution error itself falls below 1e-10
+    x12, info12 = s.solve(torch.from_numpy(b).cuda(), tol=1e-12, maxit=5000)
+    err12 = np.linalg.norm(x12.cpu().numpy() - tight.x, axis=0) / nt
+    say(f"  refined to 1e-12: outer {list(s.refine_outer())}, max rel error {err12.max():.2e}")
+    assert np.all(info12.status == 0) and np.all(err12 < 1e-10)
+    if variant == "classical":
+        for c in range(8):
+            ref = orf.refine_solve(S, b[:, c], tol=1e-10, inner_tol=1e-5, precond=precond)
+            assert ref["status"] == oracle.CONVERGED
+            assert abs(int(outer[c]) - ref["outer"]) <= 1, (c, outer[c], ref["outer"])
+
+
+def test_precision_tier_edge_columns(lib):
+    import torch
+
+    say("precision tier edges")
+    A = conv_diff(8, 3, (1.0, 0.7, 0.3))
+    n = A.n
+    b, _ = manufactured_rhs(A, 3, seed=5)
+    b[:, 1] = 0.0
+    s = lib.Solver.from_csr(A, 3, precision="fp32_refine")
+    x0 = torch.ones(n, 3, dtype=torch.float64).cuda()
+    x, info = s.solve(torch.from_numpy(b).cuda(), x0, tol=1e-10, maxit=2000)
+    X = x.cpu().numpy()
+    assert list(info.status) == [0, 0, 0]
+    assert np.all(X[:, 1] == 0)
+    assert np.all(info.relres_true[[0, 2]] < 1e-10)
+
+
+# --------------------------------------------------------- differentiation ---
+
+def test_grad_values_kernel(lib):
+    """The SDDMM kernel against the pattern-gradient definition."""
+    import torch
+
+    say("grad_values kernel")
+    A = conv_diff(11, 3, (1.0, -0.5, 0.25))
+    for k in (1, 3, 8, 32):
+        rng = np.random.default_rng(k)
+        lam = rng.uniform(-1, 1, (A.n, k))
+        X = rng.uniform(-1, 1, (A.n, k))
+        s = lib.Solver.from_csr(A, k)
+        g = s.grad_values(torch.from_numpy(lam).cuda(), torch.from_numpy(X).cuda()).cpu().numpy()
+        ref = oad.pattern_grad(A.to_scipy(), lam, X)
+        scale = np.abs(lam)[A.row_of_entry()].sum(axis=1) * 1.0 + 1e-300
+        assert np.all(np.abs(g - ref) <= 16 * np.finfo(float).eps * scale * max(1, k))
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_transpose_solve(lib, precond):
+    """A^T Lambda = G by the same method on the device-built transposed CSR
+    (nonsymmetric matrix, so A vs A^T matters)."""
+    import torch
+
+    say(f"transpose solve {precond}")
+    A = conv_diff(14, 3, (3.0, -2.0, 1.5))
+    St = A.to_scipy().T.tocsr()
+    G = np.random.default_rng(11).uniform(-1, 1, (A.n, 4))
+    s = lib.Solver.from_csr(A, 4, precond=precond)
+    lam, info = s.solve_transpose(torch.from_numpy(G).cuda(), tol=1e-12, maxit=3000)
+    L = lam.cpu().numpy()
+    assert np.all(info.status == 0)
+    rt = np.linalg.norm(G - St @ L, axis=0) / np.linalg.norm(G, axis=0)
+    assert np.all(rt < 1.1e-12)
+    ref = np.linalg.solve(St.toarray(), G)
+    assert np.linalg.norm(L - ref) / np.linalg.norm(ref) < 1e-9
+
+
+def _dense_grad_field(A, assemble, field, B):
+    import torch
+
+    rows = torch.as_tensor(A.row_of_entry())
+    cols = torch.as_tensor(A.col_idx.astype(np.int64))
+    ft = torch.tensor(field, dtype=torch.float64, requires_grad=True)
+    vals = assemble(ft)
+    Ad = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((rows, cols), vals)
+    X = torch.linalg.solve(Ad, torch.as_tensor(B))
+    (X * X).sum().backward()
+    return ft.grad.numpy()
+
+
+def test_autograd_diffusion_12cubed(lib):
+    """The differentiation-tier recipe at 12^3 (k = 8): gradient of
+    sum ||x||^2 with respect to the log-conductivity field through the GPU
+    solve and adjoint, against torch autograd of a dense FP64 solve, and
+    against central differences of GPU solves."""
+    import torch
+
+    from paper_1907_12874_amd import autograd as pag
+
+    say("autograd 12^3")
+    g0 = 12
+    A, field = wg.diffusion_varcoef(g0, seed=0)
+    B = np.random.default_rng(7).uniform(-1, 1, (A.n, 8))
+    assemble = wg.diffusion_values_torch(A, g0)
+    s = lib.Solver.from_csr(A, 8)
+    ft = torch.tensor(field, dtype=torch.float64, device="cuda", requires_grad=True)
+    Bt = torch.from_numpy(B).cuda()
+    X = pag.solve(assemble(ft), Bt, s, tol=1e-13, maxit=3000)
+    (X * X).sum().backward()
+    grad = ft.grad.cpu().numpy()
+    ref = _dense_grad_field(A, assemble, field, B)
+    assert np.linalg.norm(grad - ref) / np.linalg.norm(ref) < 1e-8
+
+    def loss(fld):
+        with torch.no_grad():
+            Xl = pag.solve(assemble(torch.from_numpy(fld).cuda()), Bt, s, tol=1e-13, maxit=3000)
+            return float((Xl * Xl).sum())
+
+    # iterative solves at 1e-13 leave ~1e-10 relative noise in the loss, so the
+    # step is 1e-4 (central-difference truncation ~1e-8) and the bar 2e-5
+    rng = np.random.default_rng(12)
+    h = 1e-4
+    for _ in range(3):
+        d = rng.standard_normal(A.n)
+        fd = (loss(field + h * d) - loss(field - h * d)) / (2 * h)
+        an = grad @ d
+        assert abs(fd - an) <= 2e-5 * abs(an), (fd, an)
+
+
+def test_autograd_nonsymmetric_values_and_b(lib):
+    """Nonsymmetric matrix: gradients with respect to the stored values and
+    to B against dense autograd (catches A vs A^T mix-ups)."""
+    import torch
+
+    from paper_1907_12874_amd import autograd as pag
+
+    say("autograd nonsymmetric")
+    A = conv_diff(6, 3, (3.0, -2.0, 1.5))
+    B = np.random.default_rng(13).uniform(-1, 1, (A.n, 3))
+    s = lib.Solver.from_csr(A, 3)
+    v = torch.tensor(A.values, dtype=torch.float64, device="cuda", requires_grad=True)
+    Bt = torch.tensor(B, dtype=torch.float64, device="cuda", requires_grad=True)
+    X = pag.solve(v, Bt, s, tol=1e-13, maxit=3000)
+    w = torch.linspace(-1, 1, X.numel(), dtype=torch.float64, device="cuda").view_as(X)
+    ((X * X).sum() + (w * X).sum()).backward()
+    rows = torch.as_tensor(A.row_of_entry())
+    cols = torch.as_tensor(A.col_idx.astype(np.int64))
+    vc = torch.tensor(A.values, dtype=torch.float64, requires_grad=True)
+    Bc = torch.tensor(B, dtype=torch.float64, requires_grad=True)
+    Ad = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((rows, cols), vc)
+    Xc = torch.linalg.solve(Ad, Bc)
+    ((Xc * Xc).sum() + (w.cpu() * Xc).sum()).backward()
+    gv, gb = v.grad.cpu().numpy(), Bt.grad.cpu().numpy()
+    assert np.linalg.norm(gv - vc.grad.numpy()) / np.linalg.norm(vc.grad.numpy()) < 1e-9
+    assert np.linalg.norm(gb - Bc.grad.numpy()) / np.linalg.norm(Bc.grad.numpy()) < 1e-9
+
+
+def test_autograd_full_size_64cubed(lib):
+    """The 64^3 diffusion workload, k = 8: forward and backward converge and
+    the directional derivative of the loss along a random field direction
+    matches a central difference of GPU solves."""
+    import torch
+
+    from paper_1907_12874_amd import autograd as pag
+
+    say("autograd 64^3")
+    cfg = wg.config_problem(4, seed=0)
+    A, field, B = cfg["A"], cfg["field"], cfg["b"]
+    assemble = wg.diffusion_values_torch(A, cfg["g"])
+    s = lib.Solver.from_csr(A, 8)
+    Bt = torch.from_numpy(B).cuda()
+    ft = torch.tensor(field, dtype=torch.float64, device="cuda", requires_grad=True)
+    X = pag.solve(assemble(ft), Bt, s, tol=1e-12, maxit=5000)
+    (X * X).sum().backward()
+    grad = ft.grad.cpu().numpy()
+    d = np.random.default_rng(14).standard_normal(A.n)
+    h = 1e-4
+
+    def loss(fld):
+        with torch.no_grad():
+            Xl = pag.solve(assemble(torch.from_numpy(fld).cuda()), Bt, s, tol=1e-12, maxit=5000)
+            return float((Xl * Xl).sum())
+
+    fd = (loss(field + h * d) - loss(field - h * d)) / (2 * h)
+    an = grad @ d
+    assert abs(fd - an) <= 1e-4 * abs(an), (fd, an)
