@@ -172,6 +172,77 @@ int bicgstab_kernel_times(bicgstab_t h, const double* d_b, double* d_x, int32_t 
 
 int bicgstab_destroy(bicgstab_t h);
 
+/* ---- Batched tier ----------------------------------------------------------
+ * Many independent systems A_s X_s = B_s, s = 0..nsys-1, each with its own
+ * CSR matrix (sizes may differ widely) and k_s right-hand sides, solved by one
+ * persistent kernel in one captured graph launch. Every system runs the
+ * merged classical BiCGStab without preconditioner (Appendix B, Alg. 2) on
+ * its own share of workgroups, with a barrier per system between the phases
+ * of an iteration; the per-column scalars, stop test and statuses are those of
+ * bicgstab_solve. The batched method is not in the paper: the paper treats
+ * one system with several right-hand sides.
+ *
+ * The kernel variant (threads per workgroup, rows a thread handles per step
+ * of a vector phase, entries per step of a row product; see
+ * bicgstab_batched_variant_info) and each system's share of workgroups come
+ * from the handle's configuration: a starting guess at create, replaced by
+ * bicgstab_batched_tune (timed trials on the caller's batch) or by
+ * bicgstab_batched_set_config (e.g. a configuration saved from an earlier
+ * tune). All workgroups of the launch must be resident on the device at once;
+ * a grid beyond the variant's occupancy limit is rejected with
+ * BICGSTAB_EUNSUPPORTED. A barrier that waits longer than 2 s aborts the whole
+ * launch (every workgroup exits) and the solve returns BICGSTAB_EHIP.
+ *
+ * Per system, each dot product is summed in a fixed order: per thread over its
+ * rows (a stride of block / kp rows through the workgroup's contiguous chunk of
+ * ceil(n / share) rows, kp = k rounded up to a power of two), a pairwise tree
+ * over the row slots of a 64-wide wavefront, the wavefronts in index order,
+ * then the workgroups in index order. Results depend on the block size and the
+ * shares, not on the other variant parameters, and repeat bit for bit. */
+typedef struct bicgstab_batched_ctx* bicgstab_batched_t;
+
+/* As[s]: the matrix of system s (n >= 1; pattern validated on the host, the
+ * arrays must outlive the handle); ks[s] in [1, BICGSTAB_MAX_K]. nsys >= 1. */
+int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, void* stream,
+                            bicgstab_batched_t* out);
+/* Device workspace in bytes: six n_s x k_s Krylov blocks per system, the
+ * reduction partials, barrier counters, descriptors and results. */
+int bicgstab_batched_workspace_bytes(bicgstab_batched_t h, size_t* bytes);
+/* Caller-owned workspace (256-byte aligned, at least the size above); without
+ * it the handle allocates its own at the first solve. */
+int bicgstab_batched_set_workspace(bicgstab_batched_t h, void* d_ptr, size_t bytes);
+int bicgstab_batched_set_stream(bicgstab_batched_t h, void* stream);
+/* d_b, d_x: HOST arrays of nsys DEVICE pointers; d_b[s], d_x[s] are n_s x k_s
+ * row-major (x: initial guess in, solution out). tol, maxit as in
+ * bicgstab_solve. info (may be NULL): host arrays of length sum_s k_s, the
+ * columns of system 0 first. Synchronous. */
+int bicgstab_batched_solve(bicgstab_batched_t h, const double* const* d_b, double* const* d_x, double tol,
+                           int32_t maxit, bicgstab_info* info);
+/* Autotuner: times the batch under every kernel variant at its full resident
+ * capacity, then the best variant at half and a quarter of it; for each, the
+ * shares are first proportional to measured work (bytes per pass x passes)
+ * and then twice re-derived from a per-system time model fitted to the run
+ * before (passes x (latency + bytes / (share x per-workgroup bandwidth)),
+ * least squares; the smallest makespan whose shares fit the budget). Keeps
+ * the fastest configuration. d_x holds the initial guesses on input (restored
+ * before every trial) and the solution of the chosen configuration on output.
+ * best_ms: that configuration's kernel time (may be NULL). */
+int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double* const* d_x, double tol,
+                          int32_t maxit, double* best_ms);
+/* Current configuration and the last solve's timings: variant, its threads per
+ * workgroup (block), workgroups[s] = share of system s, last_ms = kernel time,
+ * system_ms[s] = device wall time of system s (any pointer may be NULL; arrays
+ * of length nsys). */
+int bicgstab_batched_get_config(bicgstab_batched_t h, int32_t* variant, int32_t* block, int32_t* workgroups,
+                                double* last_ms, double* system_ms);
+/* Set the configuration (a variant index, workgroups[s] >= 1). */
+int bicgstab_batched_set_config(bicgstab_batched_t h, int32_t variant, const int32_t* workgroups);
+/* Host-only: parameters of kernel variant `variant` (0-based; an error past
+ * the last one). */
+int bicgstab_batched_variant_info(int32_t variant, int32_t* block, int32_t* rows_per_step,
+                                  int32_t* entries_per_step);
+int bicgstab_batched_destroy(bicgstab_batched_t h);
+
 /* Host-only query of the launch plan of one iteration (no device needed):
  * vector block reads and writes of its vector-operation passes (the counting
  * of Table 2), preconditioner applications, sparse products and kernel

@@ -5,6 +5,8 @@ The compute path is the in-tree libbicgstab.so; there is no CPU fallback.
 """
 from ._lib import BicgstabError, lib  # noqa: F401
 from .solver import Solver, SolveInfo, plan_traffic  # noqa: F401
+from . import batched  # noqa: F401
+from .batched import BatchedSolver  # noqa: F401
 
 
 def load():

@@ -34,18 +34,6 @@ class Info(C.Structure):
     ]
 
 
-class BatchedDesc(C.Structure):
-    _fields_ = [
-        ("nsys", C.c_int32),
-        ("n", C.POINTER(C.c_int64)),
-        ("nnz", C.POINTER(C.c_int64)),
-        ("k", C.POINTER(C.c_int32)),
-        ("d_row_ptr", C.POINTER(C.c_void_p)),
-        ("d_col_idx", C.POINTER(C.c_void_p)),
-        ("d_values", C.POINTER(C.c_void_p)),
-    ]
-
-
 _lib = None
 
 
@@ -86,18 +74,18 @@ def lib():
     L.bicgstab_strerror.restype = C.c_char_p
     L.bicgstab_last_error.argtypes = []
     L.bicgstab_last_error.restype = C.c_char_p
-    if hasattr(L, "bicgstab_kernel_times"):
-        L.bicgstab_kernel_times.argtypes = [H, vp, vp, i32, i32] + [C.POINTER(i32)] * 4 + [C.POINTER(dbl), C.POINTER(i32)]
-    if hasattr(L, "bicgstab_batched_create"):
-        L.bicgstab_batched_create.argtypes = [C.POINTER(BatchedDesc), i32, vp, C.POINTER(H)]
-        L.bicgstab_batched_workspace_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
-        L.bicgstab_batched_set_workspace.argtypes = [H, vp, C.c_size_t]
-        L.bicgstab_batched_set_stream.argtypes = [H, vp]
-        L.bicgstab_batched_solve.argtypes = [H, C.POINTER(vp), C.POINTER(vp), dbl, i32, C.POINTER(i32),
-                                             C.POINTER(i32), C.POINTER(dbl)]
-        L.bicgstab_batched_destroy.argtypes = [H]
-        if hasattr(L, "bicgstab_batched_tune"):
-            L.bicgstab_batched_tune.argtypes = [H, C.POINTER(vp), C.POINTER(vp), dbl, i32, C.POINTER(dbl)]
+    L.bicgstab_kernel_times.argtypes = [H, vp, vp, i32, i32] + [C.POINTER(i32)] * 4 + [C.POINTER(dbl), C.POINTER(i32)]
+    L.bicgstab_batched_create.argtypes = [C.POINTER(CSRDesc), C.POINTER(i32), i32, vp, C.POINTER(H)]
+    L.bicgstab_batched_workspace_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
+    L.bicgstab_batched_set_workspace.argtypes = [H, vp, C.c_size_t]
+    L.bicgstab_batched_set_stream.argtypes = [H, vp]
+    L.bicgstab_batched_solve.argtypes = [H, C.POINTER(vp), C.POINTER(vp), dbl, i32, C.POINTER(Info)]
+    L.bicgstab_batched_tune.argtypes = [H, C.POINTER(vp), C.POINTER(vp), dbl, i32, C.POINTER(dbl)]
+    L.bicgstab_batched_get_config.argtypes = [H, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl),
+                                              C.POINTER(dbl)]
+    L.bicgstab_batched_variant_info.argtypes = [i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.bicgstab_batched_set_config.argtypes = [H, i32, C.POINTER(i32)]
+    L.bicgstab_batched_destroy.argtypes = [H]
     _lib = L
     return L
 
@@ -115,5 +103,8 @@ def exported_symbols():
         "bicgstab_solve", "bicgstab_solve_transpose", "bicgstab_grad_values", "bicgstab_update_values",
         "bicgstab_spmm", "bicgstab_history", "bicgstab_last_solve_stats", "bicgstab_destroy",
         "bicgstab_plan_traffic", "bicgstab_strerror", "bicgstab_last_error", "bicgstab_kernel_times",
-        "bicgstab_refine_outer",
+        "bicgstab_refine_outer", "bicgstab_batched_create", "bicgstab_batched_workspace_bytes",
+        "bicgstab_batched_set_workspace", "bicgstab_batched_set_stream", "bicgstab_batched_solve",
+        "bicgstab_batched_tune", "bicgstab_batched_get_config", "bicgstab_batched_set_config",
+        "bicgstab_batched_variant_info", "bicgstab_batched_destroy",
     ]

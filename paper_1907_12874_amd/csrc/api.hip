@@ -26,6 +26,14 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace bcg {
+int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace bcg
+
+namespace {
+
 #define HIPCHK(expr)                                                                        \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
@@ -86,7 +94,6 @@ struct bicgstab_ctx {
   double* sc = nullptr;
   int* ist = nullptr;
   Globals* glob = nullptr;
-  unsigned* counter = nullptr;
   double* hist = nullptr;
   int hist_cap = 0;
   GridCaps caps{512, 512};  // workgroup caps: streaming passes, passes with dots
@@ -146,7 +153,6 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
   const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
   const size_t o_glob = take(sizeof(Globals));
-  const size_t o_cnt = take(64);
   const size_t o_hist = take((size_t)h->hist_cap * h->k * 4 * 8);
   if (assign) {
     char* b = h->base;
@@ -162,7 +168,6 @@ size_t layout(bicgstab_ctx* h, bool assign) {
     h->sc = (double*)(b + o_sc);
     h->ist = (int*)(b + o_ist);
     h->glob = (Globals*)(b + o_glob);
-    h->counter = (unsigned*)(b + o_cnt);
     h->hist = h->hist_cap > 0 ? (double*)(b + o_hist) : nullptr;
   }
   return off;
@@ -174,7 +179,6 @@ Ctl make_ctl(bicgstab_ctx* h) {
   c.ist = h->ist;
   c.glob = h->glob;
   c.partials = h->partials;
-  c.counter = h->counter;
   c.hist = h->hist;
   c.k = h->k;
   return c;

@@ -49,8 +49,9 @@ constexpr int ST_MAXIT = 1;
 constexpr int ST_BREAKDOWN = 2;
 constexpr int ST_NONFINITE = 3;
 
-// Finalize steps: the scalar recurrence run by the last workgroup of a
-// reduction (or of a dot-free kernel that closes an iteration).
+// Finalize steps: the scalar recurrence run by the one-workgroup finalize
+// kernel that follows a reduction pass (or a dot-free pass that closes an
+// iteration).
 enum FinStep {
   F_NONE = 0,
   F_INIT,           // D0=(r,r) D1=(b,b): eps^2, rho_0, early stops
@@ -74,7 +75,6 @@ struct Ctl {
   int* ist;
   Globals* glob;
   double* partials;
-  unsigned* counter;
   double* hist;
   int k;
 };
@@ -174,9 +174,9 @@ hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp3
                        hipStream_t s);
 hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
-// Workgroup-count caps: plain streaming passes (256 lanes per workgroup) and
-// passes with dot products (1024 lanes per workgroup). The dot cap also sizes
-// the reduction partials buffer.
+// Workgroup-count caps of the vector passes: plain streaming passes and passes
+// with dot products (both 256 lanes per workgroup). The dot cap also sizes the
+// reduction partials buffer.
 struct GridCaps {
   int blocks;
   int dot_blocks;
@@ -200,5 +200,9 @@ hipError_t launch_gather_values(const double* val, const int32_t* perm, double* 
 // Row-block partition for the CSR-stream SpMM (host).
 // rows_per_lane_override <= 0 picks the default for the width.
 SpmmPartition spmm_partition(const std::vector<int32_t>& row_ptr, int k, int rows_per_lane_override);
+
+// Records the message returned by bicgstab_last_error() on this thread and
+// returns code.
+int set_last_error(int code, const std::string& msg);
 
 }  // namespace bcg

@@ -838,7 +838,6 @@ __global__ void setup_state_kernel(Ctl C, double tol, int maxit, int hist_cap) {
     C.glob->maxit = maxit;
     C.glob->hist_cap = hist_cap;
     C.glob->tol = tol;
-    *C.counter = 0u;
   }
 }
 

@@ -1,0 +1,258 @@
+"""GPU tests of the batched tier (many independent systems in one persistent
+launch) against an oracle loop over the systems.
+
+The batched kernel forms every sparse product and vector update in the
+oracle's order without contraction, and sums each dot product in a fixed
+order that depends only on the system's size, k, its workgroup share and the
+workgroup size: per thread over its rows (a stride of block / kp rows through
+the workgroup's contiguous row chunk), a pairwise tree over the row slots of a
+wave, the waves in index order, then the workgroups in index order. The
+tests run the oracle with its dot product summed in that order
+(`kernel_order_dot`), which makes the whole solve reproducible bit for bit:
+pass counts, statuses and iterates must be identical. The same runs with the
+oracle's own dot products stay within the summation-order envelope (checked
+in the single-system tests).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.bicgstab as ob
+from workloads import CSR, batched_systems, config_problem, conv_diff, manufactured_rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def kernel_order_dot(n, k, nw, block):
+    """Dot product of two length-n vectors summed in the batched kernel's
+    order for a system of n rows, k columns, nw workgroups of `block` threads."""
+    kp = 1
+    while kp < k:
+        kp *= 2
+    rpp, R, waves = block // kp, 64 // kp, block // 64
+    chunk = (n + nw - 1) // nw
+    m = (chunk + rpp - 1) // rpp
+
+    def dot(u, w):
+        p = np.zeros(nw * chunk)
+        p[:n] = np.multiply(u, w)
+        q = np.zeros((nw, m * rpp))
+        q[:, :chunk] = p.reshape(nw, chunk)
+        acc = np.add.accumulate(q.reshape(nw, m, rpp), axis=1)[:, -1, :]  # per thread, rows in order
+        t = acc.reshape(nw, waves, R)
+        while t.shape[2] > 1:  # pairwise over the row slots of a wave
+            t = t[:, :, 0::2] + t[:, :, 1::2]
+        wg = np.add.accumulate(t[:, :, 0], axis=1)[:, -1]  # waves in order
+        return float(np.add.accumulate(wg)[-1])  # workgroups in order
+
+    return dot
+
+
+def oracle_kernel_order(A, k, nw, block, *args, **kw):
+    saved = ob.dot
+    ob.dot = kernel_order_dot(A.n, k, nw, block)
+    try:
+        return oracle.solve(A.to_scipy(), *args, **kw)
+    finally:
+        ob.dot = saved
+
+
+def _batch(nsys, seed, nmin=200, nmax=5000):
+    systems = batched_systems(nsys, seed, nmin=nmin, nmax=nmax)
+    rhs = [manufactured_rhs(A, k, seed * 1000 + s)[0] for s, (A, k) in enumerate(systems)]
+    return systems, rhs
+
+
+def _gpu_solve(lib, systems, rhs, tol, maxit, x0s=None, solver=None):
+    import torch
+
+    bs = lib.BatchedSolver(systems) if solver is None else solver
+    xs, infos = bs.solve([torch.from_numpy(b).cuda() for b in rhs],
+                         None if x0s is None else [torch.from_numpy(x).cuda() for x in x0s], tol=tol, maxit=maxit)
+    return bs, [x.cpu().numpy() for x in xs], infos
+
+
+def _check_bitwise(bs, systems, rhs, X, infos, tol, maxit, x0s=None, which=None):
+    """Per system: the oracle in the kernel's summation order gives the same
+    pass counts, statuses and iterates, bit for bit; the library's true
+    residual equals one recomputed on the host."""
+    cfg = bs.config()
+    block, wg = cfg.block, cfg.workgroups
+    for s in (range(len(systems)) if which is None else which):
+        A, k = systems[s]
+        b = rhs[s]
+        ref = oracle_kernel_order(A, k, int(wg[s]), block, b, None if x0s is None else x0s[s], tol=tol, maxit=maxit)
+        info = infos[s]
+        assert np.array_equal(info.status, ref.status), (s, info.status, ref.status)
+        assert np.array_equal(info.iters, ref.iters), (s, info.iters, ref.iters)
+        assert np.array_equal(X[s], ref.x), (s, np.abs(X[s] - ref.x).max())
+        nb = np.linalg.norm(b, axis=0)
+        rt = np.where(nb > 0, np.linalg.norm(b - A.to_scipy() @ X[s], axis=0) / np.where(nb > 0, nb, 1), 0.0)
+        assert np.allclose(info.relres_true, rt, rtol=1e-6, atol=1e-300), (s, info.relres_true, rt)
+
+
+def test_batched_fixed_passes_bitwise(lib):
+    """16 systems (2D 5-point and 3D 7-point, n in [200, 5000], k in 1..8),
+    12 passes with the stop test off."""
+    systems, rhs = _batch(16, seed=1)
+    say(f"batched fixed passes: {[(A.n, k) for A, k in systems]}")
+    bs, X, infos = _gpu_solve(lib, systems, rhs, tol=0.0, maxit=12)
+    for info in infos:
+        assert np.all(info.status == oracle.MAXIT) and np.all(info.iters == 12)
+    _check_bitwise(bs, systems, rhs, X, infos, 0.0, 12)
+
+
+def test_batched_converged_bitwise(lib):
+    """16 systems to tol 1e-8 with the starting configuration: every column
+    converges with a true residual <= 1.1 tol, bit for bit the oracle's."""
+    systems, rhs = _batch(16, seed=2)
+    say(f"batched converged: {[(A.n, k) for A, k in systems]}")
+    bs, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-8, maxit=3000)
+    say(f"  passes {[int(i.iters.max()) for i in infos]}")
+    for info in infos:
+        assert np.all(info.status == oracle.CONVERGED) and np.all(info.relres_true <= 1.1e-8)
+    _check_bitwise(bs, systems, rhs, X, infos, 1e-8, 3000)
+
+
+def test_batched_edges_bitwise(lib):
+    """Edge columns and systems: a zero right-hand side (solution 0), a column
+    whose initial guess is already the solution (0 passes), a 1 x 1 system, a
+    scaled identity (s = 0 after one pass: converged), and maxit = 0."""
+    A1 = conv_diff(9, 2, (0.6, -0.3))
+    b1, xs1 = manufactured_rhs(A1, 3, seed=3)
+    b1[:, 1] = 0.0
+    x01 = np.zeros_like(b1)
+    x01[:, 0] = 0.25
+    x01[:, 2] = xs1[:, 2]
+    A2 = CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    b2 = np.array([[2.0, -1.0]])
+    n3 = 50
+    A3 = CSR(n3, np.arange(n3 + 1, dtype=np.int32), np.arange(n3, dtype=np.int32), np.full(n3, 2.0))
+    b3 = np.random.default_rng(4).uniform(-1, 1, (n3, 2))
+    systems = [(A1, 3), (A2, 2), (A3, 2)]
+    rhs = [b1, b2, b3]
+    x0s = [x01, np.zeros_like(b2), np.zeros_like(b3)]
+    say("batched edges")
+    bs, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-10, maxit=500, x0s=x0s)
+    _check_bitwise(bs, systems, rhs, X, infos, 1e-10, 500, x0s=x0s)
+    assert np.all(X[0][:, 1] == 0) and list(infos[0].iters[1:]) == [0, 0]
+    assert list(infos[1].iters) == [1, 1] and list(infos[2].iters) == [1, 1]
+    assert np.all(infos[1].status == oracle.CONVERGED) and np.all(infos[2].status == oracle.CONVERGED)
+    # maxit = 0: running columns stop with MAXIT after 0 passes, x unchanged
+    bs0, X0, inf0 = _gpu_solve(lib, systems, rhs, tol=1e-10, maxit=0, x0s=x0s)
+    assert list(inf0[0].status) == [oracle.MAXIT, oracle.CONVERGED, oracle.CONVERGED]
+    assert np.array_equal(X0[0][:, [0, 2]], x01[:, [0, 2]])
+    _check_bitwise(bs0, systems, rhs, X0, inf0, 1e-10, 0, x0s=x0s)
+
+
+def test_batched_tuner_config_and_determinism(lib):
+    """The tuner returns a valid configuration whose solves are bitwise
+    reproducible and bitwise the oracle's in that configuration's summation
+    order; a hand-set configuration (one workgroup per system) too; invalid
+    configurations are rejected."""
+    import torch
+
+    systems, rhs = _batch(24, seed=5, nmin=500, nmax=30000)
+    say(f"batched tuner: {[(A.n, k) for A, k in systems]}")
+    bs = lib.BatchedSolver(systems)
+    btens = [torch.from_numpy(b).cuda() for b in rhs]
+    best, xt = bs.tune(btens, tol=1e-8, maxit=3000)
+    cfg = bs.config()
+    say(f"  best {best:.3f} ms, variant {cfg.variant} {lib.batched.variant_info(cfg.variant)}, "
+        f"workgroups {cfg.workgroups.tolist()}")
+    assert cfg.block in (256, 512) and np.all(cfg.workgroups >= 1) and best > 0
+    x1, i1 = bs.solve(btens, tol=1e-8, maxit=3000)
+    x2, i2 = bs.solve(btens, tol=1e-8, maxit=3000)
+    for s in range(len(systems)):
+        assert torch.equal(x1[s], x2[s]) and torch.equal(x1[s], xt[s]), s
+        assert np.array_equal(i1[s].iters, i2[s].iters)
+    X = [x.cpu().numpy() for x in x1]
+    small = sorted(range(len(systems)), key=lambda s: systems[s][0].n)[:6]
+    _check_bitwise(bs, systems, rhs, X, i1, 1e-8, 3000, which=small)
+    bs.set_config(0, [1] * len(systems))
+    _, Xh, ih = _gpu_solve(lib, systems, rhs, tol=1e-8, maxit=3000, solver=bs)
+    _check_bitwise(bs, systems, rhs, Xh, ih, 1e-8, 3000, which=small)
+    with pytest.raises(lib.BicgstabError):
+        bs.set_config(99, [1] * len(systems))
+    with pytest.raises(lib.BicgstabError):
+        bs.set_config(1, [100000] + [1] * (len(systems) - 1))
+    bs.close()
+
+
+def test_batched_variants_agree_bitwise(lib):
+    """The kernel variants of one block size sum in the same order: with the
+    same shares they return identical results, and each matches the oracle in
+    that order."""
+    from paper_1907_12874_amd.batched import variant_info
+
+    systems, rhs = _batch(10, seed=7)
+    bs = lib.BatchedSolver(systems)
+    shares = [max(1, min(A.n // 64, 3 + s)) for s, (A, _) in enumerate(systems)]
+    by_block = {}
+    v = 0
+    while True:
+        try:
+            block, rows, entries = variant_info(v)
+        except lib.BicgstabError:
+            break
+        say(f"variant {v}: block {block}, rows {rows}, entries {entries}")
+        bs.set_config(v, shares)
+        _, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-9, maxit=2000, solver=bs)
+        if block in by_block:
+            X0, i0 = by_block[block]
+            for s in range(len(systems)):
+                assert np.array_equal(X[s], X0[s]) and np.array_equal(infos[s].iters, i0[s].iters), (v, s)
+        else:
+            by_block[block] = (X, infos)
+            _check_bitwise(bs, systems, rhs, X, infos, 1e-9, 2000)
+        v += 1
+    assert v >= 2 and len(by_block) == 2
+    bs.close()
+
+
+def test_batched_rejects_bad_input(lib):
+    import torch
+
+    A = conv_diff(5, 2, (1.0, 0.5))
+    bad = CSR(A.n, A.row_ptr.copy(), A.col_idx.copy(), A.values.copy())
+    bad.col_idx[3] = A.n + 7
+    with pytest.raises(lib.BicgstabError):
+        lib.BatchedSolver([(A, 1), (bad, 1)])
+    bs = lib.BatchedSolver([(A, 2)])
+    with pytest.raises(ValueError):
+        bs.solve([torch.zeros(A.n, 3, dtype=torch.float64).cuda()])
+    with pytest.raises(ValueError):
+        bs.solve([torch.zeros(A.n, 2, dtype=torch.float64).cuda()] * 2)
+
+
+def test_batched_full_size_64_systems(lib):
+    """The batched workload at full size: 64 systems, n log-uniform in
+    [1e3, 2e5], k in 1..8, tol 1e-8, tuned. Every column converges with a
+    true residual <= 1.1 tol (recomputed on the host); the six smallest
+    systems are checked bit for bit against the oracle."""
+    import torch
+
+    cfg = config_problem(3, seed=0)
+    systems, rhs = cfg["systems"], [b for b, _ in cfg["rhs"]]
+    say(f"batched full size: {len(systems)} systems, n {min(A.n for A, _ in systems)}..{max(A.n for A, _ in systems)}")
+    bs = lib.BatchedSolver(systems)
+    btens = [torch.from_numpy(b).cuda() for b in rhs]
+    best, _ = bs.tune(btens, tol=1e-8, maxit=5000)
+    xs, infos = bs.solve(btens, tol=1e-8, maxit=5000)
+    say(f"  tuned kernel {best:.2f} ms, passes max {max(int(i.iters.max()) for i in infos)}")
+    X = [x.cpu().numpy() for x in xs]
+    for s, ((A, k), b) in enumerate(zip(systems, rhs)):
+        assert np.all(infos[s].status == oracle.CONVERGED), (s, infos[s].status)
+        rt = np.linalg.norm(b - A.to_scipy() @ X[s], axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(rt <= 1.1e-8), (s, rt)
+        assert np.allclose(infos[s].relres_true, rt, rtol=1e-6), s
+    small = sorted(range(len(systems)), key=lambda s: systems[s][0].n)[:6]
+    _check_bitwise(bs, systems, rhs, X, infos, 1e-8, 5000, which=small)
+    bs.close()
