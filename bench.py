@@ -18,7 +18,13 @@ The JSON line also carries:
                 passes) on the host;
   sweep         merged vs basic for every method at k = 1..32: fixed-pass
                 throughput (RHS-iterations/s, algorithmic GB/s) and solves to
-                the same tolerance (equal accuracy, checked per column).
+                the same tolerance (equal accuracy, checked per column);
+  tiers         precision (27-point random 100^3, k = 32: FP64 vs FP32 inner
+                solves + FP64 refinement at equal final accuracy), batched (64
+                systems of log-uniform size in one persistent launch, tuned,
+                vs a loop of single solves) and differentiation (64^3
+                variable-coefficient diffusion, k = 8: forward solve vs
+                forward + adjoint backward through torch.autograd).
 """
 from __future__ import annotations
 
@@ -164,6 +170,119 @@ def cpu_baseline(A, b, variant, formulation, precond, budget_s=15.0):
             "seconds": round(t, 2), "passes": m}
 
 
+def timed(fn, reps=1):
+    import torch
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps, r
+
+
+def tier_precision(pk, dev, maxit):
+    """FP64 vs FP32 + FP64 refinement on the 27-point random matrix, both to a
+    true relative residual of 1e-10; errors against the manufactured x*."""
+    import torch
+
+    from workloads import config_problem
+
+    cfg = config_problem(2, seed=0)
+    A, xs = cfg["A"], cfg["x_star"]
+    b = torch.from_numpy(cfg["b"]).to(dev)
+    xst = torch.from_numpy(xs).to(dev)
+    out = {"workload": f"27-point random 100^3, n={A.n}, nnz={A.nnz}, k={cfg['k']}, tol {cfg['tol']:g}"}
+    for prec in ("fp64", "fp32_refine"):
+        s = pk.Solver.from_csr(A, cfg["k"], precision=prec, device=dev)
+        s.solve(b, tol=cfg["tol"], maxit=maxit)
+        t, (x, info) = timed(lambda: s.solve(b, tol=cfg["tol"], maxit=maxit), reps=2)
+        err = float(((x - xst).norm(dim=0) / xst.norm(dim=0)).max())
+        row = {"ms": round(t * 1e3, 2), "all_converged": bool(np.all(info.status == 0)),
+               "relres_true_max": float(info.relres_true.max()), "err_vs_xstar_max": err,
+               "rhs_it_per_s": round(float(info.iters.sum()) / t, 1)}
+        if prec == "fp32_refine":
+            row["outer_corrections_max"] = int(s.refine_outer().max())
+            row["inner_passes_max"] = int(info.iters.max())
+        else:
+            row["passes_max"] = int(info.iters.max())
+        out[prec] = row
+        s.close()
+    out["speedup_fp32_refine"] = round(out["fp64"]["ms"] / out["fp32_refine"]["ms"], 3)
+    return out
+
+
+def tier_batched(pk, dev, maxit):
+    """64 systems in one persistent launch, tuned, vs a loop of single solves
+    (the classical merged single-system path, one system after another)."""
+    import torch
+
+    from workloads import config_problem
+
+    cfg = config_problem(3, seed=0)
+    systems = cfg["systems"]
+    bt = [torch.from_numpy(b).to(dev) for b, _ in cfg["rhs"]]
+    bs = pk.BatchedSolver(systems, device=dev)
+    t_tune, _ = timed(lambda: bs.tune(bt, tol=cfg["tol"], maxit=maxit))
+    t, (xs, infos) = timed(lambda: bs.solve(bt, tol=cfg["tol"], maxit=maxit), reps=2)
+    c = bs.config()
+    rhs_it = sum(int(i.iters.sum()) for i in infos)
+    conv = all(bool(np.all(i.status == 0)) for i in infos)
+    byts = 0.0
+    for (A, k), i in zip(systems, infos):
+        blk = 8.0 * A.n * k
+        byts += (2 * (12.0 * A.nnz + 4.0 * A.n + 2 * blk) + 18 * blk) * int(i.iters.max())
+    t_loop = 0.0
+    for (A, k), b in zip(systems, bt):
+        sv = pk.Solver.from_csr(A, k, device=dev)
+        sv.solve(b, tol=cfg["tol"], maxit=maxit)
+        tl, _ = timed(lambda: sv.solve(b, tol=cfg["tol"], maxit=maxit))
+        t_loop += tl
+        sv.close()
+    bs.close()
+    return {"workload": f"{len(systems)} conv-diff systems, n {min(A.n for A, _ in systems)}..{max(A.n for A, _ in systems)},"
+                        f" k 1..8 ({sum(k for _, k in systems)} columns), tol {cfg['tol']:g}",
+            "ms": round(t * 1e3, 2), "kernel_ms": round(c.last_ms, 2), "rhs_it_per_s": round(rhs_it / t, 1),
+            "all_converged": conv, "algorithmic_GBps": round(byts / t / 1e9, 1),
+            "variant": c.variant, "workgroups": int(c.workgroups.sum()), "tune_s": round(t_tune, 2),
+            "loop_of_single_solves_ms": round(t_loop * 1e3, 2), "speedup_vs_loop": round(t_loop / t, 3)}
+
+
+def tier_autograd(pk, dev, maxit):
+    """Forward solve vs forward + backward (adjoint solve with A^T and the
+    pattern gradient) through torch.autograd on the 64^3 diffusion problem."""
+    import torch
+
+    from paper_1907_12874_amd import autograd as pag
+    from workloads import config_problem
+    from workloads import generators as wg
+
+    cfg = config_problem(4, seed=0)
+    A = cfg["A"]
+    assemble = wg.diffusion_values_torch(A, cfg["g"])
+    s = pk.Solver.from_csr(A, cfg["k"], device=dev)
+    B = torch.from_numpy(cfg["b"]).to(dev)
+    field = torch.tensor(cfg["field"], dtype=torch.float64, device=dev)
+
+    def fwd():
+        with torch.no_grad():
+            return pag.solve(assemble(field), B, s, tol=cfg["tol"], maxit=maxit)
+
+    def fwd_bwd():
+        f = field.clone().requires_grad_(True)
+        X = pag.solve(assemble(f), B, s, tol=cfg["tol"], maxit=maxit)
+        (X * X).sum().backward()
+        return f.grad
+
+    fwd_bwd()
+    tf, _ = timed(fwd, reps=2)
+    tb, g = timed(fwd_bwd, reps=2)
+    s.close()
+    return {"workload": f"3D variable-coefficient diffusion 64^3, n={A.n}, k={cfg['k']}, tol {cfg['tol']:g}",
+            "forward_ms": round(tf * 1e3, 2), "forward_backward_ms": round(tb * 1e3, 2),
+            "backward_over_forward": round((tb - tf) / tf, 3), "grad_finite": bool(torch.isfinite(g).all())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +297,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--sweep-k", default="1,2,4,8,16,32")
     ap.add_argument("--maxit", type=int, default=5000, help="pass cap (lower it for profiled runs)")
@@ -322,6 +442,14 @@ def main():
                     mb = {r["formulation"]: r for r in m}
                     gains[f"{variant}_k{kk}"] = round(1 - mb["merged"]["fixed_ms_per_iter"] / mb["basic"]["fixed_ms_per_iter"], 4)
         out["merging_time_reduction"] = gains
+
+    # -------------------------------------------------------------- tiers
+    if not args.no_tiers:
+        tiers = {}
+        for name, fn in (("precision", tier_precision), ("batched", tier_batched), ("autograd", tier_autograd)):
+            tiers[name] = fn(pk, dev, args.maxit)
+            print(f"# tier {name}: {json.dumps(tiers[name])}", file=sys.stderr, flush=True)
+        out["tiers"] = tiers
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu:
