@@ -43,7 +43,7 @@ PEAK_HBM_GBPS = 8000.0
 OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
     "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g1", "pp_g2", "pp_g3", "pp_g4",
-    "ref_resid", "ref_scale", "ref_update",
+    "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h",
 ]
 
 
@@ -66,6 +66,8 @@ def step_bytes(step, n, nnz, k):
     blk = 8 * n * k
     if step["kind"] == "spmm":
         return spmm_bytes(n, nnz, k)
+    if step["kind"] == "spmm_dot":  # the product plus the epilogue's second operand
+        return spmm_bytes(n, nnz, k) + blk
     if step["kind"] == "prec":
         return 2 * blk + 8 * n
     return (step["nin"] + step["nout"]) * blk
@@ -74,6 +76,8 @@ def step_bytes(step, n, nnz, k):
 def kernel_name(step):
     if step["kind"] == "spmm":
         return "spmm_kernel"
+    if step["kind"] == "spmm_dot":
+        return "spmm_dot_kernel<" + ("dot_w", "ppt")[step["op"]] + ">"
     if step["kind"] == "prec":
         return "prec_kernel"
     return "group_kernel<" + OP_NAMES[step["op"]] + ">"
@@ -402,7 +406,7 @@ def main():
             x0k = torch.zeros_like(bk)
             xk = torch.empty_like(bk)
             for variant in ("classical", "reordered", "pipelined"):
-                for form in ("merged", "basic"):
+                for form in ("merged", "basic", "fused") if variant == "classical" else ("merged", "basic"):
                     sv = pk.Solver.from_csr(A, kk, variant=variant, formulation=form, precond=args.precond, device=dev)
                     tr = pk.plan_traffic(variant, form, args.precond)
                     ib = iteration_bytes(n, nnz, kk, tr)
@@ -434,14 +438,17 @@ def main():
                     sv.close()
                     del sv
         out["sweep"] = sweep
-        gains = {}
+        gains, fusion = {}, {}
         for kk in ks:
             for variant in ("classical", "reordered", "pipelined"):
                 m = [r for r in sweep if r["k"] == kk and r["variant"] == variant]
-                if len(m) == 2:
-                    mb = {r["formulation"]: r for r in m}
+                mb = {r["formulation"]: r for r in m}
+                if "merged" in mb and "basic" in mb:
                     gains[f"{variant}_k{kk}"] = round(1 - mb["merged"]["fixed_ms_per_iter"] / mb["basic"]["fixed_ms_per_iter"], 4)
+                if "fused" in mb and "merged" in mb:
+                    fusion[f"{variant}_k{kk}"] = round(1 - mb["fused"]["fixed_ms_per_iter"] / mb["merged"]["fixed_ms_per_iter"], 4)
         out["merging_time_reduction"] = gains
+        out["fusion_time_reduction_vs_merged"] = fusion
 
     # -------------------------------------------------------------- tiers
     if not args.no_tiers:

@@ -164,7 +164,8 @@ int bicgstab_last_solve_stats(bicgstab_t h, int32_t* iterations_enqueued, int32_
  * `iters` iterations with the stop test off, on the handle's stream, recording
  * a HIP event before and after every launch. For each launch i of one
  * iteration (nsteps <= cap of them) returns kind (0 sparse product,
- * 1 preconditioner, 2 vector pass), op (vector-pass id, -1 otherwise), the
+ * 1 preconditioner, 2 vector pass, 3 sparse product with a dot epilogue), op
+ * (vector-pass id, epilogue id for kind 3, -1 otherwise), the
  * vector blocks it reads and writes, and its average duration in ms. d_x is
  * overwritten. FP64 handles only. */
 int bicgstab_kernel_times(bicgstab_t h, const double* d_b, double* d_x, int32_t iters, int32_t cap, int32_t* kind,

@@ -442,7 +442,7 @@ def alg7_merged_ppipebicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vect
 # -------------------------------------------------------------- dispatch ---
 
 VARIANTS = ("classical", "reordered", "pipelined")
-FORMULATIONS = ("merged", "basic")
+FORMULATIONS = ("merged", "basic", "fused")
 PRECONDS = ("none", "jacobi")
 
 
@@ -452,7 +452,10 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     methods run the same statements (merging changes which statements share a
     pass over memory, Table 2, not what they compute), so both map to the
     listing; for the classical method the basic form is Alg. 1 with its
-    explicit residual-norm stop test."""
+    explicit residual-norm stop test. The fused form (a single-device
+    regrouping of the merged statements: dots formed in the sparse products'
+    epilogues, the Jacobi division done by the pass that produces the vector)
+    computes the merged listing's statements, so it maps to that listing."""
     import scipy.sparse as sp
 
     A = sp.csr_matrix(A)
@@ -460,6 +463,8 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     x0 = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64)
     if variant not in VARIANTS or formulation not in FORMULATIONS or precond not in PRECONDS:
         raise ValueError(f"unknown method {variant}/{formulation}/{precond}")
+    if formulation == "fused":
+        formulation = "merged"
     if precond == "jacobi":
         Minv = jacobi_preconditioner(A)
     else:

@@ -91,6 +91,8 @@ struct bicgstab_ctx {
   float* val32 = nullptr;
   int32_t* blk = nullptr;
   double* partials = nullptr;
+  double* bpart = nullptr;    // row-block partials of products with a dot epilogue
+  double* bpart_t = nullptr;  // the same for the transposed matrix (own allocation)
   double* sc = nullptr;
   int* ist = nullptr;
   Globals* glob = nullptr;
@@ -98,7 +100,9 @@ struct bicgstab_ctx {
   int hist_cap = 0;
   GridCaps caps{512, 512};  // workgroup caps: streaming passes, passes with dots
   int chunk = 8;
-  int spmm_opl = 0;     // SpMM rows per lane per row block (0: default for the width)
+  int spmm_opl = 0;          // SpMM rows per lane per row block (0: default for the width)
+  int spmm_xcd_chunk = 1;    // SpMM row blocks per XCD run (1: round-robin order)
+  int spmm_style = 1;        // SpMM inner loop (0 guarded slots, 1 branch-free slots)
   bool use_graph = true;
   // pinned host mirrors
   int* h_nrun = nullptr;
@@ -125,6 +129,14 @@ namespace {
 
 bool fp32_inner(const bicgstab_ctx* h) { return h->precision == BICGSTAB_FP32_REFINE; }
 
+// The plan has sparse products with a dot epilogue (they need row-block partials).
+bool has_spmm_dot(const bicgstab_ctx* h) {
+  for (const auto* list : {&h->plan.init, &h->plan.iter})
+    for (const Step& st : *list)
+      if (st.kind == K_SPMM_DOT) return true;
+  return false;
+}
+
 // Workspace layout; with assign = true, sets the pointers inside h->base.
 size_t layout(bicgstab_ctx* h, bool assign) {
   size_t off = 0;
@@ -149,7 +161,8 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_diag32 = take(fp32_inner(h) ? (size_t)h->n * 4 : 0);
   const size_t o_val32 = take(fp32_inner(h) ? (size_t)h->nnz * 4 : 0);
   const size_t o_blk = take(h->part.blk.size() * 4);
-  const size_t o_part = take((size_t)h->caps.dot_blocks * 7 * kMaxK * 8);
+  const size_t o_part = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
+  const size_t o_bpart = take(has_spmm_dot(h) ? (h->part.blk.size() - 1) * 3 * (size_t)h->k * 8 : 0);
   const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
   const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
   const size_t o_glob = take(sizeof(Globals));
@@ -165,6 +178,7 @@ size_t layout(bicgstab_ctx* h, bool assign) {
     h->val32 = fp32_inner(h) ? (float*)(b + o_val32) : nullptr;
     h->blk = (int32_t*)(b + o_blk);
     h->partials = (double*)(b + o_part);
+    h->bpart = has_spmm_dot(h) ? (double*)(b + o_bpart) : nullptr;
     h->sc = (double*)(b + o_sc);
     h->ist = (int*)(b + o_ist);
     h->glob = (Globals*)(b + o_glob);
@@ -225,6 +239,9 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
     m.val = fp32 ? (const void*)h->val32 : (const void*)h->val;
     m.blk = h->blk;
     m.nblk = (int)h->part.blk.size() - 1;
+    m.xcd_chunk = h->spmm_xcd_chunk;
+    m.bpart = h->bpart;
+    m.style = h->spmm_style;
     m.nnz_cap = h->part.nnz_cap;
     m.rows_cap = h->part.rows_cap;
   } else {
@@ -233,6 +250,9 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
     m.val = fp32 ? (const void*)h->val32_t : (const void*)h->val_t;
     m.blk = h->blk_t;
     m.nblk = (int)h->part_t.blk.size() - 1;
+    m.xcd_chunk = h->spmm_xcd_chunk;
+    m.bpart = h->bpart_t;
+    m.style = h->spmm_style;
     m.nnz_cap = h->part_t.nnz_cap;
     m.rows_cap = h->part_t.rows_cap;
   }
@@ -245,6 +265,9 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* 
   switch (st.kind) {
     case K_SPMM:
       return launch_spmm(M, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
+    case K_SPMM_DOT:
+      return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], vp[st.in[1]], st.op, h->k, fp32, ctl, st.slot, st.fin,
+                             M.bpart, s);
     case K_PREC:
       return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
                          (int)h->n, h->k, fp32, g, s);
@@ -253,7 +276,8 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* 
       void* out[5] = {};
       for (int i = 0; i < st.nin; ++i) in[i] = vp[st.in[i]];
       for (int i = 0; i < st.nout; ++i) out[i] = vp[st.out[i]];
-      return launch_group(st.op, in, out, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->caps, s);
+      const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
+      return launch_group(st.op, in, out, diag, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->caps, s);
     }
   }
   return hipErrorInvalidValue;
@@ -338,7 +362,7 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
       // inner solves start from d = 0, so A d = 0 without a product
       const void* in0[7] = {};
       void* out0[5] = {vp[st.out[0]]};
-      HIPCHK(launch_group(OP_FILL0, in0, out0, (int)h->n, h->k, 0, F_NONE, ctl, true, h->caps, h->ws));
+      HIPCHK(launch_group(OP_FILL0, in0, out0, nullptr, (int)h->n, h->k, 0, F_NONE, ctl, true, h->caps, h->ws));
     } else {
       HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
     }
@@ -368,7 +392,7 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
     HIPCHK(launch_spmm(M, x, z, h->k, false, nullptr, h->ws));
     const void* in[7] = {b, z, vp[V_R]};
     void* out[5] = {};
-    HIPCHK(launch_group(OP_EXIT, in, out, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->caps, h->ws));
+    HIPCHK(launch_group(OP_EXIT, in, out, nullptr, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->caps, h->ws));
     *launches += 2;
   }
   return BICGSTAB_OK;
@@ -421,7 +445,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {b, Z};
       void* out[5] = {R};
-      HIPCHK(launch_group(OP_REF_RESID, in, out, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->caps, h->ws));
+      HIPCHK(launch_group(OP_REF_RESID, in, out, nullptr, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->caps, h->ws));
     }
     *launches += 3;
     HIPCHK(hipMemcpyAsync(h->h_sc, h->sc, (size_t)S_NSCAL * kMaxK * 8, hipMemcpyDeviceToHost, h->ws));
@@ -456,7 +480,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
                             h->ws));
       const void* in[7] = {};
       void* out[5] = {x};
-      HIPCHK(launch_group(OP_ZEROB, in, out, (int)h->n, k, 0, F_NONE, ctl, false, h->caps, h->ws));
+      HIPCHK(launch_group(OP_ZEROB, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, false, h->caps, h->ws));
       ++*launches;
     }
     if (all_done) break;
@@ -467,7 +491,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {R};
       void* out[5] = {B32, D};
-      HIPCHK(launch_group(OP_REF_SCALE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
+      HIPCHK(launch_group(OP_REF_SCALE, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
     int rc = krylov(h, 0, true, B32, D, inner_tol, maxit, launches, polls, enq);
@@ -483,7 +507,7 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     {
       const void* in[7] = {x, D};
       void* out[5] = {x};
-      HIPCHK(launch_group(OP_REF_UPDATE, in, out, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
+      HIPCHK(launch_group(OP_REF_UPDATE, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
   }
@@ -547,6 +571,7 @@ int build_transpose(bicgstab_ctx* h) {
   HIPCHK(hipFree(counts));
   h->part_t = spmm_partition(rp, h->k, h->spmm_opl);
   HIPCHK(alloc((void**)&h->blk_t, h->part_t.blk.size() * 4));
+  if (has_spmm_dot(h)) HIPCHK(alloc((void**)&h->bpart_t, (h->part_t.blk.size() - 1) * 3 * (size_t)h->k * 8));
   HIPCHK(hipMemcpyAsync(h->blk_t, h->part_t.blk.data(), h->part_t.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   h->have_t = true;
@@ -568,7 +593,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) return fail(BICGSTAB_EINVAL, "nnz must fit int32");
   if (precision != BICGSTAB_FP64 && precision != BICGSTAB_FP32_REFINE)
     return fail(BICGSTAB_EINVAL, "unknown precision");
-  if (formulation == BICGSTAB_FUSED) return fail(BICGSTAB_EUNSUPPORTED, "fused formulation not available");
+  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL)
+    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical method only");
   if (n > 0 && (!A->d_row_ptr || (A->nnz > 0 && (!A->d_col_idx || !A->d_values))))
     return fail(BICGSTAB_EINVAL, "null matrix array");
   bicgstab_ctx* h = new bicgstab_ctx();
@@ -589,6 +615,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   h->hist_cap = std::max(0, env_int("BICGSTAB_HIST_CAP", 1024));
   h->caps.blocks = std::max(8, env_int("BICGSTAB_GRID_CAP", 512));
   h->caps.dot_blocks = std::max(1, std::min(4096, env_int("BICGSTAB_DOT_GRID", 512)));
+  h->spmm_xcd_chunk = std::max(1, env_int("BICGSTAB_SPMM_XCD_CHUNK", 1));
+  h->spmm_style = env_int("BICGSTAB_SPMM_STYLE", 1) == 0 ? 0 : 1;
   h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
   h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;
   std::string err;
@@ -787,7 +815,7 @@ int bicgstab_kernel_times(bicgstab_t h, const double* d_b, double* d_x, int32_t 
   for (int i = 0; i < m; ++i) {
     const Step& st = h->plan.iter[i];
     kind[i] = (int)st.kind;
-    op[i] = st.kind == K_GROUP ? st.op : -1;
+    op[i] = (st.kind == K_GROUP || st.kind == K_SPMM_DOT) ? st.op : -1;
     nin[i] = st.nin;
     nout[i] = st.nout;
     ms[i] = acc[i] / iters;
@@ -803,7 +831,7 @@ int bicgstab_destroy(bicgstab_t h) {
   clear_graphs(h);
   if (h->owned && h->base) hipFree(h->base);
   for (void* p : {(void*)h->rp_t, (void*)h->col_t, (void*)h->perm_t, (void*)h->val_t, (void*)h->val32_t,
-                  (void*)h->blk_t})
+                  (void*)h->blk_t, (void*)h->bpart_t})
     if (p) hipFree(p);
   for (void* p : {(void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
     if (p) hipHostFree(p);
@@ -827,6 +855,10 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
       if (op_info(s.op).ndot > 0 || s.fin != F_NONE) ++fin_kernels;  // its finalize kernel
     } else if (s.kind == K_PREC) {
       ++pa;
+    } else if (s.kind == K_SPMM_DOT) {
+      ++sp;
+      r += 1;         // the epilogue's second operand (the product's own traffic is counted apart)
+      ++fin_kernels;  // its finalize kernel
     } else {
       ++sp;
     }

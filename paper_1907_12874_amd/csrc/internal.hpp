@@ -110,6 +110,9 @@ enum OpId {
   OP_REF_RESID,    // refinement: r = b - z (FP64); dots (r,r), (b,b)
   OP_REF_SCALE,    // refinement: r32 = r / ||r_c|| (to FP32), d = 0
   OP_REF_UPDATE,   // refinement: x = x + ||r_c|| * d
+  OP_F_SUB_ALPHA_H,  // fused Jacobi: s = r - alpha v; sh = s / a_ii
+  OP_F_PUPD_H,       // fused Jacobi: p = r + beta (p - omega v); ph = p / a_ii
+  OP_F_XR_RHO_H,     // fused Jacobi: x += alpha ph + omega sh; r = s - omega t; dot (r, r0)
   OP_NUM
 };
 
@@ -122,7 +125,14 @@ enum VecId {
   V_NUM
 };
 
-enum StepKind { K_SPMM = 0, K_PREC, K_GROUP };
+// K_SPMM_DOT: a sparse product whose epilogue also forms dot products of the
+// rows it writes (op = SpmmEpilogue, in[1] = the second operand).
+enum StepKind { K_SPMM = 0, K_PREC, K_GROUP, K_SPMM_DOT };
+
+enum SpmmEpilogue {
+  E_DOT_W = 0,  // y = A x; dot (y, w)
+  E_PPT,        // y = A x; dots (y, w), (y, y), (w, w)
+};
 
 struct Step {
   StepKind kind;
@@ -162,6 +172,9 @@ struct SpmmMat {
   int n;
   int nnz_cap;   // entries staged in LDS per row block (largest block, <= kSpmmNnzMax)
   int rows_cap;  // rows of the largest row block
+  int xcd_chunk; // consecutive row blocks given to one XCD (1: plain round-robin order)
+  double* bpart; // per-row-block partial sums of a product with a dot epilogue (nblk x 3k)
+  int style;     // inner loop: 0 guarded slots, 1 branch-free slots
 };
 
 struct SpmmPartition {
@@ -172,6 +185,17 @@ struct SpmmPartition {
 
 hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
+// Sparse product with a dot epilogue (SpmmEpilogue epi, second operand W):
+// one workgroup per row block stores its partial sums in bpart (nblk x 3k
+// doubles at most), a second kernel sums runs of blocks into ctl.partials, and
+// the finalize kernel sums the runs and runs step `fin` on dot slots slot.. .
+hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k, bool fp32,
+                           const Ctl& ctl, int slot, int fin, double* bpart, hipStream_t s);
+// Runs of row blocks the epilogue partials are first summed over (<= 256).
+int spmm_dot_runs(int nblk);
+// The one-workgroup finalize kernel after a reduction pass of nb workgroups
+// and P = ndot * k pairs.
+hipError_t launch_finalize(const Ctl& ctl, int P, int nb, int slot, int fin, bool early, hipStream_t s);
 hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
 // Workgroup-count caps of the vector passes: plain streaming passes and passes
@@ -181,8 +205,8 @@ struct GridCaps {
   int blocks;
   int dot_blocks;
 };
-hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
-                        const Ctl& ctl, bool fp32, const GridCaps& caps, hipStream_t s);
+hipError_t launch_group(int op, const void* const* in, void* const* out, const void* diag, int n, int k, int slot,
+                        int fin, const Ctl& ctl, bool fp32, const GridCaps& caps, hipStream_t s);
 hipError_t launch_setup_state(const Ctl& ctl, double tol, int maxit, int hist_cap, hipStream_t s);
 hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
 hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,

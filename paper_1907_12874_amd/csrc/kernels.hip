@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "reduce.hpp"
 
 namespace bcg {
 
@@ -55,11 +56,15 @@ struct Coef {
 // running columns, every column, or the columns whose right-hand side is zero.
 enum Part { PART_RUN = 0, PART_ALL = 1, PART_ZEROB = 2 };
 
-#define OP_HEAD(NI, NO, ND, XI, XO, PT, EARLY_)          \
+#define OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, USED)   \
   static constexpr int NIN = NI, NOUT = NO, NDOT = ND;   \
   static constexpr unsigned XIN = XI, XOUT = XO;         \
   static constexpr int PART = PT;                        \
-  static constexpr bool EARLY = EARLY_;
+  static constexpr bool EARLY = EARLY_;                  \
+  static constexpr bool USE_D = USED;
+#define OP_HEAD(NI, NO, ND, XI, XO, PT, EARLY_) OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, false)
+// USE_D: the op also reads the row's diagonal entry a_ii, passed as v[NIN].
+#define OP_HEAD_D(NI, NO, ND, XI, XO, PT, EARLY_) OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, true)
 // Op bodies compute in FP64 from operands of storage type T; a value that is
 // both stored and used again in the same op is first rounded to T (R(.)), so
 // dots and later terms see exactly the stored vector (a no-op when T is FP64).
@@ -281,6 +286,35 @@ struct KRefScale {  // in: r (FP64) ; out: rs = r / ||r_c|| (T), d = 0 (FP64)
 struct KRefUpdate {  // in: x, d (FP64) ; out: x = x + ||r_c|| d
   OP_HEAD(2, 1, 0, 3, 1, PART_ALL, false)
   OP_F { o[0] = v[0] + c.scale * v[1]; }
+};
+
+// Fused Jacobi: the pass that produces s or p also writes the preconditioned
+// copy (the same division by a_ii as the preconditioner pass, so the values
+// are those of the merged form), and the solution update joins {r, rho'}.
+struct KFSubAlphaH {  // in: r, v (+ a_ii) ; out: s, sh
+  OP_HEAD_D(2, 2, 0, 0, 0, PART_RUN, true)
+  OP_F {
+    const double sv = R(v[0] - c.alpha * v[1]);
+    o[0] = sv;
+    o[1] = sv / v[2];
+  }
+};
+struct KFPUpdH {  // in: r, p, v (+ a_ii) ; out: p, ph
+  OP_HEAD_D(3, 2, 0, 0, 0, PART_RUN, true)
+  OP_F {
+    const double pv = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
+    o[0] = pv;
+    o[1] = pv / v[3];
+  }
+};
+struct KFXrRhoH {  // in: x, ph, sh, s, t, r0 ; out: x, r ; (r, r0)
+  OP_HEAD(6, 2, 1, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    const double r = R(v[3] - c.omega * v[4]);
+    o[1] = r;
+    a[0] += r * v[5];
+  }
 };
 
 // ------------------------------------------------------- scalar recurrence ---
@@ -567,6 +601,7 @@ __device__ void finalize_global(int step, const Ctl& C) {
 struct GArgs {
   const void* in[7];
   void* out[5];
+  const void* diag;  // a_ii (storage type) for USE_D ops
   long n;
   int k, kpl, slot, fin;
   Ctl ctl;
@@ -582,26 +617,8 @@ struct GArgs {
 constexpr int kFinBlock = 1024;
 
 template <int ND, int BS>
-__device__ void block_reduce_store(const double* acc, const GArgs& a) {
-  __shared__ double s_w[BS / 64][ND][kMaxK];
-  const int kp = 1 << a.kpl;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    double v = acc[d];
-    for (int off = kp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if (lane < kp) s_w[wave][d][lane] = v;
-  }
-  __syncthreads();
-  const int k = a.k, P = ND * k;
-  const int nb = gridDim.x;
-  for (int t = threadIdx.x; t < P; t += BS) {
-    const int d = t / k, c = t - d * k;
-    double v = s_w[0][d][c];
-#pragma unroll
-    for (int w = 1; w < BS / 64; ++w) v += s_w[w][d][c];
-    a.ctl.partials[(size_t)t * nb + blockIdx.x] = v;
-  }
+__device__ __forceinline__ void block_reduce_store(const double* acc, const GArgs& a) {
+  store_block_partials<ND, BS>(acc, a.ctl.partials, a.k, a.kpl, gridDim.x, blockIdx.x);
 }
 
 // One workgroup: sum the nb partials of each of the P pairs (G lanes per pair
@@ -656,7 +673,7 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
     else if (Op::PART == PART_ZEROB)
       on = IS(a.ctl, I_ZEROB, c) != 0;
   }
-  constexpr int NI = Op::NIN > 0 ? Op::NIN : 1;
+  constexpr int NI = Op::NIN + (Op::USE_D ? 1 : 0) > 0 ? Op::NIN + (Op::USE_D ? 1 : 0) : 1;
   constexpr int NO = Op::NOUT > 0 ? Op::NOUT : 1;
   constexpr int ND = Op::NDOT > 0 ? Op::NDOT : 1;
   double acc[ND];
@@ -680,6 +697,7 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
 #pragma unroll
         for (int i = 0; i < Op::NIN; ++i)
           v[u][i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
+        if constexpr (Op::USE_D) v[u][Op::NIN] = ldv<T>(a.diag, (size_t)(row + u * stride));
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -700,6 +718,7 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
       double v1[NI];
 #pragma unroll
       for (int i = 0; i < Op::NIN; ++i) v1[i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
+      if constexpr (Op::USE_D) v1[Op::NIN] = ldv<T>(a.diag, (size_t)row);
       double o[NO];
       Op::template f<T>(v1, cf, o, acc);
 #pragma unroll
@@ -765,15 +784,24 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_REF_RESID: return launch_op<KRefResid, T>(a, grid_cap, s);
     case OP_REF_SCALE: return launch_op<KRefScale, T>(a, grid_cap, s);
     case OP_REF_UPDATE: return launch_op<KRefUpdate, T>(a, grid_cap, s);
+    case OP_F_SUB_ALPHA_H: return launch_op<KFSubAlphaH, T>(a, grid_cap, s);
+    case OP_F_PUPD_H: return launch_op<KFPUpdH, T>(a, grid_cap, s);
+    case OP_F_XR_RHO_H: return launch_op<KFXrRhoH, T>(a, grid_cap, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_group(int op, const void* const* in, void* const* out, int n, int k, int slot, int fin,
-                        const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s) {
+hipError_t launch_finalize(const Ctl& ctl, int P, int nb, int slot, int fin, bool early, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, ctl, P, nb, slot, fin, early ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_group(int op, const void* const* in, void* const* out, const void* diag, int n, int k, int slot,
+                        int fin, const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s) {
   GArgs a;
   for (int i = 0; i < 7; ++i) a.in[i] = in[i];
   for (int i = 0; i < 5; ++i) a.out[i] = out[i];
+  a.diag = diag;
   a.n = n;
   a.k = k;
   int kp = pad_k(k);

@@ -1,5 +1,6 @@
 // Launch plans: the sequence of kernels that makes up the start and one
-// iteration of every method, in basic and merged form.
+// iteration of every method, in basic and merged form (and, for the classical
+// method, a fused form).
 //
 // Merged plans give one streaming pass per line of the paper's merged
 // listings (Appendix B: Alg. 2 and 5 classical, Alg. 6 Reordered, Alg. 4 and 7
@@ -46,6 +47,9 @@ const OpInfo kOps[OP_NUM] = {
     {2, 1, 2, "ref_resid"},   // OP_REF_RESID
     {1, 2, 0, "ref_scale"},   // OP_REF_SCALE
     {2, 1, 0, "ref_update"},  // OP_REF_UPDATE
+    {2, 2, 0, "f_sub_alpha_h"},  // OP_F_SUB_ALPHA_H (+ the diagonal)
+    {3, 2, 0, "f_pupd_h"},       // OP_F_PUPD_H (+ the diagonal)
+    {6, 2, 1, "f_xr_rho_h"},     // OP_F_XR_RHO_H
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -74,6 +78,14 @@ Step SPMM(int in, int out) {
   return s;
 }
 
+// Sparse product y = A x with a dot epilogue against w (SpmmEpilogue epi).
+Step SPMM_DOT(int x, int y, int epi, int w, int slot, int fin) {
+  Step s = G(OP_COPY, {x, w}, {y}, slot, fin);
+  s.kind = K_SPMM_DOT;
+  s.op = epi;
+  return s;
+}
+
 Step PREC(int in, int out) {
   Step s = G(OP_COPY, {in}, {out});
   s.kind = K_PREC;
@@ -82,7 +94,47 @@ Step PREC(int in, int out) {
 }
 
 // ------------------------------------------------------------- classical ---
+// Fused form (one device, beyond the paper's grouping): the same statements as
+// Alg. 2 / Alg. 5 in five launches and their finalize kernels:
+//   v = A ph with delta = (v, r0) in the product's epilogue;
+//   s = r - alpha v (and sh = s / a_ii);
+//   t = A sh with phi = (t, s), psi = (t, t), theta = (s, s) in the epilogue;
+//   x += alpha ph + omega sh, r = s - omega t, rho' = (r, r0);
+//   p = r + beta (p - omega v) (and ph = p / a_ii).
+// With Jacobi the pass that makes p or s also writes its preconditioned copy,
+// so no separate preconditioner pass reads it back.
+void classical_fused(int precond, Plan* P) {
+  const bool jac = precond == 1;
+  const int ph = jac ? V_PH : V_P;
+  const int sh = jac ? V_SH : V_S;
+  P->init = {SPMM(V_X, V_V), G(OP_INIT_P, {V_B, V_V}, {V_R, V_R0, V_P}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
+  if (jac) P->init.push_back(PREC(V_P, V_PH));
+  auto& it = P->iter;
+  it.push_back(SPMM_DOT(ph, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
+  if (jac)
+    it.push_back(G(OP_F_SUB_ALPHA_H, {V_R, V_V}, {V_S, V_SH}));
+  else
+    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_S}));
+  it.push_back(SPMM_DOT(sh, V_T, E_PPT, V_S, 0, F_OMEGA_MERGED));
+  if (jac) {
+    it.push_back(G(OP_F_XR_RHO_H, {V_X, V_PH, V_SH, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
+    it.push_back(G(OP_F_PUPD_H, {V_R, V_P, V_V}, {V_P, V_PH}));
+  } else {
+    it.push_back(G(OP_C_XR_RHO, {V_X, V_P, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
+    it.push_back(G(OP_PUPD, {V_R, V_P, V_V}, {V_P}));
+  }
+  P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T};
+  if (jac) {
+    P->vecs.push_back(V_PH);
+    P->vecs.push_back(V_SH);
+  }
+}
+
 void classical(int formulation, int precond, Plan* P) {
+  if (formulation == 2) {
+    classical_fused(precond, P);
+    return;
+  }
   const bool jac = precond == 1;
   const int ph = jac ? V_PH : V_P;  // p-hat (= p without preconditioner)
   const int sh = jac ? V_SH : V_S;  // s-hat
@@ -269,8 +321,12 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
     *err = "unknown preconditioner";
     return false;
   }
-  if (formulation != 0 && formulation != 1) {
-    *err = "unknown or unsupported formulation";
+  if (formulation != 0 && formulation != 1 && formulation != 2) {
+    *err = "unknown formulation";
+    return false;
+  }
+  if (formulation == 2 && variant != 0) {
+    *err = "the fused formulation is built for the classical method only";
     return false;
   }
   switch (variant) {
@@ -297,6 +353,11 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
         }
         if (oi.ndot > 0 && s.slot + oi.ndot > 7) {
           *err = std::string("plan step ") + oi.name + ": dot slots out of range";
+          return false;
+        }
+      } else if (s.kind == K_SPMM_DOT) {
+        if (s.nin != 2 || s.nout != 1 || (s.op != E_DOT_W && s.op != E_PPT) || s.slot + (s.op == E_PPT ? 3 : 1) > 7) {
+          *err = "plan step: product with dot epilogue needs x, w, y and a known epilogue";
           return false;
         }
       } else if (s.nin != 1 || s.nout != 1) {

@@ -6,10 +6,21 @@
 // (kp = k rounded up to a power of two) computes Y[i, c] for its rows. A lane
 // takes its rows two at a time and issues the X gathers of both (up to 16)
 // before it adds any of them; the products of a row are added in entry order,
-// the rounding of a plain sequential sum.
+// the rounding of a plain sequential sum. The matrix value of a product is
+// read from LDS when it is used (not held in registers through the gather),
+// and X is addressed by 32-bit offsets from a uniform base when the block
+// fits, which keeps the register count, and so the number of workgroups in
+// flight per compute unit, up.
+//
+// The same row-block body serves the sparse product with a dot epilogue
+// (beyond the paper's grouping: dots of the written rows formed in the
+// product): each workgroup stores its per-column partial sums block-major,
+// a second kernel sums them over runs of blocks, and the finalize kernel sums
+// the runs, every sum in a fixed order.
 #include <algorithm>
 
 #include "internal.hpp"
+#include "reduce.hpp"
 
 namespace bcg {
 
@@ -23,18 +34,65 @@ __host__ __device__ inline int pad_k_(int k) {
 
 // Workgroup size and rows per lane of the product for padded width kp: up to
 // 2048 outputs and 256 rows per block. (Measured on the 128^3 stencil at
-// k = 32: 1024-lane workgroups with two rows per lane, column tiling and an
-// XCD-contiguous block order were all slower; in plain round-robin order the
-// XCDs work on neighbouring rows at the same time and share X rows through
-// the Infinity Cache.)
-__host__ __device__ inline int spmm_block(int kp) { return 256; }
+// k = 32: 1024-lane workgroups with two rows per lane and column tiling were
+// slower.)
+constexpr int kSpmmBlock = 256;
 inline int spmm_rows_per_lane(int kp) { return kp >= 8 ? 8 : kp; }
 
-template <class T, int KPL, int BS>
-__global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y, int k,
-                                                  const Globals* glob) {
-  if (glob && glob->nrun == 0) return;
-  const int L = blockIdx.x;
+// Row block of workgroup w. Workgroups are dealt to the 8 XCDs in turn
+// (XCD = w mod 8); with C > 1, runs of C consecutive row blocks go to one XCD,
+// so rows a few blocks apart (the neighbours of a stencil row) meet in the
+// same L2. A bijection of [0, nblk): the tail beyond a multiple of 8C keeps
+// the plain order.
+__device__ __forceinline__ int block_of(int w, int nblk, int C) {
+  if (C <= 1) return w;
+  const int full = nblk / (8 * C) * (8 * C);
+  if (w >= full) return w;
+  const int x = w & 7, q = w >> 3;
+  return ((q / C) * 8 + x) * C + (q % C);
+}
+
+typedef __attribute__((address_space(1))) const char gcchar;
+
+// Element (j, c) of the row-major block X: through a 32-bit byte offset from
+// the uniform base when the whole block is below 4 GiB (OFF32), else 64-bit.
+template <class T, bool OFF32>
+__device__ __forceinline__ T load_x(const T* X, int j, int k, int c) {
+  if constexpr (OFF32) {
+    const unsigned off = ((unsigned)j * (unsigned)k + (unsigned)c) * (unsigned)sizeof(T);
+    return *(const __attribute__((address_space(1))) T*)((gcchar*)X + off);
+  } else {
+    return X[(size_t)j * k + c];
+  }
+}
+
+struct NoEpilogue {
+  template <class T>
+  __device__ __forceinline__ void operator()(int, T) {}
+};
+
+// Dots of the written rows against W (E_DOT_W: (y, w); E_PPT: (y, w), (y, y),
+// (w, w)), per lane in the order the lane writes its rows.
+template <class T, int EPI>
+struct DotEpilogue {
+  const T* W;
+  int k, c;
+  double acc[3];
+  __device__ __forceinline__ void operator()(int row, T y) {
+    const double yv = (double)y;
+    const double wv = (double)W[(size_t)row * k + c];
+    acc[0] += yv * wv;
+    if (EPI == E_PPT) {
+      acc[1] += yv * yv;
+      acc[2] += wv * wv;
+    }
+  }
+};
+
+// Y rows of row block L; every finished output (row, value) goes to epi.
+template <class T, int KPL, int BS, bool OFF32, int STYLE, class Epi>
+__device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict__ X, T* __restrict__ Y, int k, int L,
+                                          Epi& epi) {
   extern __shared__ double s_mem[];
   T* s_val = reinterpret_cast<T*>(s_mem);
   T* s_red = s_val + A.nnz_cap;
@@ -64,30 +122,66 @@ __global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict
       const int ebB = has_b ? s_rp[rb] : 0, eeB = has_b ? s_rp[rb + 1] : 0;
       const int len = max(eeA - ebA, eeB - ebB);
       T sumA = (T)0, sumB = (T)0;
-      for (int o = 0; o < len; o += 8) {
-        T aA[8], xA[8], aB[8], xB[8];
+      if constexpr (STYLE == 0) {
+        // guarded slots, the value of a product read with its column index
+        for (int o = 0; o < len; o += 8) {
+          T aA[8], xA[8], aB[8], xB[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int ea = ebA + o + j;
-          if (ea < eeA) {
-            aA[j] = s_val[ea];
-            xA[j] = X[(size_t)s_col[ea] * k + c];
+          for (int j = 0; j < 8; ++j) {
+            const int ea = ebA + o + j;
+            if (ea < eeA) {
+              aA[j] = s_val[ea];
+              xA[j] = X[(size_t)s_col[ea] * k + c];
+            }
+            const int eb = ebB + o + j;
+            if (eb < eeB) {
+              aB[j] = s_val[eb];
+              xB[j] = X[(size_t)s_col[eb] * k + c];
+            }
           }
-          const int eb = ebB + o + j;
-          if (eb < eeB) {
-            aB[j] = s_val[eb];
-            xB[j] = X[(size_t)s_col[eb] * k + c];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (ebA + o + j < eeA) sumA += aA[j] * xA[j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (ebB + o + j < eeB) sumB += aB[j] * xB[j];
+        }
+      } else {
+        // Branch-free: a slot past its row's end gathers row 0 of X (always a
+        // valid address) and its product is not added (a select, so the sums
+        // are those of the entries alone, in order). Every gather of the step
+        // is then in flight before the first is used.
+        const int lastA = max(eeA - 1, 0), lastB = max(eeB - 1, 0);
+        for (int o = 0; o < len; o += 8) {
+          T xA[8], xB[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int ea = ebA + o + j, eb = ebB + o + j;
+            const int ja = ea < eeA ? s_col[min(ea, lastA)] : 0;
+            const int jb = eb < eeB ? s_col[min(eb, lastB)] : 0;
+            xA[j] = load_x<T, OFF32>(X, ja, k, c);
+            xB[j] = load_x<T, OFF32>(X, jb, k, c);
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int ea = ebA + o + j;
+            const T t = sumA + s_val[min(ea, lastA)] * xA[j];
+            sumA = ea < eeA ? t : sumA;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int eb = ebB + o + j;
+            const T t = sumB + s_val[min(eb, lastB)] * xB[j];
+            sumB = eb < eeB ? t : sumB;
           }
         }
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (ebA + o + j < eeA) sumA += aA[j] * xA[j];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (ebB + o + j < eeB) sumB += aB[j] * xB[j];
       }
       Y[(size_t)(r0 + r) * k + c] = sumA;
-      if (has_b) Y[(size_t)(r0 + rb) * k + c] = sumB;
+      epi(r0 + r, sumA);
+      if (has_b) {
+        Y[(size_t)(r0 + rb) * k + c] = sumB;
+        epi(r0 + rb, sumB);
+      }
     }
   } else {
     // one long row (r1 == r0 + 1): lanes of the same column split its entries
@@ -102,7 +196,7 @@ __global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict
       }
       __syncthreads();
       if (c < k)
-        for (int e = rsub; e < m; e += rpp) sum += s_val[e] * X[(size_t)s_col[e] * k + c];
+        for (int e = rsub; e < m; e += rpp) sum += s_val[e] * load_x<T, OFF32>(X, s_col[e], k, c);
     }
     s_red[threadIdx.x] = sum;
     __syncthreads();
@@ -110,19 +204,61 @@ __global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict
       T s = (T)0;
       for (int g = 0; g < rpp; ++g) s += s_red[g * kp + c];
       Y[(size_t)r0 * k + c] = s;
+      epi(r0, s);
     }
   }
 }
 
-template <class T, int BS>
+template <class T, int KPL, int BS, bool OFF32, int STYLE>
+__global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y, int k,
+                                                  const Globals* glob) {
+  if (glob && glob->nrun == 0) return;
+  NoEpilogue none;
+  row_block<T, KPL, BS, OFF32, STYLE>(A, X, Y, k, block_of(blockIdx.x, A.nblk, A.xcd_chunk), none);
+}
+
+// The product with a dot epilogue: one workgroup per row block, as the plain
+// product; the block's ND x k partial sums go to bpart[L * P + d * k + c]
+// (block-major, P = ND * k).
+template <class T, int KPL, int BS, bool OFF32, int STYLE, int EPI>
+__global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y,
+                                                      const T* __restrict__ W, int k, double* __restrict__ bpart,
+                                                      const Globals* glob) {
+  if (glob->nrun == 0) return;
+  constexpr int ND = EPI == E_DOT_W ? 1 : 3;
+  const int L = block_of(blockIdx.x, A.nblk, A.xcd_chunk);
+  DotEpilogue<T, EPI> epi{W, k, (int)(threadIdx.x & ((1 << KPL) - 1)), {0.0, 0.0, 0.0}};
+  row_block<T, KPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
+  // lanes past k returned from the row loop with their sums still zero
+  store_block_partials_strided<ND, BS>(epi.acc, bpart + (size_t)L * ND * k, k, KPL, 1);
+}
+
+// Sums the block-major partials of nb row blocks over G runs of consecutive
+// blocks: out[p * G + g] = sum of bpart[b * P + p] for b in run g, in block
+// order; the finalize kernel then sums the G runs of each pair in run order.
+__global__ __launch_bounds__(256) void reduce_runs_kernel(const double* __restrict__ bpart, int nb, int P,
+                                                          double* __restrict__ out, int G, const Globals* glob) {
+  if (glob->nrun == 0) return;
+  const int g = blockIdx.x;
+  const int b0 = (int)((long)nb * g / G), b1 = (int)((long)nb * (g + 1) / G);
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    double v = 0.0;
+    for (int b = b0; b < b1; ++b) v += bpart[(size_t)b * P + p];
+    out[(size_t)p * G + g] = v;
+  }
+}
+
+template <class T, int BS, bool OFF32, int STYLE>
 hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globals* glob, hipStream_t s) {
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
                      (size_t)(A.rows_cap + 1) * 4 + 16;
   switch (kp) {
-#define SPMM_CASE(KP, KPL) \
-  case KP: hipLaunchKernelGGL((spmm_kernel<T, KPL, BS>), dim3(grid), dim3(BS), lds, s, A, x, y, k, glob); break;
+#define SPMM_CASE(KP, KPL)                                                                                  \
+  case KP:                                                                                                  \
+    hipLaunchKernelGGL((spmm_kernel<T, KPL, BS, OFF32, STYLE>), dim3(grid), dim3(BS), lds, s, A, x, y, k, glob); \
+    break;
     SPMM_CASE(1, 0)
     SPMM_CASE(2, 1)
     SPMM_CASE(4, 2)
@@ -136,12 +272,63 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
   return hipGetLastError();
 }
 
+template <class T, int BS, bool OFF32, int STYLE, int EPI>
+hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k, double* bpart,
+                           const Globals* glob, hipStream_t s) {
+  const int kp = pad_k_(k);
+  const unsigned grid = (unsigned)A.nblk;
+  const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
+                     (size_t)(A.rows_cap + 1) * 4 + 16;
+  switch (kp) {
+#define SPMM_DOT_CASE(KP, KPL)                                                                              \
+  case KP:                                                                                                  \
+    hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), lds, s, A, x, y, w, \
+                       k, bpart, glob);                                                                     \
+    break;
+    SPMM_DOT_CASE(1, 0)
+    SPMM_DOT_CASE(2, 1)
+    SPMM_DOT_CASE(4, 2)
+    SPMM_DOT_CASE(8, 3)
+    SPMM_DOT_CASE(16, 4)
+    SPMM_DOT_CASE(32, 5)
+    SPMM_DOT_CASE(64, 6)
+#undef SPMM_DOT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// X block bytes below 4 GiB: 32-bit gather offsets.
+inline bool off32(const SpmmMat& A, int k, size_t elem) { return (size_t)A.n * (size_t)k * elem < ((size_t)1 << 32); }
+
 template <class T>
 hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
-  if (spmm_block(pad_k_(k)) == 256) return spmm_launch_bs<T, 256>(A, x, y, k, glob, s);
-  return spmm_launch_bs<T, 1024>(A, x, y, k, glob, s);
+  if (A.style == 0) return spmm_launch_bs<T, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+  if (off32(A, k, sizeof(T))) return spmm_launch_bs<T, kSpmmBlock, true, 1>(A, x, y, k, glob, s);
+  return spmm_launch_bs<T, kSpmmBlock, false, 1>(A, x, y, k, glob, s);
+}
+
+template <class T>
+hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k,
+                             double* bpart, const Globals* glob, hipStream_t s) {
+  const T* x = static_cast<const T*>(X);
+  T* y = static_cast<T*>(Y);
+  const T* w = static_cast<const T*>(W);
+  const bool o32 = off32(A, k, sizeof(T));
+  if (A.style == 0) {
+    if (epi == E_DOT_W) return spmm_dot_launch<T, kSpmmBlock, false, 0, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
+    if (epi == E_PPT) return spmm_dot_launch<T, kSpmmBlock, false, 0, E_PPT>(A, x, y, w, k, bpart, glob, s);
+    return hipErrorInvalidValue;
+  }
+  if (epi == E_DOT_W)
+    return o32 ? spmm_dot_launch<T, kSpmmBlock, true, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s)
+               : spmm_dot_launch<T, kSpmmBlock, false, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
+  if (epi == E_PPT)
+    return o32 ? spmm_dot_launch<T, kSpmmBlock, true, 1, E_PPT>(A, x, y, w, k, bpart, glob, s)
+               : spmm_dot_launch<T, kSpmmBlock, false, 1, E_PPT>(A, x, y, w, k, bpart, glob, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -154,7 +341,7 @@ SpmmPartition spmm_partition(const std::vector<int32_t>& row_ptr, int k, int row
   const int n = (int)row_ptr.size() - 1;
   const int kp = pad_k_(k);
   const int rpl = rows_per_lane_override > 0 ? rows_per_lane_override : spmm_rows_per_lane(kp);
-  int rows_target = spmm_block(kp) * rpl / kp;
+  int rows_target = kSpmmBlock * rpl / kp;
   if (rows_target > kSpmmRowsMax) rows_target = kSpmmRowsMax;
   if (rows_target < 1) rows_target = 1;
   SpmmPartition P;
@@ -178,6 +365,25 @@ hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp3
                        hipStream_t s) {
   if (A.nblk <= 0) return hipSuccess;
   return fp32 ? spmm_dispatch<float>(A, X, Y, k, glob, s) : spmm_dispatch<double>(A, X, Y, k, glob, s);
+}
+
+int spmm_dot_runs(int nblk) { return std::max(1, std::min(nblk, 256)); }
+
+hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k, bool fp32,
+                           const Ctl& ctl, int slot, int fin, double* bpart, hipStream_t s) {
+  const int nd = epi == E_DOT_W ? 1 : 3;
+  const int P = nd * k;
+  const int G = spmm_dot_runs(A.nblk);
+  if (A.nblk > 0) {
+    hipError_t e = fp32 ? spmm_dot_dispatch<float>(A, X, Y, W, epi, k, bpart, ctl.glob, s)
+                        : spmm_dot_dispatch<double>(A, X, Y, W, epi, k, bpart, ctl.glob, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_runs_kernel, dim3(G), dim3(256), 0, s, bpart, A.nblk, P, ctl.partials, G, ctl.glob);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // with no rows the partials are not written: the finalize then sums nothing
+  return launch_finalize(ctl, A.nblk > 0 ? P : 0, G, slot, fin, true, s);
 }
 
 }  // namespace bcg

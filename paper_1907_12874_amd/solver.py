@@ -197,7 +197,7 @@ class Solver:
                                           nout.ctypes.data_as(P), ms.ctypes.data_as(C.POINTER(C.c_double)),
                                           C.byref(ns)), "bicgstab_kernel_times")
         m = ns.value
-        return [{"kind": ["spmm", "prec", "group"][kind[i]], "op": int(op[i]), "nin": int(nin[i]),
+        return [{"kind": ["spmm", "prec", "group", "spmm_dot"][kind[i]], "op": int(op[i]), "nin": int(nin[i]),
                  "nout": int(nout[i]), "ms": float(ms[i])} for i in range(m)]
 
     def close(self):

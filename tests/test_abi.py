@@ -89,6 +89,31 @@ def test_merging_reduces_launches(L):
             assert plan_traffic(v, "merged", p)["launches"] < plan_traffic(v, "basic", p)["launches"]
 
 
+def test_fused_plan_traffic(L):
+    """Fused classical form: the dots of the products' epilogues read one more
+    block each, the Jacobi division rides on the passes that produce p and s,
+    and the solution update joins {r, rho'}: 12 reads / 4 writes without a
+    preconditioner (merged: 14 / 4) and 13 / 6 with Jacobi and no separate
+    preconditioner pass (merged: 15 / 4 plus two passes of 1 / 1)."""
+    from paper_1907_12874_amd import plan_traffic
+
+    a = plan_traffic("classical", "fused", "none")
+    b = plan_traffic("classical", "fused", "jacobi")
+    assert (a["reads"], a["writes"], a["spmms"], a["precond_apps"], a["launches"]) == (12, 4, 2, 0, 8)
+    assert (b["reads"], b["writes"], b["spmms"], b["precond_apps"], b["launches"]) == (13, 6, 2, 0, 8)
+    m = plan_traffic("classical", "merged", "jacobi")
+    assert b["reads"] + b["writes"] < m["reads"] + m["writes"] + 2 * m["precond_apps"]
+    assert b["launches"] < m["launches"]
+    from paper_1907_12874_amd import _lib
+
+    r = ctypes.c_int32()
+    for variant in (1, 2):  # not built for the Reordered and Pipelined methods
+        assert L.bicgstab_plan_traffic(variant, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
+        desc = _lib.CSRDesc(4, 0, None, None, None)
+        h = ctypes.c_void_p()
+        assert L.bicgstab_create(ctypes.byref(desc), 4, 1, variant, 2, 0, 0, None, ctypes.byref(h)) == _lib.EUNSUPPORTED
+
+
 def test_invalid_arguments_are_errors(L):
     from paper_1907_12874_amd import _lib
 

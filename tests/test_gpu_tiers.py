@@ -23,20 +23,21 @@ def say(*a):
 
 # ------------------------------------------------------------- precision ---
 
-@pytest.mark.parametrize("variant,precond", [("classical", "none"), ("classical", "jacobi"), ("pipelined", "none"),
-                                             ("reordered", "jacobi")])
-def test_precision_tier_matches_refinement_oracle(lib, variant, precond):
+@pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
+                                                         ("pipelined", "none", "merged"), ("reordered", "jacobi", "merged"),
+                                                         ("classical", "jacobi", "fused")])
+def test_precision_tier_matches_refinement_oracle(lib, variant, precond, formulation):
     """27-point random matrix (the precision-tier recipe at 20^3), k = 8,
     tol 1e-10: every column converges in FP64 terms, the number of FP64
     corrections matches the NumPy FP32-refinement oracle within 1, and the
     error against a tight FP64 solve is within the conditioning bound."""
     import torch
 
-    say(f"precision tier {variant}/{precond}")
+    say(f"precision tier {variant}/{precond}/{formulation}")
     A = random_27pt(20, seed=3)
     S = A.to_scipy()
     b, xs = manufactured_rhs(A, 8, seed=4)
-    s = lib.Solver.from_csr(A, 8, variant=variant, formulation="merged", precond=precond, precision="fp32_refine")
+    s = lib.Solver.from_csr(A, 8, variant=variant, formulation=formulation, precond=precond, precision="fp32_refine")
     x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=5000)
     X = x.cpu().numpy()
     outer = s.refine_outer()
@@ -47,7 +48,7 @@ def test_precision_tier_matches_refinement_oracle(lib, variant, precond):
     nt = np.linalg.norm(tight.x, axis=0)
     err = np.linalg.norm(X - tight.x, axis=0) / nt
     # equal accuracy: the FP64 solve to the same tolerance on the same GPU
-    s64 = lib.Solver.from_csr(A, 8, variant=variant, formulation="merged", precond=precond)
+    s64 = lib.Solver.from_csr(A, 8, variant=variant, formulation=formulation, precond=precond)
     x64, info64 = s64.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=5000)
     err64 = np.linalg.norm(x64.cpu().numpy() - tight.x, axis=0) / nt
     say(f"  outer {list(outer)}, max rel error vs FP64 tight solve {err.max():.2e} (FP64 solve at the same tol "
@@ -101,17 +102,17 @@ def test_grad_values_kernel(lib):
         assert np.all(np.abs(g - ref) <= 16 * np.finfo(float).eps * scale * max(1, k))
 
 
-@pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_transpose_solve(lib, precond):
+@pytest.mark.parametrize("precond,formulation", [("none", "merged"), ("jacobi", "merged"), ("jacobi", "fused")])
+def test_transpose_solve(lib, precond, formulation):
     """A^T Lambda = G by the same method on the device-built transposed CSR
     (nonsymmetric matrix, so A vs A^T matters)."""
     import torch
 
-    say(f"transpose solve {precond}")
+    say(f"transpose solve {precond} {formulation}")
     A = conv_diff(14, 3, (3.0, -2.0, 1.5))
     St = A.to_scipy().T.tocsr()
     G = np.random.default_rng(11).uniform(-1, 1, (A.n, 4))
-    s = lib.Solver.from_csr(A, 4, precond=precond)
+    s = lib.Solver.from_csr(A, 4, precond=precond, formulation=formulation)
     lam, info = s.solve_transpose(torch.from_numpy(G).cuda(), tol=1e-12, maxit=3000)
     L = lam.cpu().numpy()
     assert np.all(info.status == 0)
