@@ -102,7 +102,6 @@ struct bicgstab_ctx {
   int chunk = 8;
   int spmm_opl = 0;          // SpMM rows per lane per row block (0: default for the width)
   int spmm_xcd_chunk = 1;    // SpMM row blocks per XCD run (1: round-robin order)
-  int spmm_style = 1;        // SpMM inner loop (0 guarded slots, 1 branch-free slots)
   bool use_graph = true;
   // pinned host mirrors
   int* h_nrun = nullptr;
@@ -241,7 +240,6 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
     m.nblk = (int)h->part.blk.size() - 1;
     m.xcd_chunk = h->spmm_xcd_chunk;
     m.bpart = h->bpart;
-    m.style = h->spmm_style;
     m.nnz_cap = h->part.nnz_cap;
     m.rows_cap = h->part.rows_cap;
   } else {
@@ -252,7 +250,6 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
     m.nblk = (int)h->part_t.blk.size() - 1;
     m.xcd_chunk = h->spmm_xcd_chunk;
     m.bpart = h->bpart_t;
-    m.style = h->spmm_style;
     m.nnz_cap = h->part_t.nnz_cap;
     m.rows_cap = h->part_t.rows_cap;
   }
@@ -616,7 +613,6 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   h->caps.blocks = std::max(8, env_int("BICGSTAB_GRID_CAP", 512));
   h->caps.dot_blocks = std::max(1, std::min(4096, env_int("BICGSTAB_DOT_GRID", 512)));
   h->spmm_xcd_chunk = std::max(1, env_int("BICGSTAB_SPMM_XCD_CHUNK", 1));
-  h->spmm_style = env_int("BICGSTAB_SPMM_STYLE", 1) == 0 ? 0 : 1;
   h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
   h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;
   std::string err;

@@ -174,7 +174,6 @@ struct SpmmMat {
   int rows_cap;  // rows of the largest row block
   int xcd_chunk; // consecutive row blocks given to one XCD (1: plain round-robin order)
   double* bpart; // per-row-block partial sums of a product with a dot epilogue (nblk x 3k)
-  int style;     // inner loop: 0 guarded slots, 1 branch-free slots
 };
 
 struct SpmmPartition {

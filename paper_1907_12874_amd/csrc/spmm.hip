@@ -6,11 +6,12 @@
 // (kp = k rounded up to a power of two) computes Y[i, c] for its rows. A lane
 // takes its rows two at a time and issues the X gathers of both (up to 16)
 // before it adds any of them; the products of a row are added in entry order,
-// the rounding of a plain sequential sum. The matrix value of a product is
-// read from LDS when it is used (not held in registers through the gather),
-// and X is addressed by 32-bit offsets from a uniform base when the block
-// fits, which keeps the register count, and so the number of workgroups in
-// flight per compute unit, up.
+// the rounding of a plain sequential sum. Two forms of that inner loop
+// (measured on the 128^3 stencil, k = 1..32): the plain product guards each
+// slot and reads a product's value with its column index (STYLE 0, fastest
+// there); the product with a dot epilogue uses branch-free slots with 32-bit
+// gather offsets (STYLE 1), which keeps its register count, and so the
+// workgroups in flight per compute unit, up.
 //
 // The same row-block body serves the sparse product with a dot epilogue
 // (beyond the paper's grouping: dots of the written rows formed in the
@@ -305,9 +306,7 @@ template <class T>
 hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
-  if (A.style == 0) return spmm_launch_bs<T, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
-  if (off32(A, k, sizeof(T))) return spmm_launch_bs<T, kSpmmBlock, true, 1>(A, x, y, k, glob, s);
-  return spmm_launch_bs<T, kSpmmBlock, false, 1>(A, x, y, k, glob, s);
+  return spmm_launch_bs<T, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
 }
 
 template <class T>
@@ -317,11 +316,6 @@ hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const voi
   T* y = static_cast<T*>(Y);
   const T* w = static_cast<const T*>(W);
   const bool o32 = off32(A, k, sizeof(T));
-  if (A.style == 0) {
-    if (epi == E_DOT_W) return spmm_dot_launch<T, kSpmmBlock, false, 0, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
-    if (epi == E_PPT) return spmm_dot_launch<T, kSpmmBlock, false, 0, E_PPT>(A, x, y, w, k, bpart, glob, s);
-    return hipErrorInvalidValue;
-  }
   if (epi == E_DOT_W)
     return o32 ? spmm_dot_launch<T, kSpmmBlock, true, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s)
                : spmm_dot_launch<T, kSpmmBlock, false, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
