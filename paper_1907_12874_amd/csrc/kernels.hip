@@ -699,6 +699,10 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
           v[u][i] = ((Op::XIN >> i) & 1) ? ldv<double>(a.in[i], e) : ldv<T>(a.in[i], e);
         if constexpr (Op::USE_D) v[u][Op::NIN] = ldv<T>(a.diag, (size_t)(row + u * stride));
       }
+      // passes with dot products: keep every load of the step ahead of the
+      // arithmetic (the scheduler otherwise sinks loads next to their use,
+      // fewer registers but one memory latency per row instead of per step)
+      if constexpr (Op::NDOT > 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const size_t e = (size_t)(row + u * stride) * k + c;
