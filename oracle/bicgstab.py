@@ -37,6 +37,16 @@ Section 1):
   t_{j+1} = A w-hat_{j+1}.
 * Pipelined "previous" vectors are zero before the first pass, with
   beta_{-1} = 0 and omega_{-1} = 1.
+* Improved BiCGStab (Alg. 3) is taken as printed (the paper notes two
+  corrections it took from another code base; the printed listing includes
+  them). Its scalars rho_{j+1}, delta_{j+1}, beta_{j+1}, tau_{j+1} and
+  alpha_{j+1} are formed at the start of pass j: rho_{j+1} = 0 or
+  tau_{j+1} = 0 stops the column as BREAKDOWN, and a non-finite delta, beta,
+  tau or alpha as NONFINITE, both before any update of that pass (the pass
+  counts as entered). kappa = 0 sets omega = 0; a non-finite omega, sigma or
+  stop estimate nu - omega*theta stops the column as NONFINITE before the x
+  and r updates; otherwise the updates are applied, then the stop test, then
+  omega = 0 gives BREAKDOWN. Alg. 3 has no preconditioned form in the paper.
 """
 from __future__ import annotations
 
@@ -257,6 +267,64 @@ def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     return ColumnResult(x, r, maxit, MAXIT, trace)
 
 
+# -------------------------------------------------------------- improved ---
+
+def alg3_merged_ibicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False):
+    """Alg. 3: merged Improved BiCGStab, one grouped reduction of seven dot
+    products per pass. f_0 = A^T r_0 is formed once; sigma_j equals
+    (r_0, A r_j) and rho_{j+1} equals (r_0, r_j) in exact arithmetic, and the
+    stop estimate nu - omega*theta equals (r_{j+1}, r_{j+1})."""
+    rec = _Recorder(trace, trace_vectors)
+    early, x, r, _, eps2 = _begin(A, b, x0, tol)
+    if early is not None:
+        return early
+    r0 = r.copy()
+    u = A @ r
+    f0 = A.T @ r0
+    q = np.zeros_like(r)
+    v = np.zeros_like(r)
+    z = np.zeros_like(r)
+    sigma_prev, pi, tau = 0.0, 0.0, 0.0
+    sigma = dot(r0, u)
+    rho = alpha = omega = 1.0
+    phi = dot(r0, r0)
+    for j in range(maxit):
+        rho1 = phi - omega * sigma_prev + omega * alpha * pi
+        delta = (rho1 / rho) * alpha
+        beta = delta / omega
+        tau = sigma + beta * tau - delta * pi
+        if rho1 == 0.0 or tau == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        alpha1 = rho1 / tau
+        if not (np.isfinite(delta) and np.isfinite(beta) and np.isfinite(tau) and np.isfinite(alpha1)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        z = alpha1 * r + (beta * (alpha1 / alpha)) * z - (alpha1 * delta) * v
+        v = u + beta * v - delta * q
+        s = r - alpha1 * v
+        q = A @ v
+        t = u - alpha1 * q
+        phi, pi = dot(r0, s), dot(r0, q)
+        gamma, eta = dot(f0, s), dot(f0, t)
+        theta, kappa, nu = dot(s, t), dot(t, t), dot(s, s)
+        omega = theta / kappa if kappa != 0.0 else 0.0
+        sigma_new = gamma - omega * eta
+        est = nu - omega * theta
+        if not (np.isfinite(omega) and np.isfinite(sigma_new) and np.isfinite(est)):
+            return ColumnResult(x, r, j + 1, NONFINITE, trace)
+        r = s - omega * t
+        x = x + z + omega * s
+        rec(j, {"alpha": alpha1, "omega": omega, "rho": rho1, "est": est, "sigma": sigma_new, "tau": tau},
+            x=x, r=r)
+        if est < eps2:
+            return ColumnResult(x, r, j + 1, CONVERGED, trace)
+        if omega == 0.0:
+            return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        u = A @ r
+        sigma_prev, sigma = sigma, sigma_new
+        alpha, rho = alpha1, rho1
+    return ColumnResult(x, r, maxit, MAXIT, trace)
+
+
 # ------------------------------------------------------------- reordered ---
 
 def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
@@ -441,7 +509,7 @@ def alg7_merged_ppipebicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vect
 
 # -------------------------------------------------------------- dispatch ---
 
-VARIANTS = ("classical", "reordered", "pipelined")
+VARIANTS = ("classical", "reordered", "pipelined", "improved")
 FORMULATIONS = ("merged", "basic", "fused")
 PRECONDS = ("none", "jacobi")
 
@@ -465,6 +533,11 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
         raise ValueError(f"unknown method {variant}/{formulation}/{precond}")
     if formulation == "fused":
         formulation = "merged"
+    if variant == "improved":
+        # Alg. 3; its basic form runs the same statements one per pass
+        if precond != "none":
+            raise ValueError("Improved BiCGStab has no preconditioned form in the paper")
+        return alg3_merged_ibicgstab(A, b, x0, tol, maxit, trace=trace, trace_vectors=trace_vectors)
     if precond == "jacobi":
         Minv = jacobi_preconditioner(A)
     else:

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import oracle
 from oracle import BREAKDOWN, CONVERGED, MAXIT, NONFINITE, solve, solve_column
 from oracle import bicgstab as ob
 from oracle import model as om
@@ -295,3 +296,73 @@ def test_paper_model_tables():
             for m, v in zip(mach["m"], vals):
                 t = om.iteration_time(meth, N, m, C, B)
                 assert abs(t - v) / v < 0.03, (meth, m, t, v)
+
+
+# ------------------------------------------------- Improved BiCGStab (Alg. 3) ---
+
+def _ib_problem(seed=1, g=10):
+    A = conv_diff(g, 3, (1.0, -0.6, 0.4))
+    b, xs = manufactured_rhs(A, 1, seed=seed)
+    return A.to_scipy(), b[:, 0], xs[:, 0]
+
+
+def test_improved_equals_classical_in_exact_arithmetic():
+    """Alg. 3 is an algebraic rearrangement of BiCGStab: pass by pass, its
+    alpha_{j+1}, omega_{j+1}, rho_{j+1} and iterate equal the classical
+    method's alpha_j, omega_j, rho_j and iterate up to rounding. A dropped
+    term or wrong index in any of its scalar recurrences breaks this at once."""
+    S, b, _ = _ib_problem()
+    ib = oracle.solve_column(S, b, variant="improved", tol=0.0, maxit=12, trace=[], trace_vectors=True)
+    cl = oracle.solve_column(S, b, variant="classical", tol=0.0, maxit=12, trace=[], trace_vectors=True)
+    for j in range(12):
+        for key in ("alpha", "omega", "rho"):
+            a, c = ib.trace[j][key], cl.trace[j][key]
+            assert abs(a - c) <= 1e-9 * abs(c), (j, key, a, c)
+        xi, xc = ib.trace[j]["vec"]["x"], cl.trace[j]["vec"]["x"]
+        assert np.linalg.norm(xi - xc) <= 1e-9 * np.linalg.norm(xc), j
+
+
+def test_improved_invariants():
+    """rho_{j+1} = (r_0, r_j), sigma_{j+1} = (r_0, A r_{j+1}) and the stop
+    estimate nu - omega theta = (r_{j+1}, r_{j+1}) hold along the run (they
+    are what the recurrences replace)."""
+    S, b, _ = _ib_problem(seed=2)
+    res = oracle.solve_column(S, b, variant="improved", tol=0.0, maxit=15, trace=[], trace_vectors=True)
+    r0 = b.copy()  # x0 = 0
+    prev_r = r0
+    for j, t in enumerate(res.trace):
+        r = t["vec"]["r"]
+        assert abs(t["rho"] - r0 @ prev_r) <= 1e-8 * abs(r0 @ r0), (j, t["rho"], r0 @ prev_r)
+        ar = S @ r
+        assert abs(t["sigma"] - r0 @ ar) <= 1e-8 * np.linalg.norm(r0) * np.linalg.norm(ar), j
+        assert abs(t["est"] - r @ r) <= 1e-8 * (r0 @ r0), (j, t["est"], r @ r)
+        prev_r = r
+
+
+def test_improved_dense_solve_and_edges():
+    S, b, xs = _ib_problem(seed=3, g=6)
+    res = oracle.solve_column(S, b, variant="improved", tol=1e-12, maxit=500)
+    assert res.status == oracle.CONVERGED
+    xd = np.linalg.solve(S.toarray(), b)
+    assert np.linalg.norm(res.x - xd) <= 1e-9 * np.linalg.norm(xd)
+    # b = 0: x = 0 after 0 passes; maxit = 0: MAXIT, x unchanged
+    z = oracle.solve_column(S, np.zeros_like(b), np.ones_like(b), variant="improved")
+    assert z.status == oracle.CONVERGED and z.iters == 0 and np.all(z.x == 0)
+    m = oracle.solve_column(S, b, variant="improved", tol=1e-12, maxit=0)
+    assert m.status == oracle.MAXIT and m.iters == 0 and np.all(m.x == 0)
+    with pytest.raises(ValueError):
+        oracle.solve_column(S, b, variant="improved", precond="jacobi")
+
+
+def test_improved_scaled_identity_one_pass():
+    """A = 2I: alpha_1 = 1/2 makes s = 0 and t = 0, so kappa = 0 (omega = 0)
+    and the estimate nu - omega theta = 0: converged in one pass with the
+    exact solution x = b / 2."""
+    import scipy.sparse as sp
+
+    n = 40
+    S = sp.identity(n, format="csr") * 2.0
+    b = np.random.default_rng(4).uniform(-1, 1, n)
+    res = oracle.solve_column(S, b, variant="improved", tol=1e-10, maxit=10)
+    assert res.status == oracle.CONVERGED and res.iters == 1
+    assert np.array_equal(res.x, b * 0.5)
