@@ -43,7 +43,8 @@ PEAK_HBM_GBPS = 8000.0
 OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
     "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g1", "pp_g2", "pp_g3", "pp_g4",
-    "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h",
+    "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h", "ib_init", "ib_g1", "ib_g2",
+    "ib_g3", "ib_z", "ib_v", "ib_x",
 ]
 
 
@@ -405,7 +406,8 @@ def main():
                 continue
             x0k = torch.zeros_like(bk)
             xk = torch.empty_like(bk)
-            for variant in ("classical", "reordered", "pipelined"):
+            variants = ("classical", "reordered", "pipelined") + (("improved",) if args.precond == "none" else ())
+            for variant in variants:
                 for form in ("merged", "basic", "fused") if variant == "classical" else ("merged", "basic"):
                     sv = pk.Solver.from_csr(A, kk, variant=variant, formulation=form, precond=args.precond, device=dev)
                     tr = pk.plan_traffic(variant, form, args.precond)
@@ -440,7 +442,7 @@ def main():
         out["sweep"] = sweep
         gains, fusion = {}, {}
         for kk in ks:
-            for variant in ("classical", "reordered", "pipelined"):
+            for variant in ("classical", "reordered", "pipelined", "improved"):
                 m = [r for r in sweep if r["k"] == kk and r["variant"] == variant]
                 mb = {r["formulation"]: r for r in m}
                 if "merged" in mb and "basic" in mb:

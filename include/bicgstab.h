@@ -8,6 +8,7 @@
  *   - classical BiCGStab            (Appendix B, Alg. 1 basic; Alg. 2 / Alg. 5 merged)
  *   - Reordered BiCGStab            (Appendix B, Alg. 6)
  *   - Pipelined BiCGStab            (Appendix B, Alg. 4 / Alg. 7)
+ *   - Improved BiCGStab             (Appendix B, Alg. 3)
  * each in the "basic" form (one memory pass per vector operation, the Basic
  * columns of Table 2) and the "merged" form (the operations of one listing
  * line share one pass, the Merged columns of Table 2), optionally with a
@@ -55,8 +56,11 @@ enum {
   BICGSTAB_EUNSUPPORTED = -4 /* valid but unsupported combination */
 };
 
-/* Methods (Appendix B). */
-enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2 };
+/* Methods (Appendix B). Improved BiCGStab (Alg. 3: one grouped reduction of
+ * seven dot products per pass, f0 = A^T r0 formed once from a transposed CSR
+ * built on the device) has no preconditioned form in the paper and runs in
+ * FP64 only; other combinations return BICGSTAB_EUNSUPPORTED. */
+enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2, BICGSTAB_IMPROVED = 3 };
 /* Formulations: merged = Table 2 "Merged" grouping, basic = Table 2 "Basic";
  * fused = the merged grouping with the further fusions only a single device
  * allows (the Jacobi scaling folded into the products and updates, adjacent

@@ -7,7 +7,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbicgstab.so")
 
 OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
-VARIANTS = {"classical": 0, "reordered": 1, "pipelined": 2}
+VARIANTS = {"classical": 0, "reordered": 1, "pipelined": 2, "improved": 3}
 FORMULATIONS = {"merged": 0, "basic": 1, "fused": 2}
 PRECONDS = {"none": 0, "jacobi": 1}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}

@@ -128,6 +128,14 @@ namespace {
 
 bool fp32_inner(const bicgstab_ctx* h) { return h->precision == BICGSTAB_FP32_REFINE; }
 
+// The plan has a product with the transposed matrix (built at first use).
+bool has_spmm_t(const bicgstab_ctx* h) {
+  for (const auto* list : {&h->plan.init, &h->plan.iter})
+    for (const Step& st : *list)
+      if (st.kind == K_SPMM_T) return true;
+  return false;
+}
+
 // The plan has sparse products with a dot epilogue (they need row-block partials).
 bool has_spmm_dot(const bicgstab_ctx* h) {
   for (const auto* list : {&h->plan.init, &h->plan.iter})
@@ -202,6 +210,8 @@ void clear_graphs(bicgstab_ctx* h) {
   h->graphs.clear();
 }
 
+int build_transpose(bicgstab_ctx* h);
+
 int prepare(bicgstab_ctx* h) {
   if (h->prepared) return BICGSTAB_OK;
   if (!h->base) {
@@ -225,6 +235,10 @@ int prepare(bicgstab_ctx* h) {
   }
   if (fp32_inner(h)) HIPCHK(launch_convert_f32(h->val, h->val32, h->nnz, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
+  if (has_spmm_t(h) && h->n > 0) {
+    const int rc = build_transpose(h);
+    if (rc) return rc;
+  }
   h->prepared = true;
   return BICGSTAB_OK;
 }
@@ -262,6 +276,11 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* 
   switch (st.kind) {
     case K_SPMM:
       return launch_spmm(M, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
+    case K_SPMM_T: {
+      // the other matrix of the pair (A, A^T): A^T when solving with A
+      const SpmmMat Mt = mat_of(h, M.blk == h->blk ? 1 : 0, fp32);
+      return launch_spmm(Mt, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
+    }
     case K_SPMM_DOT:
       return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], vp[st.in[1]], st.op, h->k, fp32, ctl, st.slot, st.fin,
                              M.bpart, s);
@@ -592,6 +611,10 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
     return fail(BICGSTAB_EINVAL, "unknown precision");
   if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL)
     return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical method only");
+  if (variant == BICGSTAB_IMPROVED && precond != BICGSTAB_PRECOND_NONE)
+    return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
+  if (variant == BICGSTAB_IMPROVED && precision != BICGSTAB_FP64)
+    return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab runs in FP64 only");
   if (n > 0 && (!A->d_row_ptr || (A->nnz > 0 && (!A->d_col_idx || !A->d_values))))
     return fail(BICGSTAB_EINVAL, "null matrix array");
   bicgstab_ctx* h = new bicgstab_ctx();

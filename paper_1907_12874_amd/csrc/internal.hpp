@@ -27,11 +27,19 @@ enum ScalarSlot {
   S_RELRES_REC,
   S_RHONEXT,
   S_SCALE,  // refinement: ||r_c|| of the outer residual
+  S_DELTA,       // Improved BiCGStab (Alg. 3): delta_{j+1}
+  S_TAU,         //   tau_{j+1}
+  S_SIGMA,       //   sigma_j
+  S_SIGMA_PREV,  //   sigma_{j-1}
+  S_C1,          //   beta_{j+1} alpha_{j+1} / alpha_j (z update)
+  S_C2,          //   alpha_{j+1} delta_{j+1} (z update)
   S_D0,  // dot results D0..D6 follow
   S_NSCAL = S_D0 + 7
 };
 // ---- per-column ints ist[slot * kMaxK + c] ------------------------------------
-enum IntSlot { I_STATUS = 0, I_PEND, I_ITERS, I_ZEROB, I_NINT };
+// I_PEND_NEXT: a stop found while forming the next pass's scalars (Alg. 3),
+// taken when that pass would start.
+enum IntSlot { I_STATUS = 0, I_PEND, I_ITERS, I_ZEROB, I_PEND_NEXT, I_NINT };
 // ---- globals -----------------------------------------------------------------
 struct Globals {
   int nrun;      // columns with status RUNNING; every iteration kernel exits at once when 0
@@ -67,6 +75,10 @@ enum FinStep {
   F_PIPE_BETA_END,  // D3=rho' D4=psi D5=sigma D6=delta: beta, alpha_{j+1}, close
   F_EXIT,           // D0=||b-Ax||^2 D1=||r||^2: relative residuals
   F_REFINE_NORM,    // refinement: D0=||r||^2, D1=||b||^2 of the outer residual
+  F_IB_INIT,        // Alg. 3: D0=sigma_0=(r0,u0) D1=phi_0=(r0,r0): the first pass's scalars
+  F_IB_OMEGA,       // Alg. 3: D0..D6 = phi, pi, gamma, eta, theta, kappa, nu: omega, sigma,
+                    //   stop test, then the next pass's rho, delta, beta, tau, alpha
+  F_IB_END,         // Alg. 3: close the iteration (a pending stop, or the next pass's)
 };
 
 // Pointers to the per-solve device state, passed by value to kernels.
@@ -113,6 +125,13 @@ enum OpId {
   OP_F_SUB_ALPHA_H,  // fused Jacobi: s = r - alpha v; sh = s / a_ii
   OP_F_PUPD_H,       // fused Jacobi: p = r + beta (p - omega v); ph = p / a_ii
   OP_F_XR_RHO_H,     // fused Jacobi: x += alpha ph + omega sh; r = s - omega t; dot (r, r0)
+  OP_IB_INIT,        // Alg. 3 start: dots (r0, u), (r0, r0)
+  OP_IB_G1,          // Alg. 3: z, v, s updates
+  OP_IB_G2,          // Alg. 3: t = u - alpha q and the seven dots
+  OP_IB_G3,          // Alg. 3: r = s - omega t; x = x + z + omega s
+  OP_IB_Z,           // Alg. 3 basic: z = alpha r + c1 z - c2 v
+  OP_IB_V,           // Alg. 3 basic: v = u + beta v - delta q
+  OP_IB_X,           // Alg. 3 basic: x = x + z + omega s
   OP_NUM
 };
 
@@ -127,7 +146,8 @@ enum VecId {
 
 // K_SPMM_DOT: a sparse product whose epilogue also forms dot products of the
 // rows it writes (op = SpmmEpilogue, in[1] = the second operand).
-enum StepKind { K_SPMM = 0, K_PREC, K_GROUP, K_SPMM_DOT };
+// K_SPMM_T: the product with the transposed matrix (Alg. 3's f0 = A^T r0).
+enum StepKind { K_SPMM = 0, K_PREC, K_GROUP, K_SPMM_DOT, K_SPMM_T };
 
 enum SpmmEpilogue {
   E_DOT_W = 0,  // y = A x; dot (y, w)

@@ -47,6 +47,7 @@ __host__ __device__ inline int pad_k(int k) {
 
 struct Coef {
   double alpha, omega, beta, scale;
+  double delta, c1, c2;  // Alg. 3 updates
 };
 
 // ------------------------------------------------------------ op bodies ---
@@ -317,6 +318,58 @@ struct KFXrRhoH {  // in: x, ph, sh, s, t, r0 ; out: x, r ; (r, r0)
   }
 };
 
+// Improved BiCGStab (Alg. 3). Coefficients: alpha = alpha_{j+1}, beta, delta,
+// c1 = beta alpha_{j+1} / alpha_j, c2 = alpha_{j+1} delta, omega = omega_{j+1}.
+struct KIbInit {  // in: r0, u ; (r0, u), (r0, r0)
+  OP_HEAD(2, 0, 2, 0, 0, PART_RUN, true)
+  OP_F {
+    a[0] += v[0] * v[1];
+    a[1] += v[0] * v[0];
+  }
+};
+struct KIbG1 {  // in: r, z, v, u, q ; out: z, v, s
+  OP_HEAD(5, 3, 0, 0, 0, PART_RUN, true)
+  OP_F {
+    o[0] = c.alpha * v[0] + c.c1 * v[1] - c.c2 * v[2];  // z = alpha r + c1 z - c2 v
+    const double vn = R(v[3] + c.beta * v[2] - c.delta * v[4]);  // v = u + beta v - delta q
+    o[1] = vn;
+    o[2] = v[0] - c.alpha * vn;  // s = r - alpha v
+  }
+};
+struct KIbG2 {  // in: u, q, r0, s, f0 ; out: t ; phi, pi, gamma, eta, theta, kappa, nu
+  OP_HEAD(5, 1, 7, 0, 0, PART_RUN, true)
+  OP_F {
+    const double t = R(v[0] - c.alpha * v[1]);
+    o[0] = t;
+    a[0] += v[2] * v[3];  // (r0, s)
+    a[1] += v[2] * v[1];  // (r0, q)
+    a[2] += v[4] * v[3];  // (f0, s)
+    a[3] += v[4] * t;     // (f0, t)
+    a[4] += v[3] * t;     // (s, t)
+    a[5] += t * t;        // (t, t)
+    a[6] += v[3] * v[3];  // (s, s)
+  }
+};
+struct KIbG3 {  // in: s, t, x, z ; out: r, x
+  OP_HEAD(4, 2, 0, 4, 2, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] - c.omega * v[1];         // r = s - omega t
+    o[1] = v[2] + v[3] + c.omega * v[0];  // x = x + z + omega s
+  }
+};
+struct KIbZ {  // in: r, z, v ; out: z
+  OP_HEAD(3, 1, 0, 0, 0, PART_RUN, true)
+  OP_F { o[0] = c.alpha * v[0] + c.c1 * v[1] - c.c2 * v[2]; }
+};
+struct KIbV {  // in: u, v, q ; out: v
+  OP_HEAD(3, 1, 0, 0, 0, PART_RUN, true)
+  OP_F { o[0] = v[0] + c.beta * v[1] - c.delta * v[2]; }
+};
+struct KIbX {  // in: x, z, s ; out: x
+  OP_HEAD(3, 1, 0, 1, 1, PART_RUN, true)
+  OP_F { o[0] = v[0] + v[1] + c.omega * v[2]; }
+};
+
 // ------------------------------------------------------- scalar recurrence ---
 
 __device__ __forceinline__ double& SC(const Ctl& C, int slot, int c) { return C.sc[slot * kMaxK + c]; }
@@ -347,6 +400,29 @@ __device__ void end_column(const Ctl& C, int c) {
   }
 }
 
+// Alg. 3: the scalars that open a pass, from phi, pi, omega of the pass before
+// and sigma_{j-1}, sigma_j, rho_j, alpha_j, tau_j; stored for the pass's
+// updates. Returns -1, or the stop the pass would take (BREAKDOWN on a zero
+// rho_{j+1} or tau_{j+1}, NONFINITE on a non-finite scalar).
+__device__ int ib_open_pass(const Ctl& C, int c, double phi, double pi, double omega, double sigma_prev,
+                            double sigma, double rho, double alpha, double tau) {
+  const double rho1 = phi - omega * sigma_prev + omega * alpha * pi;
+  const double delta = (rho1 / rho) * alpha;
+  const double beta = delta / omega;
+  const double tau1 = sigma + beta * tau - delta * pi;
+  if (rho1 == 0.0 || tau1 == 0.0) return ST_BREAKDOWN;
+  const double alpha1 = rho1 / tau1;
+  if (!(isfinite(delta) && isfinite(beta) && isfinite(tau1) && isfinite(alpha1))) return ST_NONFINITE;
+  SC(C, S_RHO, c) = rho1;
+  SC(C, S_DELTA, c) = delta;
+  SC(C, S_BETA, c) = beta;
+  SC(C, S_TAU, c) = tau1;
+  SC(C, S_C1, c) = beta * (alpha1 / alpha);
+  SC(C, S_C2, c) = alpha1 * delta;
+  SC(C, S_ALPHA, c) = alpha1;
+  return -1;
+}
+
 // Per-column scalar work of a finalize step (see the FinStep list).
 __device__ void finalize_column(int step, int c, const Ctl& C) {
   int& st = IS(C, I_STATUS, c);
@@ -356,6 +432,7 @@ __device__ void finalize_column(int step, int c, const Ctl& C) {
     const double rr = D0, bb = D1;
     SC(C, S_BB, c) = bb;
     IS(C, I_PEND, c) = -1;
+    IS(C, I_PEND_NEXT, c) = -1;
     IS(C, I_ITERS, c) = 0;
     IS(C, I_ZEROB, c) = 0;
     SC(C, S_ALPHA, c) = 0.0;
@@ -514,6 +591,54 @@ __device__ void finalize_column(int step, int c, const Ctl& C) {
       SC(C, S_RHONEXT, c) = rho1;
       return;
     }
+    case F_IB_INIT: {
+      // sigma_{-1} = pi_0 = tau_0 = 0, rho_0 = alpha_0 = omega_0 = 1
+      const double sigma0 = D0, phi0 = D1;
+      SC(C, S_SIGMA_PREV, c) = 0.0;
+      SC(C, S_SIGMA, c) = sigma0;
+      SC(C, S_OMEGA, c) = 1.0;
+      const int bad = ib_open_pass(C, c, phi0, 0.0, 1.0, 0.0, sigma0, 1.0, 1.0, 0.0);
+      // the first pass is entered and stops before its updates (unless maxit = 0)
+      if (bad >= 0 && C.glob->maxit > 0) stop(bad);
+      return;
+    }
+    case F_IB_OMEGA: {
+      const double phi = D0, pi = D1, gamma = D2, eta = D3;
+      const double theta = SC(C, S_D0 + 4, c), kappa = SC(C, S_D0 + 5, c), nu = SC(C, S_D0 + 6, c);
+      const double omega = kappa != 0.0 ? theta / kappa : 0.0;
+      const double sigma1 = gamma - omega * eta;
+      const double est = nu - omega * theta;
+      if (!(isfinite(omega) && isfinite(sigma1) && isfinite(est))) {
+        stop(ST_NONFINITE);
+        return;
+      }
+      SC(C, S_OMEGA, c) = omega;
+      SC(C, S_EST, c) = est;
+      record_history(C, c, SC(C, S_ALPHA, c), omega, SC(C, S_RHO, c), est);
+      if (est < eps2)
+        pend = ST_CONVERGED;
+      else if (omega == 0.0)
+        pend = ST_BREAKDOWN;
+      const double sigma = SC(C, S_SIGMA, c);
+      if (pend < 0)
+        IS(C, I_PEND_NEXT, c) = ib_open_pass(C, c, phi, pi, omega, sigma, sigma1, SC(C, S_RHO, c),
+                                             SC(C, S_ALPHA, c), SC(C, S_TAU, c));
+      SC(C, S_SIGMA_PREV, c) = sigma;
+      SC(C, S_SIGMA, c) = sigma1;
+      return;
+    }
+    case F_IB_END: {
+      // a stop found when forming the next pass's scalars is taken as that
+      // pass starts (it counts as entered), unless maxit ends the solve first
+      const int nx = IS(C, I_PEND_NEXT, c);
+      if (pend < 0 && nx >= 0 && it1 < C.glob->maxit) {
+        st = nx;
+        IS(C, I_ITERS, c) = it1 + 1;
+        return;
+      }
+      end_column(C, c);
+      return;
+    }
     case F_END: {
       record_history(C, c, SC(C, S_ALPHA, c), SC(C, S_OMEGA, c), SC(C, S_RHO, c), SC(C, S_EST, c));
       if (pend < 0) SC(C, S_RHO, c) = SC(C, S_RHONEXT, c);
@@ -585,7 +710,7 @@ __device__ void finalize_column(int step, int c, const Ctl& C) {
 }
 
 __device__ __forceinline__ bool closes_iteration(int step) {
-  return step == F_BETA_END || step == F_END || step == F_PIPE_BETA_END;
+  return step == F_BETA_END || step == F_END || step == F_PIPE_BETA_END || step == F_IB_END;
 }
 
 // Run by thread 0 of the last workgroup after finalize_column.
@@ -685,6 +810,9 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
     cf.omega = SC(a.ctl, S_OMEGA, c);
     cf.beta = SC(a.ctl, S_BETA, c);
     cf.scale = SC(a.ctl, S_SCALE, c);
+    cf.delta = SC(a.ctl, S_DELTA, c);
+    cf.c1 = SC(a.ctl, S_C1, c);
+    cf.c2 = SC(a.ctl, S_C2, c);
     const int rpb = BS >> kpl;
     const long n = a.n;
     const long stride = (long)gridDim.x * rpb;
@@ -791,6 +919,13 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_F_SUB_ALPHA_H: return launch_op<KFSubAlphaH, T>(a, grid_cap, s);
     case OP_F_PUPD_H: return launch_op<KFPUpdH, T>(a, grid_cap, s);
     case OP_F_XR_RHO_H: return launch_op<KFXrRhoH, T>(a, grid_cap, s);
+    case OP_IB_INIT: return launch_op<KIbInit, T>(a, grid_cap, s);
+    case OP_IB_G1: return launch_op<KIbG1, T>(a, grid_cap, s);
+    case OP_IB_G2: return launch_op<KIbG2, T>(a, grid_cap, s);
+    case OP_IB_G3: return launch_op<KIbG3, T>(a, grid_cap, s);
+    case OP_IB_Z: return launch_op<KIbZ, T>(a, grid_cap, s);
+    case OP_IB_V: return launch_op<KIbV, T>(a, grid_cap, s);
+    case OP_IB_X: return launch_op<KIbX, T>(a, grid_cap, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -50,6 +50,13 @@ const OpInfo kOps[OP_NUM] = {
     {2, 2, 0, "f_sub_alpha_h"},  // OP_F_SUB_ALPHA_H (+ the diagonal)
     {3, 2, 0, "f_pupd_h"},       // OP_F_PUPD_H (+ the diagonal)
     {6, 2, 1, "f_xr_rho_h"},     // OP_F_XR_RHO_H
+    {2, 0, 2, "ib_init"},        // OP_IB_INIT
+    {5, 3, 0, "ib_g1"},          // OP_IB_G1
+    {5, 1, 7, "ib_g2"},          // OP_IB_G2
+    {4, 2, 0, "ib_g3"},          // OP_IB_G3
+    {3, 1, 0, "ib_z"},           // OP_IB_Z
+    {3, 1, 0, "ib_v"},           // OP_IB_V
+    {3, 1, 0, "ib_x"},           // OP_IB_X
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -83,6 +90,14 @@ Step SPMM_DOT(int x, int y, int epi, int w, int slot, int fin) {
   Step s = G(OP_COPY, {x, w}, {y}, slot, fin);
   s.kind = K_SPMM_DOT;
   s.op = epi;
+  return s;
+}
+
+// y = A^T x (the transposed matrix).
+Step SPMM_T(int in, int out) {
+  Step s = G(OP_COPY, {in}, {out});
+  s.kind = K_SPMM_T;
+  s.op = -1;
   return s;
 }
 
@@ -308,6 +323,44 @@ void pipelined(int formulation, int precond, Plan* P) {
   }
 }
 
+// -------------------------------------------------------------- improved ---
+// Alg. 3. Vectors: u -> V_W, f0 -> V_Y, q -> V_Q, plus r, r0, v, z, s, t.
+// Merged: one pass per grouped line ({z, v, s}, {t and the seven dots},
+// {r, x}); basic: one pass per statement, each dot its own pass (Tab. 2:
+// 14 / 6 and 27 / 6 block reads / writes).
+void improved(int formulation, Plan* P) {
+  auto& in = P->init;
+  in = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X}),
+        SPMM(V_R, V_W),                                   // u0 = A r0
+        SPMM_T(V_R0, V_Y),                                // f0 = A^T r0
+        G(OP_IB_INIT, {V_R0, V_W}, {}, 0, F_IB_INIT)};    // sigma_0, phi_0
+  for (int v : {V_Q, V_V, V_Z}) in.push_back(G(OP_FILL0, {}, {v}));
+  auto& it = P->iter;
+  if (formulation == 0) {
+    it.push_back(G(OP_IB_G1, {V_R, V_Z, V_V, V_W, V_Q}, {V_Z, V_V, V_S}));
+    it.push_back(SPMM(V_V, V_Q));
+    it.push_back(G(OP_IB_G2, {V_W, V_Q, V_R0, V_S, V_Y}, {V_T}, 0, F_IB_OMEGA));
+    it.push_back(G(OP_IB_G3, {V_S, V_T, V_X, V_Z}, {V_R, V_X}, 0, F_IB_END));
+  } else {
+    it.push_back(G(OP_IB_Z, {V_R, V_Z, V_V}, {V_Z}));
+    it.push_back(G(OP_IB_V, {V_W, V_V, V_Q}, {V_V}));
+    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_S}));   // s = r - alpha v
+    it.push_back(SPMM(V_V, V_Q));
+    it.push_back(G(OP_SUB_ALPHA, {V_W, V_Q}, {V_T}));   // t = u - alpha q
+    it.push_back(G(OP_DOT, {V_R0, V_S}, {}, 0));        // phi
+    it.push_back(G(OP_DOT, {V_R0, V_Q}, {}, 1));        // pi
+    it.push_back(G(OP_DOT, {V_Y, V_S}, {}, 2));         // gamma
+    it.push_back(G(OP_DOT, {V_Y, V_T}, {}, 3));         // eta
+    it.push_back(G(OP_DOT, {V_S, V_T}, {}, 4));         // theta
+    it.push_back(G(OP_DOTSELF, {V_T}, {}, 5));          // kappa
+    it.push_back(G(OP_DOTSELF, {V_S}, {}, 6, F_IB_OMEGA));  // nu
+    it.push_back(G(OP_SUB_OMEGA, {V_S, V_T}, {V_R}));   // r = s - omega t
+    it.push_back(G(OP_IB_X, {V_X, V_Z, V_S}, {V_X}, 0, F_IB_END));
+  }
+  it.push_back(SPMM(V_R, V_W));  // u = A r
+  P->vecs = {V_R, V_R0, V_W, V_Y, V_Q, V_V, V_Z, V_S, V_T};
+}
+
 }  // namespace
 
 const OpInfo& op_info(int op) { return kOps[op]; }
@@ -329,10 +382,15 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
     *err = "the fused formulation is built for the classical method only";
     return false;
   }
+  if (variant == 3 && precond != 0) {
+    *err = "Improved BiCGStab has no preconditioned form";
+    return false;
+  }
   switch (variant) {
     case 0: classical(formulation, precond, P); break;
     case 1: reordered(formulation, precond, P); break;
     case 2: pipelined(formulation, precond, P); break;
+    case 3: improved(formulation, P); break;
     default: *err = "unknown variant"; return false;
   }
   // Every operand must be a vector the plan allocates (or x, b, or an alias),

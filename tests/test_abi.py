@@ -48,6 +48,7 @@ def test_binding_covers_header(L):
 # Table 2 names -> (variant, preconditioner) of this library
 TABLE2 = {
     "BiCGStab": ("classical", "none"),
+    "IBiCGStab": ("improved", "none"),
     "PipeBiCGStab": ("pipelined", "none"),
     "PBiCGStab": ("classical", "jacobi"),
     "RBiCGStab": ("reordered", "jacobi"),
@@ -107,6 +108,12 @@ def test_fused_plan_traffic(L):
     from paper_1907_12874_amd import _lib
 
     r = ctypes.c_int32()
+    # Improved BiCGStab: no preconditioned, fused or FP32 form
+    desc = _lib.CSRDesc(4, 0, None, None, None)
+    h = ctypes.c_void_p()
+    for formulation, precond, precision in ((0, 1, 0), (2, 0, 0), (0, 0, 1)):
+        assert L.bicgstab_create(ctypes.byref(desc), 4, 1, 3, formulation, precond, precision, None,
+                                 ctypes.byref(h)) == _lib.EUNSUPPORTED
     for variant in (1, 2):  # not built for the Reordered and Pipelined methods
         assert L.bicgstab_plan_traffic(variant, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
         desc = _lib.CSRDesc(4, 0, None, None, None)

@@ -32,6 +32,8 @@ pytestmark = pytest.mark.gpu
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
 # the fused form exists for the classical method; its oracle is the merged listing
 METHODS += [("classical", "fused", p) for p in ("none", "jacobi")]
+# Improved BiCGStab (Alg. 3) has no preconditioned form
+METHODS += [("improved", f, "none") for f in ("merged", "basic")]
 
 
 def say(*a):

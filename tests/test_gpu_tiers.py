@@ -102,17 +102,18 @@ def test_grad_values_kernel(lib):
         assert np.all(np.abs(g - ref) <= 16 * np.finfo(float).eps * scale * max(1, k))
 
 
-@pytest.mark.parametrize("precond,formulation", [("none", "merged"), ("jacobi", "merged"), ("jacobi", "fused")])
-def test_transpose_solve(lib, precond, formulation):
+@pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
+                                                         ("classical", "jacobi", "fused"), ("improved", "none", "merged")])
+def test_transpose_solve(lib, variant, precond, formulation):
     """A^T Lambda = G by the same method on the device-built transposed CSR
     (nonsymmetric matrix, so A vs A^T matters)."""
     import torch
 
-    say(f"transpose solve {precond} {formulation}")
+    say(f"transpose solve {variant} {precond} {formulation}")
     A = conv_diff(14, 3, (3.0, -2.0, 1.5))
     St = A.to_scipy().T.tocsr()
     G = np.random.default_rng(11).uniform(-1, 1, (A.n, 4))
-    s = lib.Solver.from_csr(A, 4, precond=precond, formulation=formulation)
+    s = lib.Solver.from_csr(A, 4, variant=variant, precond=precond, formulation=formulation)
     lam, info = s.solve_transpose(torch.from_numpy(G).cuda(), tol=1e-12, maxit=3000)
     L = lam.cpu().numpy()
     assert np.all(info.status == 0)
