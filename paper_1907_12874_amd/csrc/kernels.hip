@@ -740,24 +740,29 @@ struct GArgs {
 // multi-XCD part a device-scope release writes back the L2, and one per
 // workgroup serialises the whole pass).
 constexpr int kFinBlock = 1024;
+constexpr int kFinLanes = 16;  // finalize lanes per (dot, column) pair
 
 template <int ND, int BS>
 __device__ __forceinline__ void block_reduce_store(const double* acc, const GArgs& a) {
   store_block_partials<ND, BS>(acc, a.ctl.partials, a.k, a.kpl, gridDim.x, blockIdx.x);
 }
 
-// One workgroup: sum the nb partials of each of the P pairs (G lanes per pair
-// read consecutive workgroups' values, coalesced, then the G sums are added in
-// lane order), write the dot slots, run the finalize step. Every sum has a
-// fixed order, so results are bitwise repeatable.
+// One workgroup: sum the nb partials of each of the P pairs (lane g of the
+// kFinLanes lanes of a pair sums workgroups g, g + kFinLanes, ... in order,
+// then the lane sums are added in lane order), write the dot slots, run the
+// finalize step. Every sum has a fixed order, so results are bitwise
+// repeatable.
 __global__ __launch_bounds__(kFinBlock) void finalize_kernel(Ctl ctl, int P, int nb, int slot, int fin, int early) {
   if (early && ctl.glob->nrun == 0) return;
   __shared__ double s_g[kFinBlock];
   const int k = ctl.k;
   const int t = threadIdx.x;
   if (P > 0) {
-    const int G = P <= kFinBlock ? kFinBlock / P : 1;  // lanes per pair
-    const int PP = kFinBlock / G;                        // pairs per round
+    // a fixed number of lanes per pair, whatever P: the summation order of a
+    // dot product then depends only on the pass's grid, not on how many dots
+    // the pass forms
+    constexpr int G = kFinLanes;
+    constexpr int PP = kFinBlock / G;  // pairs per round
     for (int p0 = 0; p0 < P; p0 += PP) {
       const int p = p0 + t / G, g = t % G;
       double v = 0.0;

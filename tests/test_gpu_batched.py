@@ -8,7 +8,7 @@ workgroup size: per thread over its rows (a stride of block / kp rows through
 the workgroup's contiguous row chunk), a pairwise tree over the row slots of a
 wave, the waves in index order, then the workgroups in index order. The
 tests run the oracle with its dot product summed in that order
-(`kernel_order_dot`), which makes the whole solve reproducible bit for bit:
+(`kernel_order.batched_dot`), which makes the whole solve reproducible bit for bit:
 pass counts, statuses and iterates must be identical. The same runs with the
 oracle's own dot products stay within the summation-order envelope (checked
 in the single-system tests).
@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-import oracle.bicgstab as ob
+from kernel_order import batched_dot, oracle_dot
 from workloads import CSR, batched_systems, config_problem, conv_diff, manufactured_rhs
 
 pytestmark = pytest.mark.gpu
@@ -30,38 +30,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def kernel_order_dot(n, k, nw, block):
-    """Dot product of two length-n vectors summed in the batched kernel's
-    order for a system of n rows, k columns, nw workgroups of `block` threads."""
-    kp = 1
-    while kp < k:
-        kp *= 2
-    rpp, R, waves = block // kp, 64 // kp, block // 64
-    chunk = (n + nw - 1) // nw
-    m = (chunk + rpp - 1) // rpp
-
-    def dot(u, w):
-        p = np.zeros(nw * chunk)
-        p[:n] = np.multiply(u, w)
-        q = np.zeros((nw, m * rpp))
-        q[:, :chunk] = p.reshape(nw, chunk)
-        acc = np.add.accumulate(q.reshape(nw, m, rpp), axis=1)[:, -1, :]  # per thread, rows in order
-        t = acc.reshape(nw, waves, R)
-        while t.shape[2] > 1:  # pairwise over the row slots of a wave
-            t = t[:, :, 0::2] + t[:, :, 1::2]
-        wg = np.add.accumulate(t[:, :, 0], axis=1)[:, -1]  # waves in order
-        return float(np.add.accumulate(wg)[-1])  # workgroups in order
-
-    return dot
-
-
 def oracle_kernel_order(A, k, nw, block, *args, **kw):
-    saved = ob.dot
-    ob.dot = kernel_order_dot(A.n, k, nw, block)
-    try:
+    with oracle_dot(batched_dot(A.n, k, nw, block)):
         return oracle.solve(A.to_scipy(), *args, **kw)
-    finally:
-        ob.dot = saved
 
 
 def _batch(nsys, seed, nmin=200, nmax=5000):

@@ -1,6 +1,14 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle on
 the same seeded inputs.
 
+Bitwise. Every dot product of the non-fused plans is formed by the vector-pass
+kernel and the finalize kernel in a fixed order that depends only on n, k and
+the pass's grid; run with its dot product summed in that order
+(`kernel_order.group_dot`), the oracle reproduces the library's trajectories
+and converged solves bit for bit: pass counts, statuses, per-pass scalars and
+iterates (`test_bitwise_*`). The envelope tests below compare against the
+oracle's own summation order instead.
+
 Tolerances. The library evaluates every vector update and sparse product in
 the same order as the oracle with no fused multiply-add, and divides by a_ii
 for Jacobi, so those steps round identically; only the dot products sum in a
@@ -389,6 +397,93 @@ def test_fused_equals_merged_up_to_dot_order(lib):
             spread = max(np.linalg.norm(a.x[:, c] - ref.x[:, c]) / nref for a in alts)
             d = np.linalg.norm(xs["fused"][:, c] - xs["merged"][:, c]) / nref
             assert d <= 1e-12 + 40 * spread, (precond, c, d, spread)
+
+
+# ----------------------------------------------------------- bitwise ---
+
+from kernel_order import group_dot, oracle_dot, scheduled_dot, spmm_epilogue_dot  # noqa: E402
+
+BITWISE = [m for m in METHODS if m[1] != "fused"]
+
+
+@pytest.mark.parametrize("variant,formulation,precond", BITWISE)
+@pytest.mark.parametrize("k", [1, 5])
+def test_bitwise_fixed_passes(lib, variant, formulation, precond, k):
+    """20 passes with the stop test off: every iterate and every per-pass
+    alpha, omega, rho and stop estimate equal the oracle's in the kernels'
+    summation order."""
+    import torch
+
+    say(f"bitwise passes {variant}/{formulation}/{precond} k={k}")
+    A = conv_diff(17, 3, (1.0, 0.7, 0.3))
+    b, _ = manufactured_rhs(A, k, seed=21)
+    s = gpu_solver(lib, A, k, variant, formulation, precond)
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=0.0, maxit=20)
+    hist = s.history()
+    with oracle_dot(group_dot(A.n, k)):
+        ref = oracle.solve(A.to_scipy(), b, variant=variant, formulation=formulation, precond=precond, tol=0.0,
+                           maxit=20, trace=True)
+    X = to_np(x)
+    assert np.array_equal(info.iters, ref.iters) and np.array_equal(info.status, ref.status)
+    for c in range(k):
+        assert np.array_equal(X[:, c], ref.x[:, c]), (c, np.abs(X[:, c] - ref.x[:, c]).max())
+        for j, t in enumerate(ref.traces[c]):
+            got = tuple(hist[j, c, :])
+            want = (t["alpha"], t["omega"], t["rho"], t["est"])
+            assert got == want, (c, j, got, want)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", BITWISE)
+def test_bitwise_converged(lib, variant, formulation, precond):
+    """Solves to tolerance on the 2D recipe (64 x 64, tol 1e-10) and the 3D
+    recipe (16^3, k = 4, tol 1e-8): pass counts, statuses and solutions equal
+    the oracle's in the kernels' summation order (so also within any pass
+    count margin and relative error bar)."""
+    import torch
+
+    for cfg in (config_problem(0, seed=2, k=2), config_problem(1, seed=3, k=4, scale=16)):
+        A, b, tol = cfg["A"], cfg["b"], cfg["tol"]
+        say(f"bitwise converged {variant}/{formulation}/{precond} n={A.n} k={b.shape[1]}")
+        s = gpu_solver(lib, A, b.shape[1], variant, formulation, precond)
+        x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=3000)
+        with oracle_dot(group_dot(A.n, b.shape[1])):
+            ref = oracle.solve(A.to_scipy(), b, variant=variant, formulation=formulation, precond=precond, tol=tol,
+                               maxit=3000)
+        assert np.array_equal(info.status, ref.status), (info.status, ref.status)
+        assert np.array_equal(info.iters, ref.iters), (info.iters, ref.iters)
+        assert np.array_equal(to_np(x), ref.x)
+
+
+def fused_dot(A, k):
+    """The fused classical form's dot sequence: (r, r), (b, b) from the start
+    pass, then per pass delta from the first product's epilogue, phi, psi,
+    theta from the second's, and rho' from the vector pass."""
+    g = group_dot(A.n, k)
+    e = spmm_epilogue_dot(A.row_ptr, k)
+    return scheduled_dot([g, g], [e, e, e, e, g])
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_bitwise_fused(lib, precond):
+    """The fused classical form, 20 fixed passes and a converged solve, per
+    column (each column's oracle run gets its own dot schedule): iterates,
+    pass counts and statuses equal the oracle's in the kernels' order."""
+    import torch
+
+    A = conv_diff(17, 3, (1.0, 0.7, 0.3))
+    k = 5
+    b, _ = manufactured_rhs(A, k, seed=22)
+    S = A.to_scipy()
+    for tol, maxit in ((0.0, 20), (1e-10, 3000)):
+        say(f"bitwise fused {precond} tol={tol}")
+        s = gpu_solver(lib, A, k, "classical", "fused", precond)
+        x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=maxit)
+        X = to_np(x)
+        for c in range(k):
+            with oracle_dot(fused_dot(A, k)):
+                ref = oracle.solve_column(S, b[:, c], None, "classical", "fused", precond, tol, maxit)
+            assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), (c, info.iters[c], ref.iters)
+            assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
 
 
 # ---------------------------------------------------- full-size checks ---
