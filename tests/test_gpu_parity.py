@@ -491,9 +491,10 @@ def test_bitwise_fused(lib, precond):
 def test_full_size_cfg1_sampled(lib):
     """The 128^3 7-point Jacobi workload at k = 32 (the benchmark's launch
     configuration): SpMM rows sampled against the oracle's product, three
-    passes of every merged method against the oracle on columns 0 and 31, and
-    a converged classical solve checked by its recomputed residual and the
-    manufactured solution."""
+    passes of every merged method and of the fused form bit for bit against
+    the oracle (kernel summation order) on columns 0 and 31, and a converged
+    classical solve checked by its recomputed residual and the manufactured
+    solution."""
     import torch
 
     say("full size 128^3 k=32")
@@ -506,13 +507,14 @@ def test_full_size_cfg1_sampled(lib):
     rows = np.random.default_rng(0).choice(A.n, 2000, replace=False)
     assert np.array_equal(Y[rows], S[rows] @ b)
     for v, f in (("classical", "merged"), ("reordered", "merged"), ("pipelined", "merged"), ("classical", "fused")):
-        say(f"  3 passes {v} {f}")
+        say(f"  3 passes {v} {f} (bitwise)")
         s3 = gpu_solver(lib, A, 32, v, f, "jacobi")
         x, info = s3.solve(bt, tol=0.0, maxit=3)
         X = to_np(x)
-        ref = oracle.solve(S, b, variant=v, formulation="merged", precond="jacobi", tol=0.0, maxit=3, columns=[0, 31])
         for c in (0, 31):
-            assert np.linalg.norm(X[:, c] - ref.x[:, c]) / np.linalg.norm(ref.x[:, c]) < 1e-12
+            with oracle_dot(fused_dot(A, 32) if f == "fused" else group_dot(A.n, 32)):
+                ref = oracle.solve_column(S, b[:, c], None, v, f, "jacobi", 0.0, 3)
+            assert np.array_equal(X[:, c], ref.x), (v, f, c)
         del s3
     say("  converged solve")
     x, info = s.solve(bt, tol=1e-8, maxit=2000)
