@@ -188,8 +188,8 @@ int bicgstab_destroy(bicgstab_t h);
  * one system with several right-hand sides.
  *
  * The kernel variant (threads per workgroup, rows a thread handles per step
- * of a vector phase, entries per step of a row product; see
- * bicgstab_batched_variant_info) and each system's share of workgroups come
+ * of a vector phase and of a sparse product, entries per step of a row
+ * product; see bicgstab_batched_variant_info) and each system's share of workgroups come
  * from the handle's configuration: a starting guess at create, replaced by
  * bicgstab_batched_tune (timed trials on the caller's batch) or by
  * bicgstab_batched_set_config (e.g. a configuration saved from an earlier
@@ -243,9 +243,11 @@ int bicgstab_batched_get_config(bicgstab_batched_t h, int32_t* variant, int32_t*
 /* Set the configuration (a variant index, workgroups[s] >= 1). */
 int bicgstab_batched_set_config(bicgstab_batched_t h, int32_t variant, const int32_t* workgroups);
 /* Host-only: parameters of kernel variant `variant` (0-based; an error past
- * the last one). */
+ * the last one): threads per workgroup, rows a thread takes per step of a
+ * vector phase, entries per step of a row product, rows per step of a sparse
+ * product. Any pointer may be NULL. */
 int bicgstab_batched_variant_info(int32_t variant, int32_t* block, int32_t* rows_per_step,
-                                  int32_t* entries_per_step);
+                                  int32_t* entries_per_step, int32_t* product_rows_per_step);
 int bicgstab_batched_destroy(bicgstab_batched_t h);
 
 /* Host-only query of the launch plan of one iteration (no device needed):

@@ -83,7 +83,7 @@ def lib():
     L.bicgstab_batched_tune.argtypes = [H, C.POINTER(vp), C.POINTER(vp), dbl, i32, C.POINTER(dbl)]
     L.bicgstab_batched_get_config.argtypes = [H, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl),
                                               C.POINTER(dbl)]
-    L.bicgstab_batched_variant_info.argtypes = [i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.bicgstab_batched_variant_info.argtypes = [i32] + [C.POINTER(i32)] * 4
     L.bicgstab_batched_set_config.argtypes = [H, i32, C.POINTER(i32)]
     L.bicgstab_batched_destroy.argtypes = [H]
     _lib = L

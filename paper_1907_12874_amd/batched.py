@@ -24,11 +24,12 @@ class BatchedConfig:
 
 
 def variant_info(variant: int):
-    """(threads per workgroup, rows per vector-phase step, entries per row-product step)."""
-    b, r, e = C.c_int32(), C.c_int32(), C.c_int32()
-    check(lib().bicgstab_batched_variant_info(int(variant), C.byref(b), C.byref(r), C.byref(e)),
+    """(threads per workgroup, rows per vector-phase step, entries per
+    row-product step, rows per sparse-product step)."""
+    b, r, e, pr = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().bicgstab_batched_variant_info(int(variant), C.byref(b), C.byref(r), C.byref(e), C.byref(pr)),
           "bicgstab_batched_variant_info")
-    return int(b.value), int(r.value), int(e.value)
+    return int(b.value), int(r.value), int(e.value), int(pr.value)
 
 
 class BatchedSolver:

@@ -140,8 +140,10 @@ __device__ __forceinline__ T& at(T* base, unsigned e) {
 }
 
 // (A X)[row, c], the row's entries in stored order, no contraction (bitwise
-// the CSR product of the single-system path). CH entries per step: their
-// column, value and gathered loads are issued before any is used.
+// the CSR product of the single-system path). CH entries per step, branch
+// free: a slot past the row's end repeats the row's last entry and its product
+// is not added (a select), so the column indices and values of a step load
+// together, then all its gathers are in flight before the first is used.
 template <int CH>
 __device__ __forceinline__ double row_product(const BSys& S, const gdouble* __restrict__ X, int row, int c) {
   gcint* __restrict__ rp = (gcint*)S.row_ptr;
@@ -150,26 +152,87 @@ __device__ __forceinline__ double row_product(const BSys& S, const gdouble* __re
   const int eb = rp[row], ee = rp[row + 1];
   double sum = 0.0;
   for (int e0 = eb; e0 < ee; e0 += CH) {
+    int cj[CH];
     double av[CH], xv[CH];
 #pragma unroll
-    for (int j = 0; j < CH; ++j)
-      if (e0 + j < ee) {
-        av[j] = val[e0 + j];
-        xv[j] = at(X, (unsigned)(col[e0 + j] * S.k + c));
-      }
+    for (int j = 0; j < CH; ++j) {
+      const int e = min(e0 + j, ee - 1);
+      cj[j] = col[e];
+      av[j] = val[e];
+    }
 #pragma unroll
-    for (int j = 0; j < CH; ++j)
-      if (e0 + j < ee) sum += av[j] * xv[j];
+    for (int j = 0; j < CH; ++j) xv[j] = at(X, (unsigned)(cj[j] * S.k + c));
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const double t = sum + av[j] * xv[j];
+      sum = e0 + j < ee ? t : sum;
+    }
   }
   return sum;
 }
 
+// The products of RU rows at once (rows row + u * rpp below row1; the others
+// give 0): each row's entries in stored order as in row_product, with the
+// loads of all RU rows of a step issued together.
+template <int CH, int RU>
+__device__ __forceinline__ void rows_product(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
+                                             int row1, int c, double (&z)[RU]) {
+  if constexpr (RU == 1) {
+    z[0] = row < row1 ? row_product<CH>(S, X, row, c) : 0.0;
+  } else {
+    gcint* __restrict__ rp = (gcint*)S.row_ptr;
+    gcint* __restrict__ col = (gcint*)S.col;
+    gcdouble* __restrict__ val = (gcdouble*)S.val;
+    int eb[RU], ne[RU];
+    int len = 0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int rr = row + u * rpp;
+      eb[u] = 0;
+      ne[u] = 0;
+      if (rr < row1) {
+        eb[u] = rp[rr];
+        ne[u] = rp[rr + 1] - eb[u];
+      }
+      z[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) len = max(len, ne[u]);
+    for (int o = 0; o < len; o += CH) {
+      int cj[RU][CH];
+      double av[RU][CH], xv[RU][CH];
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          // a slot past the row's end repeats its last entry; an empty row's
+          // slots gather row 0 and load no entry
+          const int e = ne[u] > 0 ? eb[u] + min(o + j, ne[u] - 1) : -1;
+          cj[u][j] = e >= 0 ? col[e] : 0;
+          av[u][j] = e >= 0 ? val[e] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int j = 0; j < CH; ++j) xv[u][j] = at(X, (unsigned)(cj[u][j] * S.k + c));
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const double t = z[u] + av[u][j] * xv[u][j];
+          z[u] = o + j < ne[u] ? t : z[u];
+        }
+    }
+  }
+}
+
 enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_EPS2, B_BB, B_NS };
 
-// VU: rows per step of a thread in the vector phases (all their loads issued
-// before any is used); a thread still visits its rows in increasing order, so
-// its partial sums keep their order. CH: entries per step of a row product.
-template <int BS, int VU, int CH>
+// VU: rows per step of a thread in the vector phases and RU in the sparse
+// products (all their loads issued before any is used); a thread still
+// visits its rows in increasing order, so its partial sums keep their order.
+// CH: entries per step of a row product.
+template <int BS, int VU, int CH, int RU>
 __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ Gp, const BSys* __restrict__ sys,
                                                      const int32_t* __restrict__ wg_sys) {
   const BGlob G = *Gp;
@@ -207,16 +270,22 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   // ---- start: r = b - A x0, r0 = r, p = r; partial (r, r), (b, b)
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < k)
-    for (int row = row0 + rsub; row < row1; row += rpp) {
-      const double z = row_product<CH>(S, x, row, c);
-      const unsigned e = eidx(row);
-      const double bv = at(b, e);
-      const double res = bv - z;
-      at(r, e) = res;
-      at(r0, e) = res;
-      at(p, e) = res;
-      acc[0] += res * res;
-      acc[1] += bv * bv;
+    for (int row = row0 + rsub; row < row1; row += RU * rpp) {
+      double z[RU];
+      rows_product<CH, RU>(S, x, row, rpp, row1, c, z);
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int rr = row + u * rpp;
+        if (rr >= row1) break;
+        const unsigned e = eidx(rr);
+        const double bv = at(b, e);
+        const double res = bv - z[u];
+        at(r, e) = res;
+        at(r0, e) = res;
+        at(p, e) = res;
+        acc[0] += res * res;
+        acc[1] += bv * bv;
+      }
     }
   store_partials<BS, 2>(S, 0, w, acc, s_w);
   if (!barrier()) return;
@@ -262,11 +331,17 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     const bool run1 = c < k && st[c] == ST_RUNNING;
     acc[0] = 0.0;
     if (run1)
-      for (int row = row0 + rsub; row < row1; row += rpp) {
-        const double z = row_product<CH>(S, p, row, c);
-        const unsigned e = eidx(row);
-        at(v, e) = z;
-        acc[0] += z * at(r0, e);
+      for (int row = row0 + rsub; row < row1; row += RU * rpp) {
+        double z[RU];
+        rows_product<CH, RU>(S, p, row, rpp, row1, c, z);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int rr = row + u * rpp;
+          if (rr >= row1) break;
+          const unsigned e = eidx(rr);
+          at(v, e) = z[u];
+          acc[0] += z[u] * at(r0, e);
+        }
       }
     store_partials<BS, 1>(S, 1, w, acc, s_w);
     if (!barrier()) return;
@@ -313,14 +388,21 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     // ---- C: t = A s; phi = (t, s), psi = (t, t), theta = (s, s)
     acc[0] = acc[1] = acc[2] = 0.0;
     if (run2)
-      for (int row = row0 + rsub; row < row1; row += rpp) {
-        const double tt = row_product<CH>(S, s, row, c);
-        const unsigned e = eidx(row);
-        const double ss = at(s, e);
-        at(t, e) = tt;
-        acc[0] += tt * ss;
-        acc[1] += tt * tt;
-        acc[2] += ss * ss;
+      for (int row = row0 + rsub; row < row1; row += RU * rpp) {
+        double z[RU];
+        rows_product<CH, RU>(S, s, row, rpp, row1, c, z);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int rr = row + u * rpp;
+          if (rr >= row1) break;
+          const unsigned e = eidx(rr);
+          const double tt = z[u];
+          const double ss = at(s, e);
+          at(t, e) = tt;
+          acc[0] += tt * ss;
+          acc[1] += tt * tt;
+          acc[2] += ss * ss;
+        }
       }
     store_partials<BS, 3>(S, 2, w, acc, s_w);
     if (!barrier()) return;
@@ -436,11 +518,18 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   // ---- exit: partial (b - A x, b - A x) and (r, r) per column
   acc[0] = acc[1] = 0.0;
   if (c < k)
-    for (int row = row0 + rsub; row < row1; row += rpp) {
-      const unsigned e = eidx(row);
-      const double d = at(b, e) - row_product<CH>(S, x, row, c);
-      acc[0] += d * d;
-      acc[1] += at(r, e) * at(r, e);
+    for (int row = row0 + rsub; row < row1; row += RU * rpp) {
+      double z[RU];
+      rows_product<CH, RU>(S, x, row, rpp, row1, c, z);
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int rr = row + u * rpp;
+        if (rr >= row1) break;
+        const unsigned e = eidx(rr);
+        const double d = at(b, e) - z[u];
+        acc[0] += d * d;
+        acc[1] += at(r, e) * at(r, e);
+      }
     }
   store_partials<BS, 2>(S, 0, w, acc, s_w);
   if (!barrier()) return;
@@ -466,16 +555,18 @@ __global__ void batched_reset_kernel(unsigned* bars, int nsys, int* abort_flag) 
 constexpr double kBarrierWaitSeconds = 2.0;
 
 // Kernel variants the tuner chooses from: threads per workgroup, rows per
-// step in the vector phases, entries per step of a row product.
+// step in the vector phases, entries per step of a row product, rows per
+// step in the sparse products.
 struct Variant {
-  int block, rows, entries;
+  int block, rows, entries, product_rows;
 };
-constexpr Variant kVariants[] = {{256, 1, 4}, {256, 2, 8}, {256, 4, 8}, {512, 1, 4}, {512, 2, 8}, {512, 4, 8}};
+constexpr Variant kVariants[] = {{256, 2, 8, 1}, {256, 4, 8, 2}, {512, 2, 8, 1},
+                                 {512, 4, 8, 2}, {512, 4, 4, 4}, {256, 4, 4, 4}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <int V>
 constexpr auto variant_kernel() {
-  return batched_kernel<kVariants[V].block, kVariants[V].rows, kVariants[V].entries>;
+  return batched_kernel<kVariants[V].block, kVariants[V].rows, kVariants[V].entries, kVariants[V].product_rows>;
 }
 
 const void* kernel_of(int v) {
@@ -1051,11 +1142,12 @@ int bicgstab_batched_set_config(bicgstab_batched_t h, int32_t variant, const int
 }
 
 int bicgstab_batched_variant_info(int32_t variant, int32_t* block, int32_t* rows_per_step,
-                                  int32_t* entries_per_step) {
+                                  int32_t* entries_per_step, int32_t* product_rows_per_step) {
   if (variant < 0 || variant >= kNumVariants) return bfail(BICGSTAB_EINVAL, "unknown batched kernel variant");
   if (block) *block = kVariants[variant].block;
   if (rows_per_step) *rows_per_step = kVariants[variant].rows;
   if (entries_per_step) *entries_per_step = kVariants[variant].entries;
+  if (product_rows_per_step) *product_rows_per_step = kVariants[variant].product_rows;
   return BICGSTAB_OK;
 }
 

@@ -170,10 +170,10 @@ def test_batched_variants_agree_bitwise(lib):
     v = 0
     while True:
         try:
-            block, rows, entries = variant_info(v)
+            block, rows, entries, prows = variant_info(v)
         except lib.BicgstabError:
             break
-        say(f"variant {v}: block {block}, rows {rows}, entries {entries}")
+        say(f"variant {v}: block {block}, rows {rows}, entries {entries}, product rows {prows}")
         bs.set_config(v, shares)
         _, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-9, maxit=2000, solver=bs)
         if block in by_block:
