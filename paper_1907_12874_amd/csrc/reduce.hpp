@@ -6,22 +6,25 @@
 
 namespace bcg {
 
-// ND dot products per column; acc[d] holds this thread's running sum for its
-// column c = threadIdx.x mod kp. Fixed order: the row slots of a 64-wide
-// wavefront by xor shuffles, then the wavefronts in index order. Pair
-// t = d * k + c goes to out[t * stride].
-template <int ND, int BS>
-__device__ __forceinline__ void store_block_partials_strided(const double* acc, double* out, int k, int kpl,
+// ND dot products per column; acc[d * CPL + h] holds this thread's running
+// sum for column (lane mod 2^lpl) * CPL + h, 2^lpl lanes per row (CPL = 1:
+// 2^lpl = kp). Fixed order: the row slots of a 64-wide wavefront by xor
+// shuffles, then the wavefronts in index order. Pair t = d * k + c goes to
+// out[t * stride].
+template <int ND, int BS, int CPL = 1>
+__device__ __forceinline__ void store_block_partials_strided(const double* acc, double* out, int k, int lpl,
                                                              size_t stride) {
   __shared__ double s_w[BS / 64][ND][kMaxK];
-  const int kp = 1 << kpl;
+  const int lpr = 1 << lpl;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    double v = acc[d];
-    for (int off = kp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if (lane < kp) s_w[wave][d][lane] = v;
-  }
+  for (int d = 0; d < ND; ++d)
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) {
+      double v = acc[d * CPL + h];
+      for (int off = lpr; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (lane < lpr && lane * CPL + h < kMaxK) s_w[wave][d][lane * CPL + h] = v;
+    }
   __syncthreads();
   const int P = ND * k;
   for (int t = threadIdx.x; t < P; t += BS) {

@@ -2,16 +2,20 @@
 //
 // CSR-stream layout: contiguous rows are grouped into row blocks whose CSR
 // entries fit in LDS. A workgroup stages its block's column indices, values
-// and row offsets with coalesced loads, then lane c of each group of kp lanes
-// (kp = k rounded up to a power of two) computes Y[i, c] for its rows. A lane
-// takes its rows two at a time and issues the X gathers of both (up to 16)
-// before it adds any of them; the products of a row are added in entry order,
-// the rounding of a plain sequential sum. Two forms of that inner loop
-// (measured on the 128^3 stencil, k = 1..32): the plain product guards each
-// slot and reads a product's value with its column index (STYLE 0, fastest
-// there); the product with a dot epilogue uses branch-free slots with 32-bit
-// gather offsets (STYLE 1), which keeps its register count, and so the
-// workgroups in flight per compute unit, up.
+// and row offsets with coalesced loads, then each group of kp / CPL lanes
+// (kp = k rounded up to a power of two) computes the k outputs of one row,
+// CPL adjacent columns per lane. For even k a lane takes two columns (CPL = 2):
+// one 16-byte gather per entry instead of two 8-byte ones, which halves the
+// gather instructions and measured 15-25% faster on the 128^3 stencil at
+// k = 4..32; it takes its rows one at a time. For odd k (CPL = 1) a lane takes
+// its rows two at a time and issues the gathers of both before it adds any.
+// Either way the products of a row are added in entry order, the rounding of a
+// plain sequential sum. Two forms of the inner loop: the plain product guards
+// each slot and reads a product's value with its column index (STYLE 0); the
+// product with a dot epilogue uses branch-free slots with 32-bit gather offsets
+// (STYLE 1), which keeps its register count, and so the workgroups in flight
+// per compute unit, up. Output rows are written with nontemporal stores: the
+// block is far larger than the caches and is read back only by a later pass.
 //
 // The same row-block body serves the sparse product with a dot epilogue
 // (beyond the paper's grouping: dots of the written rows formed in the
@@ -19,6 +23,7 @@
 // a second kernel sums them over runs of blocks, and the finalize kernel sums
 // the runs, every sum in a fixed order.
 #include <algorithm>
+#include <initializer_list>
 
 #include "internal.hpp"
 #include "reduce.hpp"
@@ -33,12 +38,17 @@ __host__ __device__ inline int pad_k_(int k) {
   return kp;
 }
 
-// Workgroup size and rows per lane of the product for padded width kp: up to
-// 2048 outputs and 256 rows per block. (Measured on the 128^3 stencil at
-// k = 32: 1024-lane workgroups with two rows per lane and column tiling were
-// slower.)
+// Workgroup size, columns per lane and rows per lane of the product: even k
+// takes two columns per lane and two rows per lane (1024 outputs per block);
+// odd k one column and up to eight rows per lane. (Measured on the 128^3
+// stencil: 512- and 1024-lane workgroups, four or eight rows per lane at
+// CPL = 2, and column tiling were slower.)
 constexpr int kSpmmBlock = 256;
-inline int spmm_rows_per_lane(int kp) { return kp >= 8 ? 8 : kp; }
+inline int spmm_cols_per_lane(int k) { return (k % 2 == 0) ? 2 : 1; }
+inline int spmm_rows_per_lane(int k) {
+  const int kp = pad_k_(k);
+  return spmm_cols_per_lane(k) == 2 ? 2 : (kp >= 8 ? 8 : kp);
+}
 
 // Row block of workgroup w. Workgroups are dealt to the 8 XCDs in turn
 // (XCD = w mod 8); with C > 1, runs of C consecutive row blocks go to one XCD,
@@ -67,46 +77,92 @@ __device__ __forceinline__ T load_x(const T* X, int j, int k, int c) {
   }
 }
 
+template <class T>
+struct Pair {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
+// Elements (j, c) and (j, c + 1) of X in one load (c even, k even, X aligned
+// to two elements).
+template <class T, bool OFF32>
+__device__ __forceinline__ typename Pair<T>::type load_x2(const T* X, int j, int k, int c) {
+  typedef typename Pair<T>::type P2;
+  if constexpr (OFF32) {
+    const unsigned off = ((unsigned)j * (unsigned)k + (unsigned)c) * (unsigned)sizeof(T);
+    return *(const __attribute__((address_space(1))) P2*)((gcchar*)X + off);
+  } else {
+    return *(const P2*)(X + (size_t)j * k + c);
+  }
+}
+
+// Row `row`, columns c .. c + CPL - 1 of Y, nontemporal.
+template <class T, int CPL>
+__device__ __forceinline__ void store_y(T* Y, int row, int k, int c, const T (&v)[CPL]) {
+  if constexpr (CPL == 1) {
+    __builtin_nontemporal_store(v[0], Y + (size_t)row * k + c);
+  } else {
+    typename Pair<T>::type t;
+    t.x = v[0];
+    t.y = v[1];
+    __builtin_nontemporal_store(t, (typename Pair<T>::type*)(Y + (size_t)row * k + c));
+  }
+}
+
 struct NoEpilogue {
-  template <class T>
-  __device__ __forceinline__ void operator()(int, T) {}
+  template <class T, int CPL>
+  __device__ __forceinline__ void operator()(int, const T (&)[CPL]) {}
 };
 
 // Dots of the written rows against W (E_DOT_W: (y, w); E_PPT: (y, w), (y, y),
 // (w, w)), per lane in the order the lane writes its rows.
-template <class T, int EPI>
+// acc[d * CPL + h]: dot d of column c + h.
+template <class T, int EPI, int CPL>
 struct DotEpilogue {
   const T* W;
   int k, c;
-  double acc[3];
-  __device__ __forceinline__ void operator()(int row, T y) {
-    const double yv = (double)y;
-    const double wv = (double)W[(size_t)row * k + c];
-    acc[0] += yv * wv;
-    if (EPI == E_PPT) {
-      acc[1] += yv * yv;
-      acc[2] += wv * wv;
+  double acc[3 * CPL];
+  __device__ __forceinline__ void operator()(int row, const T (&y)[CPL]) {
+    T w[CPL];
+    if constexpr (CPL == 1) {
+      w[0] = W[(size_t)row * k + c];
+    } else {
+      const typename Pair<T>::type t = *(const typename Pair<T>::type*)(W + (size_t)row * k + c);
+      w[0] = t.x;
+      w[1] = t.y;
+    }
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) {
+      const double yv = (double)y[h];
+      const double wv = (double)w[h];
+      acc[h] += yv * wv;
+      if (EPI == E_PPT) {
+        acc[CPL + h] += yv * yv;
+        acc[2 * CPL + h] += wv * wv;
+      }
     }
   }
 };
 
-// Y rows of row block L; every finished output (row, value) goes to epi.
-template <class T, int KPL, int BS, bool OFF32, int STYLE, class Epi>
+// Y rows of row block L; every finished row (row, its CPL values) goes to epi.
+// KPL = log2(kp); lane c0 = (lane mod kp / CPL) * CPL holds columns c0 ..
+// c0 + CPL - 1 (all below k, or all at or above it: k is even when CPL = 2).
+template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE, class Epi>
 __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict__ X, T* __restrict__ Y, int k, int L,
                                           Epi& epi) {
   extern __shared__ double s_mem[];
   T* s_val = reinterpret_cast<T*>(s_mem);
   T* s_red = s_val + A.nnz_cap;
-  int* s_col = reinterpret_cast<int*>(s_red + BS);
+  int* s_col = reinterpret_cast<int*>(s_red + CPL * BS);
   int* s_rp = s_col + A.nnz_cap;
   const int r0 = A.blk[L], r1 = A.blk[L + 1];
   const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
   const int ne = e1 - e0;
   const T* __restrict__ val = static_cast<const T*>(A.val);
-  constexpr int kp = 1 << KPL;
-  constexpr int rpp = BS >> KPL;
-  const int c = threadIdx.x & (kp - 1);
-  const int rsub = threadIdx.x >> KPL;
+  constexpr int LPL = KPL - (CPL == 2 ? 1 : 0);  // log2 of the lanes per row
+  constexpr int lpr = 1 << LPL;
+  constexpr int rpp = BS >> LPL;                  // rows per pass of the workgroup
+  const int c = (threadIdx.x & (lpr - 1)) * CPL;
+  const int rsub = threadIdx.x >> LPL;
   if (ne <= A.nnz_cap) {
     for (int i = threadIdx.x; i < ne; i += BS) {
       s_col[i] = A.col[e0 + i];
@@ -116,78 +172,126 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
     __syncthreads();
     if (c >= k) return;
     const int nr = r1 - r0;
-    for (int r = rsub; r < nr; r += 2 * rpp) {
-      const int rb = r + rpp;
-      const bool has_b = rb < nr;
-      const int ebA = s_rp[r], eeA = s_rp[r + 1];
-      const int ebB = has_b ? s_rp[rb] : 0, eeB = has_b ? s_rp[rb + 1] : 0;
-      const int len = max(eeA - ebA, eeB - ebB);
-      T sumA = (T)0, sumB = (T)0;
-      if constexpr (STYLE == 0) {
-        // guarded slots, the value of a product read with its column index
-        for (int o = 0; o < len; o += 8) {
-          T aA[8], xA[8], aB[8], xB[8];
+    if constexpr (CPL == 2) {
+      for (int r = rsub; r < nr; r += rpp) {
+        const int eb = s_rp[r], ee = s_rp[r + 1];
+        T s0 = (T)0, s1 = (T)0;
+        if constexpr (STYLE == 0) {
+          for (int o = eb; o < ee; o += 8) {
+            T av[8];
+            typename Pair<T>::type xv[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int ea = ebA + o + j;
-            if (ea < eeA) {
-              aA[j] = s_val[ea];
-              xA[j] = X[(size_t)s_col[ea] * k + c];
+            for (int j = 0; j < 8; ++j)
+              if (o + j < ee) {
+                av[j] = s_val[o + j];
+                xv[j] = load_x2<T, OFF32>(X, s_col[o + j], k, c);
+              }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (o + j < ee) {
+                s0 += av[j] * xv[j].x;
+                s1 += av[j] * xv[j].y;
+              }
+          }
+        } else {
+          // branch-free: a slot past the row's end gathers row 0 of X and is
+          // not added (a select)
+          const int last = max(ee - 1, 0);
+          for (int o = eb; o < ee; o += 8) {
+            typename Pair<T>::type xv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xv[j] = load_x2<T, OFF32>(X, o + j < ee ? s_col[min(o + j, last)] : 0, k, c);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const T a = s_val[min(o + j, last)];
+              const T t0 = s0 + a * xv[j].x, t1 = s1 + a * xv[j].y;
+              s0 = o + j < ee ? t0 : s0;
+              s1 = o + j < ee ? t1 : s1;
             }
-            const int eb = ebB + o + j;
-            if (eb < eeB) {
-              aB[j] = s_val[eb];
-              xB[j] = X[(size_t)s_col[eb] * k + c];
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (ebA + o + j < eeA) sumA += aA[j] * xA[j];
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (ebB + o + j < eeB) sumB += aB[j] * xB[j];
-        }
-      } else {
-        // Branch-free: a slot past its row's end gathers row 0 of X (always a
-        // valid address) and its product is not added (a select, so the sums
-        // are those of the entries alone, in order). Every gather of the step
-        // is then in flight before the first is used.
-        const int lastA = max(eeA - 1, 0), lastB = max(eeB - 1, 0);
-        for (int o = 0; o < len; o += 8) {
-          T xA[8], xB[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int ea = ebA + o + j, eb = ebB + o + j;
-            const int ja = ea < eeA ? s_col[min(ea, lastA)] : 0;
-            const int jb = eb < eeB ? s_col[min(eb, lastB)] : 0;
-            xA[j] = load_x<T, OFF32>(X, ja, k, c);
-            xB[j] = load_x<T, OFF32>(X, jb, k, c);
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int ea = ebA + o + j;
-            const T t = sumA + s_val[min(ea, lastA)] * xA[j];
-            sumA = ea < eeA ? t : sumA;
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int eb = ebB + o + j;
-            const T t = sumB + s_val[min(eb, lastB)] * xB[j];
-            sumB = eb < eeB ? t : sumB;
           }
         }
+        const T out[2] = {s0, s1};
+        store_y<T, 2>(Y, r0 + r, k, c, out);
+        epi(r0 + r, out);
       }
-      Y[(size_t)(r0 + r) * k + c] = sumA;
-      epi(r0 + r, sumA);
-      if (has_b) {
-        Y[(size_t)(r0 + rb) * k + c] = sumB;
-        epi(r0 + rb, sumB);
+    } else {
+      for (int r = rsub; r < nr; r += 2 * rpp) {
+        const int rb = r + rpp;
+        const bool has_b = rb < nr;
+        const int ebA = s_rp[r], eeA = s_rp[r + 1];
+        const int ebB = has_b ? s_rp[rb] : 0, eeB = has_b ? s_rp[rb + 1] : 0;
+        const int len = max(eeA - ebA, eeB - ebB);
+        T sumA = (T)0, sumB = (T)0;
+        if constexpr (STYLE == 0) {
+          // guarded slots, the value of a product read with its column index
+          for (int o = 0; o < len; o += 8) {
+            T aA[8], xA[8], aB[8], xB[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int ea = ebA + o + j;
+              if (ea < eeA) {
+                aA[j] = s_val[ea];
+                xA[j] = X[(size_t)s_col[ea] * k + c];
+              }
+              const int eb = ebB + o + j;
+              if (eb < eeB) {
+                aB[j] = s_val[eb];
+                xB[j] = X[(size_t)s_col[eb] * k + c];
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (ebA + o + j < eeA) sumA += aA[j] * xA[j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (ebB + o + j < eeB) sumB += aB[j] * xB[j];
+          }
+        } else {
+          // Branch-free: a slot past its row's end gathers row 0 of X (always a
+          // valid address) and its product is not added (a select, so the sums
+          // are those of the entries alone, in order). Every gather of the step
+          // is then in flight before the first is used.
+          const int lastA = max(eeA - 1, 0), lastB = max(eeB - 1, 0);
+          for (int o = 0; o < len; o += 8) {
+            T xA[8], xB[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int ea = ebA + o + j, eb = ebB + o + j;
+              const int ja = ea < eeA ? s_col[min(ea, lastA)] : 0;
+              const int jb = eb < eeB ? s_col[min(eb, lastB)] : 0;
+              xA[j] = load_x<T, OFF32>(X, ja, k, c);
+              xB[j] = load_x<T, OFF32>(X, jb, k, c);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int ea = ebA + o + j;
+              const T t = sumA + s_val[min(ea, lastA)] * xA[j];
+              sumA = ea < eeA ? t : sumA;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int eb = ebB + o + j;
+              const T t = sumB + s_val[min(eb, lastB)] * xB[j];
+              sumB = eb < eeB ? t : sumB;
+            }
+          }
+        }
+        const T outA[1] = {sumA};
+        store_y<T, 1>(Y, r0 + r, k, c, outA);
+        epi(r0 + r, outA);
+        if (has_b) {
+          const T outB[1] = {sumB};
+          store_y<T, 1>(Y, r0 + rb, k, c, outB);
+          epi(r0 + rb, outB);
+        }
       }
     }
   } else {
-    // one long row (r1 == r0 + 1): lanes of the same column split its entries
+    // one long row (r1 == r0 + 1): lanes of the same columns split its entries
     // and their sums are added in lane order
-    T sum = (T)0;
+    T sum[CPL];
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) sum[h] = (T)0;
     for (int base = 0; base < ne; base += A.nnz_cap) {
       const int m = min(A.nnz_cap, ne - base);
       __syncthreads();
@@ -197,41 +301,56 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
       }
       __syncthreads();
       if (c < k)
-        for (int e = rsub; e < m; e += rpp) sum += s_val[e] * load_x<T, OFF32>(X, s_col[e], k, c);
+        for (int e = rsub; e < m; e += rpp) {
+          if constexpr (CPL == 2) {
+            const typename Pair<T>::type xv = load_x2<T, OFF32>(X, s_col[e], k, c);
+            sum[0] += s_val[e] * xv.x;
+            sum[1] += s_val[e] * xv.y;
+          } else {
+            sum[0] += s_val[e] * load_x<T, OFF32>(X, s_col[e], k, c);
+          }
+        }
     }
-    s_red[threadIdx.x] = sum;
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) s_red[h * BS + threadIdx.x] = sum[h];
     __syncthreads();
-    if (threadIdx.x < kp && c < k) {
-      T s = (T)0;
-      for (int g = 0; g < rpp; ++g) s += s_red[g * kp + c];
-      Y[(size_t)r0 * k + c] = s;
-      epi(r0, s);
+    if (threadIdx.x < lpr && c < k) {
+      T out[CPL];
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) {
+        T v = (T)0;
+        for (int g = 0; g < rpp; ++g) v += s_red[h * BS + g * lpr + threadIdx.x];
+        out[h] = v;
+      }
+      store_y<T, CPL>(Y, r0, k, c, out);
+      epi(r0, out);
     }
   }
 }
 
-template <class T, int KPL, int BS, bool OFF32, int STYLE>
+template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE>
 __global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y, int k,
                                                   const Globals* glob) {
   if (glob && glob->nrun == 0) return;
   NoEpilogue none;
-  row_block<T, KPL, BS, OFF32, STYLE>(A, X, Y, k, block_of(blockIdx.x, A.nblk, A.xcd_chunk), none);
+  row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, block_of(blockIdx.x, A.nblk, A.xcd_chunk), none);
 }
 
 // The product with a dot epilogue: one workgroup per row block, as the plain
 // product; the block's ND x k partial sums go to bpart[L * P + d * k + c]
 // (block-major, P = ND * k).
-template <class T, int KPL, int BS, bool OFF32, int STYLE, int EPI>
+template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE, int EPI>
 __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y,
                                                       const T* __restrict__ W, int k, double* __restrict__ bpart,
                                                       const Globals* glob) {
   if (glob->nrun == 0) return;
   constexpr int ND = EPI == E_DOT_W ? 1 : 3;
+  constexpr int LPL = KPL - (CPL == 2 ? 1 : 0);
   const int L = block_of(blockIdx.x, A.nblk, A.xcd_chunk);
-  DotEpilogue<T, EPI> epi{W, k, (int)(threadIdx.x & ((1 << KPL) - 1)), {0.0, 0.0, 0.0}};
-  row_block<T, KPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
+  DotEpilogue<T, EPI, CPL> epi{W, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
+  row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
   // lanes past k returned from the row loop with their sums still zero
-  store_block_partials_strided<ND, BS>(epi.acc, bpart + (size_t)L * ND * k, k, KPL, 1);
+  store_block_partials_strided<ND, BS, CPL>(epi.acc, bpart + (size_t)L * ND * k, k, LPL, 1);
 }
 
 // Sums the block-major partials of nb row blocks over G runs of consecutive
@@ -249,16 +368,18 @@ __global__ __launch_bounds__(256) void reduce_runs_kernel(const double* __restri
   }
 }
 
-template <class T, int BS, bool OFF32, int STYLE>
+template <class T, int CPL, int BS, bool OFF32, int STYLE>
 hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globals* glob, hipStream_t s) {
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
-  const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
+  const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
                      (size_t)(A.rows_cap + 1) * 4 + 16;
+  if (CPL == 2 && kp < 2) return hipErrorInvalidValue;
   switch (kp) {
-#define SPMM_CASE(KP, KPL)                                                                                  \
-  case KP:                                                                                                  \
-    hipLaunchKernelGGL((spmm_kernel<T, KPL, BS, OFF32, STYLE>), dim3(grid), dim3(BS), lds, s, A, x, y, k, glob); \
+#define SPMM_CASE(KP, KPL)                                                                                       \
+  case KP:                                                                                                       \
+    hipLaunchKernelGGL((spmm_kernel<T, KPL, (KP >= 2 ? CPL : 1), BS, OFF32, STYLE>), dim3(grid), dim3(BS), lds, s, \
+                       A, x, y, k, glob);                                                                        \
     break;
     SPMM_CASE(1, 0)
     SPMM_CASE(2, 1)
@@ -273,18 +394,19 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
   return hipGetLastError();
 }
 
-template <class T, int BS, bool OFF32, int STYLE, int EPI>
+template <class T, int CPL, int BS, bool OFF32, int STYLE, int EPI>
 hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k, double* bpart,
                            const Globals* glob, hipStream_t s) {
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
-  const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
+  const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
                      (size_t)(A.rows_cap + 1) * 4 + 16;
+  if (CPL == 2 && kp < 2) return hipErrorInvalidValue;
   switch (kp) {
-#define SPMM_DOT_CASE(KP, KPL)                                                                              \
-  case KP:                                                                                                  \
-    hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), lds, s, A, x, y, w, \
-                       k, bpart, glob);                                                                     \
+#define SPMM_DOT_CASE(KP, KPL)                                                                                  \
+  case KP:                                                                                                      \
+    hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, (KP >= 2 ? CPL : 1), BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), \
+                       lds, s, A, x, y, w, k, bpart, glob);                                                     \
     break;
     SPMM_DOT_CASE(1, 0)
     SPMM_DOT_CASE(2, 1)
@@ -302,11 +424,36 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k
 // X block bytes below 4 GiB: 32-bit gather offsets.
 inline bool off32(const SpmmMat& A, int k, size_t elem) { return (size_t)A.n * (size_t)k * elem < ((size_t)1 << 32); }
 
+// Two columns per lane need even k and operands aligned to two elements;
+// otherwise (a caller's pointer into the middle of a block) one column per
+// lane, with the same sums.
+template <class T>
+bool wide_ok(int k, std::initializer_list<const void*> ptrs) {
+  if (spmm_cols_per_lane(k) != 2) return false;
+  for (const void* p : ptrs)
+    if (((uintptr_t)p % (2 * sizeof(T))) != 0) return false;
+  return true;
+}
+
 template <class T>
 hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
-  return spmm_launch_bs<T, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+  return wide_ok<T>(k, {X, Y}) ? spmm_launch_bs<T, 2, kSpmmBlock, false, 0>(A, x, y, k, glob, s)
+                               : spmm_launch_bs<T, 1, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+}
+
+template <class T, int CPL>
+hipError_t spmm_dot_dispatch_cpl(const SpmmMat& A, const T* x, T* y, const T* w, int epi, int k, double* bpart,
+                                 const Globals* glob, hipStream_t s) {
+  const bool o32 = off32(A, k, sizeof(T));
+  if (epi == E_DOT_W)
+    return o32 ? spmm_dot_launch<T, CPL, kSpmmBlock, true, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s)
+               : spmm_dot_launch<T, CPL, kSpmmBlock, false, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
+  if (epi == E_PPT)
+    return o32 ? spmm_dot_launch<T, CPL, kSpmmBlock, true, 1, E_PPT>(A, x, y, w, k, bpart, glob, s)
+               : spmm_dot_launch<T, CPL, kSpmmBlock, false, 1, E_PPT>(A, x, y, w, k, bpart, glob, s);
+  return hipErrorInvalidValue;
 }
 
 template <class T>
@@ -315,27 +462,21 @@ hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const voi
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
   const T* w = static_cast<const T*>(W);
-  const bool o32 = off32(A, k, sizeof(T));
-  if (epi == E_DOT_W)
-    return o32 ? spmm_dot_launch<T, kSpmmBlock, true, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s)
-               : spmm_dot_launch<T, kSpmmBlock, false, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
-  if (epi == E_PPT)
-    return o32 ? spmm_dot_launch<T, kSpmmBlock, true, 1, E_PPT>(A, x, y, w, k, bpart, glob, s)
-               : spmm_dot_launch<T, kSpmmBlock, false, 1, E_PPT>(A, x, y, w, k, bpart, glob, s);
-  return hipErrorInvalidValue;
+  return wide_ok<T>(k, {X, Y, W}) ? spmm_dot_dispatch_cpl<T, 2>(A, x, y, w, epi, k, bpart, glob, s)
+                                  : spmm_dot_dispatch_cpl<T, 1>(A, x, y, w, epi, k, bpart, glob, s);
 }
 
 }  // namespace
 
-// Row blocks: contiguous rows, block size x rows-per-lane / kp rows at most,
-// and no more than kSpmmNnzMax entries unless a single row is longer (that row
-// gets a block of its own, processed in chunks). Also returns the LDS extent
+// Row blocks: contiguous rows, block size x columns-per-lane x rows-per-lane
+// / kp rows at most, and no more than kSpmmNnzMax entries unless a single row
+// is longer (that row gets a block of its own, processed in chunks). Also returns the LDS extent
 // every launch needs: the largest block's staged entries and rows.
 SpmmPartition spmm_partition(const std::vector<int32_t>& row_ptr, int k, int rows_per_lane_override) {
   const int n = (int)row_ptr.size() - 1;
   const int kp = pad_k_(k);
-  const int rpl = rows_per_lane_override > 0 ? rows_per_lane_override : spmm_rows_per_lane(kp);
-  int rows_target = kSpmmBlock * rpl / kp;
+  const int rpl = rows_per_lane_override > 0 ? rows_per_lane_override : spmm_rows_per_lane(k);
+  int rows_target = kSpmmBlock * spmm_cols_per_lane(k) * rpl / kp;
   if (rows_target > kSpmmRowsMax) rows_target = kSpmmRowsMax;
   if (rows_target < 1) rows_target = 1;
   SpmmPartition P;

@@ -97,13 +97,20 @@ def oracle_dot(dotf):
         ob.dot = saved
 
 
+def _spmm_cols_per_lane(k):
+    """Columns per lane of the sparse product: two for even k, else one."""
+    return 2 if k % 2 == 0 else 1
+
+
 def spmm_row_blocks(row_ptr, k, block=256, nnz_max=4096, rows_max=1024):
     """Row blocks of the sparse product: contiguous rows, at most
-    block * rows-per-lane / kp rows (rows-per-lane = 8 for kp >= 8, else kp)
-    and nnz_max entries unless one row is longer."""
+    block * cpl * rpl / kp rows (cpl columns per lane; rows per lane rpl = 2
+    when cpl = 2, else 8 for kp >= 8 and kp below) and nnz_max entries unless
+    one row is longer."""
     kp = _pad_pow2(k)
-    rpl = 8 if kp >= 8 else kp
-    target = max(1, min(rows_max, block * rpl // kp))
+    cpl = _spmm_cols_per_lane(k)
+    rpl = 2 if cpl == 2 else (8 if kp >= 8 else kp)
+    target = max(1, min(rows_max, block * cpl * rpl // kp))
     n = len(row_ptr) - 1
     blk, r0 = [0], 0
     while r0 < n:
@@ -117,12 +124,14 @@ def spmm_row_blocks(row_ptr, k, block=256, nnz_max=4096, rows_max=1024):
 
 def spmm_epilogue_dot(row_ptr, k, block=256, runs_max=256, fin_lanes=16):
     """Dot of two length-n columns as the product's epilogue forms it: in row
-    block L, lane slot s sums rows r0 + s + j * (block / kp) in order of j;
-    the row slots of a wave by a pairwise tree; the waves in order; then the
-    G = min(#blocks, runs_max) runs of consecutive blocks in block order;
-    then the finalize kernel's lanes over the runs."""
+    block L, row slot s (a group of kp / cpl lanes) sums rows
+    r0 + s + j * (block * cpl / kp) in order of j; the row slots of a wave by a
+    pairwise tree; the waves in order; then the G = min(#blocks, runs_max)
+    runs of consecutive blocks in block order; then the finalize kernel's
+    lanes over the runs."""
     kp = _pad_pow2(k)
-    rpp, slots, waves = block // kp, 64 // kp, block // 64
+    cpl = _spmm_cols_per_lane(k)
+    rpp, slots, waves = block * cpl // kp, 64 * cpl // kp, block // 64
     blk = spmm_row_blocks(row_ptr, k, block)
     nb = len(blk) - 1
     G = max(1, min(nb, runs_max))

@@ -74,6 +74,42 @@ def test_spmm_bitwise(lib, k):
     assert np.array_equal(Y, S @ X)
 
 
+def test_spmm_and_solve_unaligned_operands(lib):
+    """Blocks that start one element past an aligned address (views into a
+    larger buffer) take the one-column-per-lane product: the same sums, so
+    the product and a whole solve equal those on aligned blocks bit for bit."""
+    import torch
+
+    say("spmm unaligned operands")
+    A = conv_diff(13, 3, (1.0, 0.7, 0.3))
+    k = 6
+    n = A.n
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (n, k))
+    s = gpu_solver(lib, A, k)
+    Y = to_np(s.spmm(torch.from_numpy(X).cuda()))
+    assert np.array_equal(Y, A.to_scipy() @ X)
+    buf_x = torch.zeros(n * k + 1, dtype=torch.float64, device="cuda")
+    buf_y = torch.zeros(n * k + 1, dtype=torch.float64, device="cuda")
+    xv = buf_x[1:].view(n, k)
+    yv = buf_y[1:].view(n, k)
+    assert xv.data_ptr() % 16 == 8 and yv.data_ptr() % 16 == 8
+    xv.copy_(torch.from_numpy(X))
+    s.spmm(xv, out=yv)
+    assert np.array_equal(to_np(yv), Y)
+    b, _ = manufactured_rhs(A, k, seed=9)
+    x_al, info_al = s.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=500)
+    bv = buf_y[1:].view(n, k)
+    bv.copy_(torch.from_numpy(b))
+    xu = buf_x[1:].view(n, k)
+    xu.zero_()
+    s2 = gpu_solver(lib, A, k)
+    x_un, info_un = s2.solve(bv, tol=1e-10, maxit=500, out=xu)
+    assert x_un.data_ptr() % 16 == 8
+    assert np.array_equal(info_al.iters, info_un.iters)
+    assert np.array_equal(to_np(x_al), to_np(x_un))
+
+
 def test_spmm_long_rows_and_empty_rows(lib):
     """Rows longer than the LDS budget take the split path (different
     summation order: a few ulp); empty rows give zeros."""
@@ -464,18 +500,20 @@ def fused_dot(A, k):
 
 
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
-def test_bitwise_fused(lib, precond):
+@pytest.mark.parametrize("k", [5, 6])
+def test_bitwise_fused(lib, precond, k):
     """The fused classical form, 20 fixed passes and a converged solve, per
     column (each column's oracle run gets its own dot schedule): iterates,
-    pass counts and statuses equal the oracle's in the kernels' order."""
+    pass counts and statuses equal the oracle's in the kernels' order. Odd k
+    runs the product one column per lane, even k two (k = 6: a padded lane
+    pair)."""
     import torch
 
     A = conv_diff(17, 3, (1.0, 0.7, 0.3))
-    k = 5
     b, _ = manufactured_rhs(A, k, seed=22)
     S = A.to_scipy()
     for tol, maxit in ((0.0, 20), (1e-10, 3000)):
-        say(f"bitwise fused {precond} tol={tol}")
+        say(f"bitwise fused {precond} k={k} tol={tol}")
         s = gpu_solver(lib, A, k, "classical", "fused", precond)
         x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=maxit)
         X = to_np(x)
