@@ -1,4 +1,6 @@
-"""Build libbicgstab.so (gfx950) in-tree with hipcc.
+"""Build libbicgstab.so (gfx950) in-tree with hipcc, and the host executor
+libbicgstab_host.so (the same launch plans on the host's cores) with g++ and
+OpenMP.
 
 Usage: python -m paper_1907_12874_amd.build
 """
@@ -15,7 +17,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbicgstab.so")
+LIB_HOST = os.path.join(PKG, "libbicgstab_host.so")
 SOURCES = ["kernels.hip", "spmm.hip", "batched.hip", "api.hip", "plans.cpp"]
+HOST_SOURCES = ["host.cpp", "plans.cpp"]
+# The host executor: plain C++ (no HIP), no contraction so its updates round
+# like the GPU's and the oracle's.
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-I", INCLUDE]
 
 # -ffp-contract=off: no fused multiply-add contraction, so the vector updates
 # and products round like their plain definitions. The packed-FP32 feature is
@@ -71,7 +78,22 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_host(verbose)
     return LIB
+
+
+def build_host(verbose: bool = False) -> str:
+    cxx = shutil.which("g++") or "/usr/bin/g++"
+    srcs = [os.path.join(CSRC, s) for s in HOST_SOURCES]
+    tmp = LIB_HOST + ".tmp"
+    cmd = [cxx, *HOST_FLAGS, "-shared", *srcs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building the host executor failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB_HOST)
+    return LIB_HOST
 
 
 if __name__ == "__main__":

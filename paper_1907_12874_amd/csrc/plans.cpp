@@ -13,7 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "internal.hpp"
+#include "plan.hpp"
 
 namespace bcg {
 

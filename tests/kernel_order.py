@@ -171,3 +171,17 @@ def scheduled_dot(first, cycle):
         return f(u, w)
 
     return dot
+
+
+def host_dot(n, threads):
+    """Dot of two length-n columns as the host executor sums it: range t of
+    `threads` holds rows [n t / T, n (t+1) / T) and sums them in row order
+    from 0; the range sums are added in order from 0."""
+    bounds = [n * t // threads for t in range(threads + 1)]
+
+    def dot(u, w):
+        p = np.multiply(u, w)
+        parts = [np.add.accumulate(np.concatenate(([0.0], p[bounds[t]:bounds[t + 1]])))[-1] for t in range(threads)]
+        return float(np.add.accumulate(np.concatenate(([0.0], parts)))[-1])
+
+    return dot

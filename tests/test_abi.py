@@ -12,10 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
 
 
-def header_functions():
+def header_functions(header=None):
+    """bicgstab_* functions declared in include/<header> (all headers if None)."""
     names = set()
     for fn in os.listdir(os.path.join(ROOT, "include")):
-        if fn.endswith(".h"):
+        if fn.endswith(".h") and (header is None or fn == header):
             txt = open(os.path.join(ROOT, "include", fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
             names |= set(re.findall(r"\b(bicgstab_\w+)\s*\(", txt))
@@ -29,20 +30,43 @@ def L():
     return _lib.lib()
 
 
+@pytest.fixture(scope="module")
+def LH():
+    from paper_1907_12874_amd import host
+
+    return host.lib_host()
+
+
 def test_header_declares_functions():
-    names = header_functions()
+    names = header_functions("bicgstab.h")
     assert "bicgstab_create" in names and "bicgstab_solve" in names and len(names) >= 15
+    assert header_functions("bicgstab_host.h") == ["bicgstab_host_create", "bicgstab_host_destroy",
+                                                   "bicgstab_host_last_error", "bicgstab_host_solve"]
 
 
-def test_library_exports_every_declared_symbol(L):
-    missing = [n for n in header_functions() if not hasattr(L, n)]
+def test_library_exports_every_declared_symbol(L, LH):
+    missing = [n for n in header_functions("bicgstab.h") if not hasattr(L, n)]
+    assert not missing, missing
+    missing = [n for n in header_functions("bicgstab_host.h") if not hasattr(LH, n)]
     assert not missing, missing
 
 
 def test_binding_covers_header(L):
     from paper_1907_12874_amd import _lib
 
-    assert set(_lib.exported_symbols()) <= set(header_functions())
+    assert set(_lib.exported_symbols()) <= set(header_functions("bicgstab.h"))
+
+
+def test_gpu_library_has_no_host_executor(L):
+    """The host executor lives in its own library: the GPU library neither
+    exports its entry points nor links it."""
+    import subprocess
+
+    from paper_1907_12874_amd import _lib
+
+    assert not hasattr(L, "bicgstab_host_solve")
+    deps = subprocess.run(["ldd", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "libbicgstab_host" not in deps
 
 
 # Table 2 names -> (variant, preconditioner) of this library

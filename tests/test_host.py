@@ -1,0 +1,119 @@
+"""The host executor (libbicgstab_host.so): the launch plans of the GPU library
+run on the host's cores. Parity with the oracle is bitwise once the oracle's
+dot product is summed in the executor's documented order (per fixed row range
+in row order, then over the ranges): the per-element updates, products and
+scalar recurrences round the same way on both sides. CPU only."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+import oracle  # noqa: E402
+from kernel_order import host_dot, oracle_dot  # noqa: E402
+from workloads import CSR, conv_diff, manufactured_rhs, random_sparse  # noqa: E402
+
+METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic")
+           for p in ("none", "jacobi")] + [("improved", "merged", "none"), ("improved", "basic", "none"),
+                                            ("classical", "fused", "none"), ("classical", "fused", "jacobi")]
+
+
+@pytest.fixture(scope="module")
+def host():
+    from paper_1907_12874_amd import host as h
+
+    h.lib_host()
+    return h
+
+
+def _solve(host, A, b, v, f, p, T, tol, maxit, x0=None):
+    s = host.HostSolver.from_csr(A, b.shape[1], variant=v, formulation=f, precond=p, threads=T)
+    return s.solve(b, x0=x0, tol=tol, maxit=maxit)
+
+
+def _ref(A, b, v, f, p, T, tol, maxit, x0=None):
+    with oracle_dot(host_dot(A.n, T)):
+        return oracle.solve(A.to_scipy(), b, X0=x0, variant=v, formulation=f, precond=p, tol=tol, maxit=maxit)
+
+
+@pytest.mark.parametrize("variant,formulation,precond", METHODS)
+def test_bitwise_fixed_passes_and_converged(host, variant, formulation, precond):
+    """15 passes with the stop test off, then a solve to 1e-10, with 1 and 4
+    row ranges: iterates, pass counts and statuses equal the oracle's."""
+    A = conv_diff(11, 3, (1.0, 0.7, 0.3))
+    b, _ = manufactured_rhs(A, 3, seed=31)
+    for T in (1, 4):
+        for tol, maxit in ((0.0, 15), (1e-10, 500)):
+            x, info = _solve(host, A, b, variant, formulation, precond, T, tol, maxit)
+            ref = _ref(A, b, variant, formulation, precond, T, tol, maxit)
+            assert np.array_equal(info.iters, ref.iters) and np.array_equal(info.status, ref.status), (T, tol)
+            assert np.array_equal(x, ref.x), (T, tol, np.abs(x - ref.x).max())
+
+
+def test_random_sparse_ragged_ranges_and_x0(host):
+    """A random nonsymmetric matrix whose size does not divide by the thread
+    count, a nonzero initial guess, 7 row ranges."""
+    A = random_sparse(1001, 7, seed=4)
+    rng = np.random.default_rng(2)
+    b = rng.uniform(-1, 1, (A.n, 5))
+    x0 = rng.uniform(-0.1, 0.1, (A.n, 5))
+    for v, f, p in (("classical", "merged", "jacobi"), ("pipelined", "merged", "none"), ("improved", "merged", "none")):
+        x, info = _solve(host, A, b, v, f, p, 7, 1e-9, 400, x0=x0)
+        ref = _ref(A, b, v, f, p, 7, 1e-9, 400, x0=x0)
+        assert np.array_equal(info.iters, ref.iters) and np.array_equal(x, ref.x), (v, f, p)
+        assert np.all(info.status == 0)
+        r = b - A.to_scipy() @ x
+        assert np.allclose(info.relres_true, np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0), rtol=1e-6)
+
+
+def test_edge_columns_and_sizes(host):
+    """A zero right-hand side column (x = 0, 0 passes), maxit = 0 (every
+    column MAXIT, x untouched), n = 0, more ranges than rows, repeatability."""
+    A = conv_diff(6, 2, (1.0, 0.5))
+    b, _ = manufactured_rhs(A, 3, seed=5)
+    b[:, 1] = 0.0
+    x, info = _solve(host, A, b, "classical", "merged", "jacobi", 3, 1e-10, 300)
+    ref = _ref(A, b, "classical", "merged", "jacobi", 3, 1e-10, 300)
+    assert np.array_equal(x, ref.x) and np.array_equal(info.iters, ref.iters)
+    assert info.iters[1] == 0 and info.status[1] == 0 and np.all(x[:, 1] == 0)
+    x0 = np.full((A.n, 3), 0.25)
+    x, info = _solve(host, A, b, "pipelined", "merged", "none", 2, 1e-10, 0, x0=x0)
+    assert np.all(info.status[[0, 2]] == 1) and np.all(info.iters == 0)
+    E = CSR(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    x, info = _solve(host, E, np.zeros((0, 2)), "classical", "merged", "none", 4, 1e-8, 10)
+    assert x.shape == (0, 2) and np.all(info.status == 0) and np.all(info.iters == 0)
+    x1, i1 = _solve(host, A, b, "reordered", "merged", "jacobi", 64, 1e-10, 300)
+    x2, i2 = _solve(host, A, b, "reordered", "merged", "jacobi", 64, 1e-10, 300)
+    ref = _ref(A, b, "reordered", "merged", "jacobi", 64, 1e-10, 300)
+    assert np.array_equal(x1, x2) and np.array_equal(x1, ref.x) and np.array_equal(i1.iters, ref.iters)
+
+
+def test_errors(host):
+    """Invalid input and unsupported combinations are errors, as in the GPU
+    library's create."""
+    from paper_1907_12874_amd._lib import EINVAL, EUNSUPPORTED, BicgstabError
+
+    A = conv_diff(5, 2, (1.0, 0.5))
+    with pytest.raises(BicgstabError) as e:
+        host.HostSolver.from_csr(A, 2, variant="improved", precond="jacobi")
+    assert e.value.code == EUNSUPPORTED
+    with pytest.raises(BicgstabError) as e:
+        host.HostSolver.from_csr(A, 2, variant="pipelined", formulation="fused")
+    assert e.value.code == EUNSUPPORTED
+    bad = CSR(A.n, A.row_ptr, A.col_idx.copy(), A.values)
+    bad.col_idx[3] = A.n
+    with pytest.raises(BicgstabError) as e:
+        host.HostSolver.from_csr(bad, 1)
+    assert e.value.code == EINVAL
+    nodiag = CSR(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(BicgstabError) as e:
+        host.HostSolver.from_csr(nodiag, 1, precond="jacobi")
+    assert e.value.code == EINVAL and "zero diagonal" in str(e.value)
+    with pytest.raises(BicgstabError):
+        host.HostSolver.from_csr(A, 65)
+    with pytest.raises(BicgstabError):
+        host.HostSolver.from_csr(A, 1, threads=0)
