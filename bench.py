@@ -297,6 +297,76 @@ def tier_autograd(pk, dev, maxit):
             "backward_over_forward": round((tb - tf) / tf, 3), "grad_finite": bool(torch.isfinite(g).all())}
 
 
+TAB4_METHODS = {  # Table 4 rows -> (variant, preconditioner)
+    "BiCGStab": ("classical", "none"),
+    "IBiCGStab": ("improved", "none"),
+    "PipeBiCGStab": ("pipelined", "none"),
+    "PBiCGStab": ("classical", "jacobi"),
+    "RBiCGStab": ("reordered", "jacobi"),
+    "PPipeBiCGStab": ("pipelined", "jacobi"),
+}
+
+
+def host_tab4(pk, grid, reps, threads, run_s=0.25):
+    """Table 4 on the host's cores: one iteration of each method, basic and
+    merged, for m = 1, 4, 16 right-hand sides of the 7-point Poisson matrix
+    (the paper's matrix at grid^3 instead of 200^3), by the host executor of
+    the same launch plans. Per-iteration time = the executor's own timing of
+    the iteration loop of a fixed-pass solve (set-up and exit excluded) of
+    about run_s seconds; basic and merged runs alternate, best of `reps`.
+    Reports the time reduction of merging beside the traffic model's
+    prediction (1 - bytes merged / bytes basic) and the paper's figures."""
+    import json
+
+    # keep OpenMP threads on their cores (read when the executor loads)
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    from paper_1907_12874_amd.host import HostSolver
+    from workloads import conv_diff
+
+    A = conv_diff(grid, 3, (0.0, 0.0, 0.0))
+    n, nnz = A.n, A.nnz
+    paper = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))["table4_merging_effect"]
+    rng = np.random.default_rng(0)
+    rows = []
+    t_all = time.perf_counter()
+    for m in (1, 4, 16):
+        b = rng.uniform(-1, 1, (n, m))
+        for name, (variant, precond) in TAB4_METHODS.items():
+            r = {"method": name, "m": m}
+            sol, passes, best = {}, {}, {}
+            for form in ("basic", "merged"):
+                sol[form] = HostSolver.from_csr(A, m, variant=variant, formulation=form, precond=precond,
+                                                threads=threads)
+                sol[form].solve(b, tol=0.0, maxit=2)
+                sec, ran = sol[form].loop_time()
+                passes[form] = int(max(2, min(200, run_s / max(sec / max(ran, 1), 1e-6))))
+                best[form] = float("inf")
+            for _ in range(reps):
+                for form in ("basic", "merged"):
+                    sol[form].solve(b, tol=0.0, maxit=passes[form])
+                    sec, ran = sol[form].loop_time()
+                    best[form] = min(best[form], sec / max(ran, 1))
+            for form in ("basic", "merged"):
+                sol[form].close()
+                ib = iteration_bytes(n, nnz, m, pk.plan_traffic(variant, form, precond))
+                r[f"{form}_ms"] = round(best[form] * 1e3, 3)
+                r[f"{form}_GBps"] = round(ib / best[form] / 1e9, 2)
+                r[f"{form}_bytes"] = ib
+                r[f"{form}_passes"] = passes[form]
+            r["improvement"] = round(1 - r["merged_ms"] / r["basic_ms"], 4)
+            r["model_improvement"] = round(1 - r["merged_bytes"] / r["basic_bytes"], 4)
+            mi = paper["m"].index(m)
+            r["paper_improvement"] = paper["rows"][name][mi][2] / 100.0
+            rows.append(r)
+            print(f"# host tab4 m={m:2d} {name:14s}: basic {r['basic_ms']:8.2f} ms merged {r['merged_ms']:8.2f} ms "
+                  f"imp {r['improvement']:6.1%} (model {r['model_improvement']:5.1%}, paper "
+                  f"{r['paper_improvement']:4.0%}), {r['merged_GBps']:.1f} GB/s", file=sys.stderr, flush=True)
+    return {"workload": f"7-point Poisson {grid}^3 (n={n}, nnz={nnz}), m = 1, 4, 16, fixed passes; the "
+                        f"preconditioned rows use Jacobi (a uniform scaling here: constant diagonal) where the "
+                        f"paper used the identity",
+            "threads": threads, "reps": reps, "seconds": round(time.perf_counter() - t_all, 1), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +383,9 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--sweep-passes", type=int, default=20)
+    ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
+    ap.add_argument("--host-grid", type=int, default=96)
+    ap.add_argument("--host-reps", type=int, default=3)
     ap.add_argument("--sweep-k", default="1,2,4,8,16,32")
     ap.add_argument("--maxit", type=int, default=5000, help="pass cap (lower it for profiled runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -470,6 +543,11 @@ def main():
             tiers[name] = fn(pk, dev, args.maxit)
             print(f"# tier {name}: {json.dumps(tiers[name])}", file=sys.stderr, flush=True)
         out["tiers"] = tiers
+
+    # ------------------------------------------- host cores: Table 4
+    if not args.no_host:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        out["host_tab4"] = host_tab4(pk, args.host_grid, args.host_reps, threads)
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu:

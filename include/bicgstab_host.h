@@ -66,6 +66,11 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
 int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double tol, int32_t maxit,
                         bicgstab_info* info);
 
+/* Wall time of the last solve's iteration loop (the passes only: set-up,
+ * start-up passes and the exit residual excluded) and the passes it ran, for
+ * per-iteration timing of fixed-pass solves (tol = 0). */
+int bicgstab_host_loop_time(bicgstab_host_t h, double* seconds, int32_t* passes);
+
 /* Release the solver (NULL is ignored). */
 int bicgstab_host_destroy(bicgstab_host_t h);
 

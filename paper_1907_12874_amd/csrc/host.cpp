@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <memory>
 #include <string>
 #include <vector>
@@ -53,6 +54,8 @@ struct bicgstab_host_ctx {
   Globals glob{};
   std::vector<double> red;  // per-range dot partials: threads x 7 x k
   Ctl ctl{};
+  double loop_seconds = 0.0;  // wall time of the last solve's iteration loop
+  int loop_passes = 0;        // passes that loop ran
 };
 
 namespace {
@@ -375,6 +378,8 @@ int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double to
   h->glob.maxit = maxit;
   h->glob.tol = tol;
   int rc = BICGSTAB_OK;
+  h->loop_seconds = 0.0;
+  h->loop_passes = 0;
   if (h->n > 0) {
     for (const Step& st : h->plan.init)
       if ((rc = run_step(*h, st, vp))) return rc;
@@ -386,11 +391,15 @@ int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double to
         }
       h->glob.nrun = 0;
     } else {
-      for (int64_t pass = 0; h->glob.nrun > 0; ++pass) {
+      const auto t0 = std::chrono::steady_clock::now();
+      int64_t pass = 0;
+      for (; h->glob.nrun > 0; ++pass) {
         if (pass > (int64_t)maxit + 2) return fail(BICGSTAB_EINVAL, "iteration counter did not reach maxit");
         for (const Step& st : h->plan.iter)
           if ((rc = run_step(*h, st, vp))) return rc;
       }
+      h->loop_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      h->loop_passes = (int)pass;
     }
     // exit: true residual b - A x and ||r|| for every column
     spmm(*h, h->rp, h->col, h->val, x, vp[V_V]);
@@ -414,6 +423,13 @@ int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double to
       if (info->relres_true) info->relres_true[c] = h->n > 0 ? SCh(*h, S_RELRES_TRUE, c) : 0.0;
       if (info->relres_recursive) info->relres_recursive[c] = h->n > 0 ? SCh(*h, S_RELRES_REC, c) : 0.0;
     }
+  return BICGSTAB_OK;
+}
+
+int bicgstab_host_loop_time(bicgstab_host_t h, double* seconds, int32_t* passes) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (seconds) *seconds = h->loop_seconds;
+  if (passes) *passes = h->loop_passes;
   return BICGSTAB_OK;
 }
 

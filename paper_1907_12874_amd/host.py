@@ -41,6 +41,7 @@ def lib_host():
     H, i32, dbl, vp = C.c_void_p, C.c_int32, C.c_double, C.c_void_p
     L.bicgstab_host_create.argtypes = [C.POINTER(HostCSRDesc), i32, i32, i32, i32, i32, C.POINTER(H)]
     L.bicgstab_host_solve.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
+    L.bicgstab_host_loop_time.argtypes = [H, C.POINTER(dbl), C.POINTER(i32)]
     L.bicgstab_host_destroy.argtypes = [H]
     L.bicgstab_host_last_error.argtypes = []
     L.bicgstab_host_last_error.restype = C.c_char_p
@@ -90,6 +91,12 @@ class HostSolver:
         _check(lib_host().bicgstab_host_solve(self._h, b.ctypes.data, x.ctypes.data, float(tol), int(maxit),
                                               C.byref(info)), "bicgstab_host_solve")
         return x, SolveInfo(*arrs)
+
+    def loop_time(self):
+        """(seconds, passes) of the last solve's iteration loop."""
+        sec, passes = C.c_double(), C.c_int32()
+        _check(lib_host().bicgstab_host_loop_time(self._h, C.byref(sec), C.byref(passes)), "bicgstab_host_loop_time")
+        return sec.value, passes.value
 
     def close(self):
         if getattr(self, "_h", None):

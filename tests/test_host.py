@@ -117,3 +117,29 @@ def test_errors(host):
         host.HostSolver.from_csr(A, 65)
     with pytest.raises(BicgstabError):
         host.HostSolver.from_csr(A, 1, threads=0)
+
+
+def test_loop_time_counts_the_passes(host):
+    """The executor's own loop timer covers exactly the passes run."""
+    A = conv_diff(8, 3, (0.0, 0.0, 0.0))
+    b, _ = manufactured_rhs(A, 2, seed=1)
+    s = host.HostSolver.from_csr(A, 2, variant="pipelined", precond="jacobi", threads=2)
+    s.solve(b, tol=0.0, maxit=7)
+    sec, passes = s.loop_time()
+    assert passes == 7 and sec > 0.0
+    s.solve(b, tol=0.0, maxit=0)
+    assert s.loop_time() == (0.0, 0)
+
+
+def test_table4_fixture_is_consistent():
+    """The stored Table 4 figures: each improvement equals 1 - merged / basic
+    of its row up to the rounding of the printed times, and merging never
+    makes an iteration slower."""
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))["table4_merging_effect"]
+    assert g["m"] == [1, 4, 16] and len(g["rows"]) == 6
+    for name, cells in g["rows"].items():
+        for basic, merged, imp in cells:
+            assert merged <= basic
+            assert abs(imp - 100 * (1 - merged / basic)) <= 1.5, (name, basic, merged, imp)
