@@ -367,6 +367,29 @@ def host_tab4(pk, grid, reps, threads, run_s=0.25):
             "threads": threads, "reps": reps, "seconds": round(time.perf_counter() - t_all, 1), "rows": rows}
 
 
+def host_baseline(A, b, variant, formulation, precond, threads, run_s=1.0):
+    """The host executor on the headline workload (same matrix, k and
+    method): fixed passes on `threads` cores, RHS-iterations/s of the
+    iteration loop (best of two runs of about run_s seconds)."""
+    from paper_1907_12874_amd.host import HostSolver
+
+    k = b.shape[1]
+    hs = HostSolver.from_csr(A, k, variant=variant, formulation=formulation, precond=precond, threads=threads)
+    hs.solve(b, tol=0.0, maxit=1)
+    sec, ran = hs.loop_time()
+    passes = int(max(2, min(100, run_s / max(sec / max(ran, 1), 1e-6))))
+    best = float("inf")
+    for _ in range(2):
+        hs.solve(b, tol=0.0, maxit=passes)
+        sec, ran = hs.loop_time()
+        best = min(best, sec / max(ran, 1))
+    hs.close()
+    return {"value": round(k / best, 2), "unit": "RHS-iterations/s", "cores": threads, "kind": "host executor",
+            "ms_per_iteration": round(best * 1e3, 3), "passes": passes,
+            "sample": f"{variant}/{formulation}/{precond}, all {k} columns of the headline workload, {passes} fixed "
+                      f"passes, libbicgstab_host.so on {threads} OpenMP threads"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,7 +407,7 @@ def main():
     ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
-    ap.add_argument("--host-grid", type=int, default=96)
+    ap.add_argument("--host-grid", type=int, default=160)
     ap.add_argument("--host-reps", type=int, default=3)
     ap.add_argument("--sweep-k", default="1,2,4,8,16,32")
     ap.add_argument("--maxit", type=int, default=5000, help="pass cap (lower it for profiled runs)")
@@ -548,6 +571,10 @@ def main():
     if not args.no_host:
         threads = max(1, min(16, os.cpu_count() or 1))
         out["host_tab4"] = host_tab4(pk, args.host_grid, args.host_reps, threads)
+        out["host_executor_baseline"] = host_baseline(A, cfg["b"], args.variant, args.formulation, args.precond,
+                                                      threads)
+        print(f"# host executor ({threads} threads): {out['host_executor_baseline']['value']} RHS-it/s",
+              file=sys.stderr, flush=True)
 
     # ------------------------------------------------------- CPU baseline
     if not args.no_cpu:
