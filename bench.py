@@ -119,7 +119,7 @@ def kernel_source_sha():
     import hashlib
 
     h = hashlib.sha256()
-    for fn in ("spmm.hip", "kernels.hip"):
+    for fn in ("spmm.hip", "kernels.hip", "method.hpp", "reduce.hpp"):
         with open(os.path.join(ROOT, "paper_1907_12874_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
