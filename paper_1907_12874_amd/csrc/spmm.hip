@@ -4,11 +4,12 @@
 // entries fit in LDS. A workgroup stages its block's column indices, values
 // and row offsets with coalesced loads, then each group of kp / CPL lanes
 // (kp = k rounded up to a power of two) computes the k outputs of one row,
-// CPL adjacent columns per lane. For even k a lane takes two columns (CPL = 2):
-// one 16-byte gather per entry instead of two 8-byte ones, which halves the
-// gather instructions and measured 15-25% faster on the 128^3 stencil at
-// k = 4..32; it takes its rows one at a time. For odd k (CPL = 1) a lane takes
-// its rows two at a time and issues the gathers of both before it adds any.
+// CPL adjacent columns per lane. Where k allows, a lane's columns fill one
+// 16-byte gather per entry (two FP64 or four FP32 columns) instead of several
+// narrower ones, which cuts the gather instructions and measured 15-25% faster
+// on the 128^3 stencil at k = 4..32 (FP64, two columns); such a lane takes its
+// rows one at a time. With one column (odd k) a lane takes its rows two at a
+// time and issues the gathers of both before it adds any.
 // Either way the products of a row are added in entry order, the rounding of a
 // plain sequential sum. Two forms of the inner loop: the plain product guards
 // each slot and reads a product's value with its column index (STYLE 0); the
@@ -77,21 +78,21 @@ __device__ __forceinline__ T load_x(const T* X, int j, int k, int c) {
   }
 }
 
-template <class T>
-struct Pair {
-  typedef T type __attribute__((ext_vector_type(2)));
+template <class T, int N>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(N)));
 };
 
-// Elements (j, c) and (j, c + 1) of X in one load (c even, k even, X aligned
-// to two elements).
-template <class T, bool OFF32>
-__device__ __forceinline__ typename Pair<T>::type load_x2(const T* X, int j, int k, int c) {
-  typedef typename Pair<T>::type P2;
+// Elements (j, c) .. (j, c + N - 1) of X in one load (c a multiple of N, k a
+// multiple of N, X aligned to N elements).
+template <class T, int N, bool OFF32>
+__device__ __forceinline__ typename VecOf<T, N>::type load_xv(const T* X, int j, int k, int c) {
+  typedef typename VecOf<T, N>::type V;
   if constexpr (OFF32) {
     const unsigned off = ((unsigned)j * (unsigned)k + (unsigned)c) * (unsigned)sizeof(T);
-    return *(const __attribute__((address_space(1))) P2*)((gcchar*)X + off);
+    return *(const __attribute__((address_space(1))) V*)((gcchar*)X + off);
   } else {
-    return *(const P2*)(X + (size_t)j * k + c);
+    return *(const V*)(X + (size_t)j * k + c);
   }
 }
 
@@ -101,10 +102,10 @@ __device__ __forceinline__ void store_y(T* Y, int row, int k, int c, const T (&v
   if constexpr (CPL == 1) {
     __builtin_nontemporal_store(v[0], Y + (size_t)row * k + c);
   } else {
-    typename Pair<T>::type t;
-    t.x = v[0];
-    t.y = v[1];
-    __builtin_nontemporal_store(t, (typename Pair<T>::type*)(Y + (size_t)row * k + c));
+    typename VecOf<T, CPL>::type t;
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) t[h] = v[h];
+    __builtin_nontemporal_store(t, (typename VecOf<T, CPL>::type*)(Y + (size_t)row * k + c));
   }
 }
 
@@ -126,9 +127,9 @@ struct DotEpilogue {
     if constexpr (CPL == 1) {
       w[0] = W[(size_t)row * k + c];
     } else {
-      const typename Pair<T>::type t = *(const typename Pair<T>::type*)(W + (size_t)row * k + c);
-      w[0] = t.x;
-      w[1] = t.y;
+      const typename VecOf<T, CPL>::type t = *(const typename VecOf<T, CPL>::type*)(W + (size_t)row * k + c);
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) w[h] = t[h];
     }
 #pragma unroll
     for (int h = 0; h < CPL; ++h) {
@@ -158,7 +159,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
   const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
   const int ne = e1 - e0;
   const T* __restrict__ val = static_cast<const T*>(A.val);
-  constexpr int LPL = KPL - (CPL == 2 ? 1 : 0);  // log2 of the lanes per row
+  constexpr int LPL = KPL - (CPL == 4 ? 2 : CPL == 2 ? 1 : 0);  // log2 of the lanes per row
   constexpr int lpr = 1 << LPL;
   constexpr int rpp = BS >> LPL;                  // rows per pass of the workgroup
   const int c = (threadIdx.x & (lpr - 1)) * CPL;
@@ -172,47 +173,51 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
     __syncthreads();
     if (c >= k) return;
     const int nr = r1 - r0;
-    if constexpr (CPL == 2) {
+    if constexpr (CPL > 1) {
+      typedef typename VecOf<T, CPL>::type V;
       for (int r = rsub; r < nr; r += rpp) {
         const int eb = s_rp[r], ee = s_rp[r + 1];
-        T s0 = (T)0, s1 = (T)0;
+        T sv[CPL];
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) sv[h] = (T)0;
         if constexpr (STYLE == 0) {
           for (int o = eb; o < ee; o += 8) {
             T av[8];
-            typename Pair<T>::type xv[8];
+            V xv[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
               if (o + j < ee) {
                 av[j] = s_val[o + j];
-                xv[j] = load_x2<T, OFF32>(X, s_col[o + j], k, c);
+                xv[j] = load_xv<T, CPL, OFF32>(X, s_col[o + j], k, c);
               }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-              if (o + j < ee) {
-                s0 += av[j] * xv[j].x;
-                s1 += av[j] * xv[j].y;
-              }
+              if (o + j < ee)
+#pragma unroll
+                for (int h = 0; h < CPL; ++h) sv[h] += av[j] * xv[j][h];
           }
         } else {
           // branch-free: a slot past the row's end gathers row 0 of X and is
           // not added (a select)
           const int last = max(ee - 1, 0);
           for (int o = eb; o < ee; o += 8) {
-            typename Pair<T>::type xv[8];
+            V xv[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xv[j] = load_x2<T, OFF32>(X, o + j < ee ? s_col[min(o + j, last)] : 0, k, c);
+            for (int j = 0; j < 8; ++j)
+              xv[j] = load_xv<T, CPL, OFF32>(X, o + j < ee ? s_col[min(o + j, last)] : 0, k, c);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               const T a = s_val[min(o + j, last)];
-              const T t0 = s0 + a * xv[j].x, t1 = s1 + a * xv[j].y;
-              s0 = o + j < ee ? t0 : s0;
-              s1 = o + j < ee ? t1 : s1;
+#pragma unroll
+              for (int h = 0; h < CPL; ++h) {
+                const T t = sv[h] + a * xv[j][h];
+                sv[h] = o + j < ee ? t : sv[h];
+              }
             }
           }
         }
-        const T out[2] = {s0, s1};
-        store_y<T, 2>(Y, r0 + r, k, c, out);
-        epi(r0 + r, out);
+        store_y<T, CPL>(Y, r0 + r, k, c, sv);
+        epi(r0 + r, sv);
       }
     } else {
       for (int r = rsub; r < nr; r += 2 * rpp) {
@@ -302,10 +307,10 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
       __syncthreads();
       if (c < k)
         for (int e = rsub; e < m; e += rpp) {
-          if constexpr (CPL == 2) {
-            const typename Pair<T>::type xv = load_x2<T, OFF32>(X, s_col[e], k, c);
-            sum[0] += s_val[e] * xv.x;
-            sum[1] += s_val[e] * xv.y;
+          if constexpr (CPL > 1) {
+            const typename VecOf<T, CPL>::type xv = load_xv<T, CPL, OFF32>(X, s_col[e], k, c);
+#pragma unroll
+            for (int h = 0; h < CPL; ++h) sum[h] += s_val[e] * xv[h];
           } else {
             sum[0] += s_val[e] * load_x<T, OFF32>(X, s_col[e], k, c);
           }
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __rest
                                                       const Globals* glob) {
   if (glob->nrun == 0) return;
   constexpr int ND = EPI == E_DOT_W ? 1 : 3;
-  constexpr int LPL = KPL - (CPL == 2 ? 1 : 0);
+  constexpr int LPL = KPL - (CPL == 4 ? 2 : CPL == 2 ? 1 : 0);
   const int L = block_of(blockIdx.x, A.nblk, A.xcd_chunk);
   DotEpilogue<T, EPI, CPL> epi{W, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
   row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
@@ -374,12 +379,12 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
                      (size_t)(A.rows_cap + 1) * 4 + 16;
-  if (CPL == 2 && kp < 2) return hipErrorInvalidValue;
+  if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
-#define SPMM_CASE(KP, KPL)                                                                                       \
-  case KP:                                                                                                       \
-    hipLaunchKernelGGL((spmm_kernel<T, KPL, (KP >= 2 ? CPL : 1), BS, OFF32, STYLE>), dim3(grid), dim3(BS), lds, s, \
-                       A, x, y, k, glob);                                                                        \
+#define SPMM_CASE(KP, KPL)                                                                                         \
+  case KP:                                                                                                         \
+    hipLaunchKernelGGL((spmm_kernel<T, KPL, (KP >= CPL ? CPL : 1), BS, OFF32, STYLE>), dim3(grid), dim3(BS), lds, s, \
+                       A, x, y, k, glob);                                                                          \
     break;
     SPMM_CASE(1, 0)
     SPMM_CASE(2, 1)
@@ -401,12 +406,12 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
                      (size_t)(A.rows_cap + 1) * 4 + 16;
-  if (CPL == 2 && kp < 2) return hipErrorInvalidValue;
+  if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
-#define SPMM_DOT_CASE(KP, KPL)                                                                                  \
-  case KP:                                                                                                      \
-    hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, (KP >= 2 ? CPL : 1), BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), \
-                       lds, s, A, x, y, w, k, bpart, glob);                                                     \
+#define SPMM_DOT_CASE(KP, KPL)                                                                                    \
+  case KP:                                                                                                        \
+    hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, (KP >= CPL ? CPL : 1), BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), \
+                       lds, s, A, x, y, w, k, bpart, glob);                                                       \
     break;
     SPMM_DOT_CASE(1, 0)
     SPMM_DOT_CASE(2, 1)
@@ -424,23 +429,32 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k
 // X block bytes below 4 GiB: 32-bit gather offsets.
 inline bool off32(const SpmmMat& A, int k, size_t elem) { return (size_t)A.n * (size_t)k * elem < ((size_t)1 << 32); }
 
-// Two columns per lane need even k and operands aligned to two elements;
-// otherwise (a caller's pointer into the middle of a block) one column per
-// lane, with the same sums.
+// Columns per lane of a launch: one 16-byte gather per entry where k and the
+// operands' alignment allow it (two FP64 or four FP32 columns), else two
+// FP32 columns (8 bytes), else one column; the sums are the same whichever.
 template <class T>
-bool wide_ok(int k, std::initializer_list<const void*> ptrs) {
-  if (spmm_cols_per_lane(k) != 2) return false;
-  for (const void* p : ptrs)
-    if (((uintptr_t)p % (2 * sizeof(T))) != 0) return false;
-  return true;
+int lane_cols(int k, std::initializer_list<const void*> ptrs) {
+  auto aligned = [&](size_t a) {
+    for (const void* p : ptrs)
+      if (((uintptr_t)p % a) != 0) return false;
+    return true;
+  };
+  if (sizeof(T) == 4 && k % 4 == 0 && aligned(16)) return 4;
+  if (k % 2 == 0 && aligned(2 * sizeof(T))) return 2;
+  return 1;
 }
 
 template <class T>
 hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const Globals* glob, hipStream_t s) {
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
-  return wide_ok<T>(k, {X, Y}) ? spmm_launch_bs<T, 2, kSpmmBlock, false, 0>(A, x, y, k, glob, s)
-                               : spmm_launch_bs<T, 1, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+  switch (lane_cols<T>(k, {X, Y})) {
+    case 4:
+      if constexpr (sizeof(T) == 4) return spmm_launch_bs<T, 4, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+      return hipErrorInvalidValue;
+    case 2: return spmm_launch_bs<T, 2, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+    default: return spmm_launch_bs<T, 1, kSpmmBlock, false, 0>(A, x, y, k, glob, s);
+  }
 }
 
 template <class T, int CPL>
@@ -462,8 +476,13 @@ hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const voi
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
   const T* w = static_cast<const T*>(W);
-  return wide_ok<T>(k, {X, Y, W}) ? spmm_dot_dispatch_cpl<T, 2>(A, x, y, w, epi, k, bpart, glob, s)
-                                  : spmm_dot_dispatch_cpl<T, 1>(A, x, y, w, epi, k, bpart, glob, s);
+  switch (lane_cols<T>(k, {X, Y, W})) {
+    case 4:
+      if constexpr (sizeof(T) == 4) return spmm_dot_dispatch_cpl<T, 4>(A, x, y, w, epi, k, bpart, glob, s);
+      return hipErrorInvalidValue;
+    case 2: return spmm_dot_dispatch_cpl<T, 2>(A, x, y, w, epi, k, bpart, glob, s);
+    default: return spmm_dot_dispatch_cpl<T, 1>(A, x, y, w, epi, k, bpart, glob, s);
+  }
 }
 
 }  // namespace
