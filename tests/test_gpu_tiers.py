@@ -66,21 +66,28 @@ def test_precision_tier_matches_refinement_oracle(lib, variant, precond, formula
             assert abs(int(outer[c]) - ref["outer"]) <= 1, (c, outer[c], ref["outer"])
 
 
-def test_precision_tier_edge_columns(lib):
+@pytest.mark.parametrize("k", [3, 6, 4])
+def test_precision_tier_edge_columns(lib, k):
+    """A zero right-hand side column and a nonzero x0 in the FP32 tier, for
+    the three FP32 product layouts (k = 3: one column per lane, 6: two, 4:
+    four): every column converges in FP64 terms, the zero column stays 0."""
     import torch
 
-    say("precision tier edges")
+    say(f"precision tier edges k={k}")
     A = conv_diff(8, 3, (1.0, 0.7, 0.3))
     n = A.n
-    b, _ = manufactured_rhs(A, 3, seed=5)
+    b, _ = manufactured_rhs(A, k, seed=5)
     b[:, 1] = 0.0
-    s = lib.Solver.from_csr(A, 3, precision="fp32_refine")
-    x0 = torch.ones(n, 3, dtype=torch.float64).cuda()
+    s = lib.Solver.from_csr(A, k, precision="fp32_refine")
+    x0 = torch.ones(n, k, dtype=torch.float64).cuda()
     x, info = s.solve(torch.from_numpy(b).cuda(), x0, tol=1e-10, maxit=2000)
     X = x.cpu().numpy()
-    assert list(info.status) == [0, 0, 0]
+    assert list(info.status) == [0] * k
     assert np.all(X[:, 1] == 0)
-    assert np.all(info.relres_true[[0, 2]] < 1e-10)
+    others = [c for c in range(k) if c != 1]
+    assert np.all(info.relres_true[others] < 1e-10)
+    rt = np.linalg.norm(b - A.to_scipy() @ X, axis=0)[others] / np.linalg.norm(b, axis=0)[others]
+    assert np.all(rt < 1e-10)
 
 
 # --------------------------------------------------------- differentiation ---
