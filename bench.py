@@ -390,6 +390,57 @@ def host_baseline(A, b, variant, formulation, precond, threads, run_s=1.0):
                       f"passes, libbicgstab_host.so on {threads} OpenMP threads"}
 
 
+def axpby_tab1_gpu(pk, n=10**8, reps=5):
+    """Table 1 on the GPU: the three runs of vector updates on n doubles,
+    median of `reps` timed with HIP events on torch's stream (the library
+    enqueues on it)."""
+    import torch
+
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.rand(n, dtype=torch.float64, device="cuda")
+    z = torch.rand(n, dtype=torch.float64, device="cuda")
+    out = {}
+    for run in (1, 2, 3):
+        pk.axpby_tab1(run, x, y, z, 0.5, 0.25, 0.125)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pk.axpby_tab1(run, x, y, z, 0.5, 0.25, 0.125)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[f"run{run}_ms"] = round(sorted(ts)[len(ts) // 2], 3)
+    moved = {1: 9, 2: 5, 3: 5}
+    for run in (1, 2, 3):
+        out[f"run{run}_GBps"] = round(moved[run] * n * 8 / (out[f"run{run}_ms"] * 1e-3) / 1e9, 1)
+    out["ratio_run1_run2"] = round(out["run1_ms"] / out["run2_ms"], 3)
+    out["ratio_run3_run2"] = round(out["run3_ms"] / out["run2_ms"], 3)
+    del x, y, z
+    return out
+
+
+def axpby_tab1_host(n=10**8, threads=16, reps=3):
+    """Table 1 on the host's cores (the host executor's loops), best of reps."""
+    from paper_1907_12874_amd.host import axpby_tab1
+
+    rng = np.random.default_rng(0)
+    x, y, z = rng.random(n), rng.random(n), rng.random(n)
+    out = {}
+    for run in (1, 2, 3):
+        axpby_tab1(run, x, y, z, 0.5, 0.25, 0.125, threads=threads)
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            axpby_tab1(run, x, y, z, 0.5, 0.25, 0.125, threads=threads)
+            best = min(best, time.perf_counter() - t0)
+        out[f"run{run}_ms"] = round(best * 1e3, 2)
+    out["ratio_run1_run2"] = round(out["run1_ms"] / out["run2_ms"], 3)
+    out["ratio_run3_run2"] = round(out["run3_ms"] / out["run2_ms"], 3)
+    out["threads"] = threads
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -566,6 +617,16 @@ def main():
             tiers[name] = fn(pk, dev, args.maxit)
             print(f"# tier {name}: {json.dumps(tiers[name])}", file=sys.stderr, flush=True)
         out["tiers"] = tiers
+
+    # ------------------------------------------------------------ Table 1
+    tab1 = {"n": 10**8, "paper_ratio_run1_run2": {"Lomonosov": round(207 / 117, 3),
+                                                   "Lomonosov-2": round(125 / 71, 3)},
+            "traffic_ratio_run1_run2": 1.8, "gpu": axpby_tab1_gpu(pk)}
+    print(f"# table 1 gpu: {json.dumps(tab1['gpu'])}", file=sys.stderr, flush=True)
+    if not args.no_host:
+        tab1["host"] = axpby_tab1_host(threads=max(1, min(16, os.cpu_count() or 1)))
+        print(f"# table 1 host: {json.dumps(tab1['host'])}", file=sys.stderr, flush=True)
+    out["axpby_tab1"] = tab1
 
     # ------------------------------------------- host cores: Table 4
     if not args.no_host:

@@ -250,6 +250,20 @@ int bicgstab_batched_variant_info(int32_t variant, int32_t* block, int32_t* rows
                                   int32_t* entries_per_step, int32_t* product_rows_per_step);
 int bicgstab_batched_destroy(bicgstab_batched_t h);
 
+/* The vector-update experiment of Section 2.1 (Table 1), which motivates
+ * merging: with scalars a, b, c and device vectors x, y, z of length n,
+ *   run 1: three passes  y = a x + b y;  z = b x + a z;  z = b y + c z
+ *          (9n elements moved),
+ *   run 2: one pass of the first two updates (5n elements),
+ *   run 3: one pass of all three updates, the same values as run 1 (5n).
+ * Each product and sum rounds as written (no contraction). y and z are
+ * updated in place. The work is enqueued on `stream` (a hipStream_t, NULL =
+ * the null stream) and the call returns without waiting, so the caller can
+ * time it with events. BICGSTAB_EINVAL for a run outside 1-3 or a null
+ * vector with n > 0. */
+int bicgstab_axpby_tab1(int32_t run, int64_t n, double a, double b, double c, const double* d_x, double* d_y,
+                        double* d_z, void* stream);
+
 /* Host-only query of the launch plan of one iteration (no device needed):
  * vector block reads and writes of its vector-operation passes (the counting
  * of Table 2), preconditioner applications, sparse products and kernel

@@ -71,6 +71,14 @@ int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double to
  * per-iteration timing of fixed-pass solves (tol = 0). */
 int bicgstab_host_loop_time(bicgstab_host_t h, double* seconds, int32_t* passes);
 
+/* Table 1's vector updates (Section 2.1) on host vectors of length n, on
+ * `threads` fixed row ranges: run 1 = three passes y = a x + b y,
+ * z = b x + a z, z = b y + c z; run 2 = the first two updates in one pass;
+ * run 3 = all three in one pass (the values of run 1). y, z updated in place;
+ * synchronous. */
+int bicgstab_host_axpby_tab1(int32_t run, int64_t n, double a, double b, double c, const double* x, double* y,
+                             double* z, int32_t threads);
+
 /* Release the solver (NULL is ignored). */
 int bicgstab_host_destroy(bicgstab_host_t h);
 

@@ -4,7 +4,7 @@ basic and merged), a HIP library for gfx950 behind a C ABI.
 The compute path is the in-tree libbicgstab.so; there is no CPU fallback.
 """
 from ._lib import BicgstabError, lib  # noqa: F401
-from .solver import Solver, SolveInfo, plan_traffic  # noqa: F401
+from .solver import Solver, SolveInfo, axpby_tab1, plan_traffic  # noqa: F401
 from . import batched  # noqa: F401
 from .batched import BatchedSolver  # noqa: F401
 

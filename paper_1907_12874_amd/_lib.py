@@ -70,6 +70,7 @@ def lib():
     L.bicgstab_refine_outer.argtypes = [H, C.POINTER(i32)]
     L.bicgstab_destroy.argtypes = [H]
     L.bicgstab_plan_traffic.argtypes = [i32, i32, i32] + [C.POINTER(i32)] * 5
+    L.bicgstab_axpby_tab1.argtypes = [i32, i64, dbl, dbl, dbl, vp, vp, vp, vp]
     L.bicgstab_strerror.argtypes = [C.c_int]
     L.bicgstab_strerror.restype = C.c_char_p
     L.bicgstab_last_error.argtypes = []
@@ -106,5 +107,5 @@ def exported_symbols():
         "bicgstab_refine_outer", "bicgstab_batched_create", "bicgstab_batched_workspace_bytes",
         "bicgstab_batched_set_workspace", "bicgstab_batched_set_stream", "bicgstab_batched_solve",
         "bicgstab_batched_tune", "bicgstab_batched_get_config", "bicgstab_batched_set_config",
-        "bicgstab_batched_variant_info", "bicgstab_batched_destroy",
+        "bicgstab_batched_variant_info", "bicgstab_batched_destroy", "bicgstab_axpby_tab1",
     ]

@@ -860,6 +860,15 @@ int bicgstab_destroy(bicgstab_t h) {
   return BICGSTAB_OK;
 }
 
+int bicgstab_axpby_tab1(int32_t run, int64_t n, double a, double b, double c, const double* d_x, double* d_y,
+                        double* d_z, void* stream) {
+  if (run < 1 || run > 3) return fail(BICGSTAB_EINVAL, "run must be 1, 2 or 3");
+  if (n < 0) return fail(BICGSTAB_EINVAL, "n must be >= 0");
+  if (n > 0 && (!d_x || !d_y || !d_z)) return fail(BICGSTAB_EINVAL, "null vector");
+  HIPCHK(launch_axpby(run, d_x, d_y, d_z, (long)n, a, b, c, (hipStream_t)stream));
+  return BICGSTAB_OK;
+}
+
 int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond, int32_t* reads, int32_t* writes,
                           int32_t* precond_apps, int32_t* spmms, int32_t* launches) {
   Plan P;

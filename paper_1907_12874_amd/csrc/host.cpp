@@ -426,6 +426,41 @@ int bicgstab_host_solve(bicgstab_host_t h, const double* b, double* x, double to
   return BICGSTAB_OK;
 }
 
+int bicgstab_host_axpby_tab1(int32_t run, int64_t n, double a, double b, double c, const double* x, double* y,
+                             double* z, int32_t threads) {
+  if (run < 1 || run > 3) return fail(BICGSTAB_EINVAL, "run must be 1, 2 or 3");
+  if (n < 0) return fail(BICGSTAB_EINVAL, "n must be >= 0");
+  if (n > 0 && (!x || !y || !z)) return fail(BICGSTAB_EINVAL, "null vector");
+  if (threads < 1 || threads > 1024) return fail(BICGSTAB_EINVAL, "threads must be in [1, 1024]");
+  const int T = threads;
+  auto pass = [&](auto body) {
+#pragma omp parallel num_threads(T)
+    {
+      const int nth = omp_get_num_threads(), tid = omp_get_thread_num();
+      for (int t = tid; t < T; t += nth)
+        for (int64_t i = range_begin(n, t, T); i < range_begin(n, t + 1, T); ++i) body(i);
+    }
+  };
+  if (run == 1) {
+    pass([&](int64_t i) { y[i] = a * x[i] + b * y[i]; });
+    pass([&](int64_t i) { z[i] = b * x[i] + a * z[i]; });
+    pass([&](int64_t i) { z[i] = b * y[i] + c * z[i]; });
+  } else if (run == 2) {
+    pass([&](int64_t i) {
+      y[i] = a * x[i] + b * y[i];
+      z[i] = b * x[i] + a * z[i];
+    });
+  } else {
+    pass([&](int64_t i) {
+      const double yi = a * x[i] + b * y[i];
+      const double zi = b * x[i] + a * z[i];
+      y[i] = yi;
+      z[i] = b * yi + c * zi;
+    });
+  }
+  return BICGSTAB_OK;
+}
+
 int bicgstab_host_loop_time(bicgstab_host_t h, double* seconds, int32_t* passes) {
   if (!h) return fail(BICGSTAB_EINVAL, "null handle");
   if (seconds) *seconds = h->loop_seconds;

@@ -61,6 +61,10 @@ hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
 hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,
                                float* diag32, int n, Globals* glob, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t s);
+// The three runs of Table 1's vector updates (1: three passes, 2: two updates
+// merged, 3: three updates merged).
+hipError_t launch_axpby(int run, const double* x, double* y, double* z, long n, double a, double b, double c,
+                        hipStream_t s);
 hipError_t launch_grad_values(const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
                               double* grad, int n, int k, hipStream_t s);
 hipError_t launch_transpose_count(const int32_t* col, int64_t nnz, int32_t* counts, hipStream_t s);

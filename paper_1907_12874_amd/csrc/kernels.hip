@@ -400,6 +400,58 @@ hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipSt
   return hipGetLastError();
 }
 
+// ------------------------------------------------- merging demonstration ---
+// The three groups of vector updates of Section 2.1 (Table 1): run 1 makes the
+// updates y = a x + b y, z = b x + a z, z = b y + c z as three passes, run 2
+// the first two in one pass, run 3 all three in one pass. Each thread takes
+// two adjacent elements per step (16-byte loads and stores) over a
+// grid-stride loop; STEP selects the single update of a run-1 pass (0, 1, 2)
+// or the merged run (3: run 2, 4: run 3).
+template <int STEP>
+__global__ __launch_bounds__(kBlock) void axpby_kernel(const double* __restrict__ x, double* __restrict__ y,
+                                                       double* __restrict__ z, long n, double a, double b,
+                                                       double c) {
+  const long stride = (long)gridDim.x * kBlock * 2;
+  for (long i = ((long)blockIdx.x * kBlock + threadIdx.x) * 2; i < n; i += stride) {
+    const int m = n - i >= 2 ? 2 : 1;
+    double xv[2], yv[2], zv[2];
+    for (int j = 0; j < m; ++j) {
+      xv[j] = STEP == 2 ? 0.0 : x[i + j];
+      yv[j] = STEP == 1 ? 0.0 : y[i + j];
+      zv[j] = STEP == 0 ? 0.0 : z[i + j];
+    }
+    for (int j = 0; j < m; ++j) {
+      if (STEP == 0 || STEP >= 3) yv[j] = a * xv[j] + b * yv[j];
+      if (STEP == 1 || STEP >= 3) zv[j] = b * xv[j] + a * zv[j];
+      if (STEP == 2 || STEP == 4) zv[j] = b * yv[j] + c * zv[j];
+    }
+    for (int j = 0; j < m; ++j) {
+      if (STEP == 0 || STEP >= 3) __builtin_nontemporal_store(yv[j], y + i + j);
+      if (STEP >= 1) __builtin_nontemporal_store(zv[j], z + i + j);
+    }
+  }
+}
+
+hipError_t launch_axpby(int run, const double* x, double* y, double* z, long n, double a, double b, double c,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long blocks = (n + 2 * kBlock - 1) / (2 * kBlock);
+  if (blocks > 2048) blocks = 2048;
+  const dim3 g((unsigned)blocks), t(kBlock);
+  if (run == 1) {
+    hipLaunchKernelGGL(axpby_kernel<0>, g, t, 0, s, x, y, z, n, a, b, c);
+    hipLaunchKernelGGL(axpby_kernel<1>, g, t, 0, s, x, y, z, n, a, b, c);
+    hipLaunchKernelGGL(axpby_kernel<2>, g, t, 0, s, x, y, z, n, a, b, c);
+  } else if (run == 2) {
+    hipLaunchKernelGGL(axpby_kernel<3>, g, t, 0, s, x, y, z, n, a, b, c);
+  } else if (run == 3) {
+    hipLaunchKernelGGL(axpby_kernel<4>, g, t, 0, s, x, y, z, n, a, b, c);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------- adjoint ---
 
 // grad[e] = - sum_c lam[i, c] * x[j, c] for every stored entry e = (i, j).

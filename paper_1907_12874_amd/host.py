@@ -43,6 +43,7 @@ def lib_host():
     L.bicgstab_host_solve.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
     L.bicgstab_host_loop_time.argtypes = [H, C.POINTER(dbl), C.POINTER(i32)]
     L.bicgstab_host_destroy.argtypes = [H]
+    L.bicgstab_host_axpby_tab1.argtypes = [i32, C.c_int64, dbl, dbl, dbl, vp, vp, vp, i32]
     L.bicgstab_host_last_error.argtypes = []
     L.bicgstab_host_last_error.restype = C.c_char_p
     _libh = L
@@ -52,6 +53,17 @@ def lib_host():
 def _check(code, where):
     if code != 0:
         raise BicgstabError(code, where, lib_host().bicgstab_host_last_error().decode())
+
+
+def axpby_tab1(run: int, x, y, z, a: float, b: float, c: float, threads: int = 1):
+    """Table 1's vector updates on host float64 arrays (y and z updated in
+    place): run 1 as three passes, run 2 the first two merged, run 3 all
+    three merged."""
+    for t, name in ((x, "x"), (y, "y"), (z, "z")):
+        if not (isinstance(t, np.ndarray) and t.dtype == np.float64 and t.flags.c_contiguous and t.size == x.size):
+            raise ValueError(f"{name} must be a contiguous float64 array of length {x.size}")
+    _check(lib_host().bicgstab_host_axpby_tab1(int(run), int(x.size), float(a), float(b), float(c), x.ctypes.data,
+                                               y.ctypes.data, z.ctypes.data, int(threads)), "bicgstab_host_axpby_tab1")
 
 
 class HostSolver:

@@ -221,3 +221,17 @@ def plan_traffic(variant: str, formulation: str, precond: str):
                                   *[C.byref(x) for x in v]), "bicgstab_plan_traffic")
     r, w, p, s, l = (x.value for x in v)
     return {"reads": r, "writes": w, "precond_apps": p, "spmms": s, "launches": l}
+
+
+def axpby_tab1(run: int, x, y, z, a: float, b: float, c: float):
+    """Table 1's vector updates on device tensors (float64, same length; y and
+    z updated in place): run 1 as three passes, run 2 the first two updates
+    merged, run 3 all three merged. Enqueued on torch's current stream."""
+    n = int(x.numel())
+    for t, name in ((x, "x"), (y, "y"), (z, "z")):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or int(t.numel()) != n:
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of length {n}")
+    with torch.cuda.device(x.device):
+        check(lib().bicgstab_axpby_tab1(int(run), n, float(a), float(b), float(c), C.c_void_p(x.data_ptr()),
+                                        C.c_void_p(y.data_ptr()), C.c_void_p(z.data_ptr()),
+                                        C.c_void_p(_stream_ptr(x.device))), "bicgstab_axpby_tab1")

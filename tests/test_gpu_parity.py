@@ -561,3 +561,33 @@ def test_full_size_cfg1_sampled(lib):
     rt = np.linalg.norm(b - S @ X, axis=0) / np.linalg.norm(b, axis=0)
     assert np.all(rt <= 1.1e-8) and np.allclose(rt, info.relres_true, rtol=1e-6)
     assert np.all(np.linalg.norm(X - xs, axis=0) / np.linalg.norm(xs, axis=0) < 1e-4)
+
+
+# ------------------------------------------------------------ Table 1 ---
+
+def test_table1_updates_gpu(lib):
+    """The three runs of Table 1 on the GPU against the updates in NumPy, bit
+    for bit: run 1 (three passes) and run 3 (one pass) give the same vectors,
+    run 2 the first two updates; odd lengths take the one-element tail."""
+    import torch
+
+    say("table 1 updates")
+    rng = np.random.default_rng(9)
+    for n in (1, 1001, 2**20 + 3):
+        x, y0, z0 = (rng.uniform(-1, 1, n) for _ in range(3))
+        a, b, c = 0.3, -1.7, 2.5
+        xt = torch.from_numpy(x).cuda()
+        for run in (1, 2, 3):
+            yt, zt = torch.from_numpy(y0).cuda(), torch.from_numpy(z0).cuda()
+            lib.axpby_tab1(run, xt, yt, zt, a, b, c)
+            torch.cuda.synchronize()
+            ry, rz = y0.copy(), z0.copy()
+            ry = a * x + b * ry
+            rz = b * x + a * rz
+            if run != 2:
+                rz = b * ry + c * rz
+            assert np.array_equal(to_np(yt), ry) and np.array_equal(to_np(zt), rz), (n, run)
+    e = torch.zeros(0, dtype=torch.float64, device="cuda")
+    lib.axpby_tab1(3, e, e.clone(), e.clone(), 1.0, 1.0, 1.0)
+    with pytest.raises(lib.BicgstabError):
+        lib.axpby_tab1(4, xt, xt.clone(), xt.clone(), 1.0, 1.0, 1.0)

@@ -143,3 +143,40 @@ def test_table4_fixture_is_consistent():
         for basic, merged, imp in cells:
             assert merged <= basic
             assert abs(imp - 100 * (1 - merged / basic)) <= 1.5, (name, basic, merged, imp)
+
+
+def _axpby_ref(x, y, z, a, b, c, run):
+    """Table 1's updates in NumPy, each product and sum rounded as written."""
+    y, z = y.copy(), z.copy()
+    y = a * x + b * y
+    z = b * x + a * z
+    if run != 2:
+        z = b * y + c * z
+    return y, z
+
+
+def test_table1_updates_host(host):
+    """The three runs of Table 1 on the host: run 1 (three passes) and run 3
+    (one merged pass) give the same vectors bit for bit, run 2 the first two
+    updates; ragged lengths and more ranges than elements."""
+    rng = np.random.default_rng(8)
+    for n, T in ((1001, 4), (7, 16), (0, 2)):
+        x, y0, z0 = (rng.uniform(-1, 1, n) for _ in range(3))
+        a, b, c = 0.3, -1.7, 2.5
+        for run in (1, 2, 3):
+            y, z = y0.copy(), z0.copy()
+            host.axpby_tab1(run, x, y, z, a, b, c, threads=T)
+            ry, rz = _axpby_ref(x, y0, z0, a, b, c, run)
+            assert np.array_equal(y, ry) and np.array_equal(z, rz), (n, T, run)
+
+
+def test_table1_fixture_is_consistent():
+    """The stored Table 1 figures: run 1 moves 9/5 of run 2's elements and
+    takes 1.7-1.8 times as long; runs 2 and 3 move the same elements and take
+    the same time within 1 ms although run 3 does 1.5x the flops."""
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))["table1_axpby"]
+    assert g["elements_moved_per_n"] == {"run1": 9, "run2": 5, "run3": 5}
+    for r1, r2, r3 in g["ms"].values():
+        assert 1.7 <= r1 / r2 <= 1.8 and abs(r2 - r3) <= 1
