@@ -403,40 +403,57 @@ hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipSt
 // ------------------------------------------------- merging demonstration ---
 // The three groups of vector updates of Section 2.1 (Table 1): run 1 makes the
 // updates y = a x + b y, z = b x + a z, z = b y + c z as three passes, run 2
-// the first two in one pass, run 3 all three in one pass. Each thread takes
-// two adjacent elements per step (16-byte loads and stores) over a
-// grid-stride loop; STEP selects the single update of a run-1 pass (0, 1, 2)
-// or the merged run (3: run 2, 4: run 3).
+// the first two in one pass, run 3 all three in one pass. The shape of the
+// streaming vector passes: a grid-stride loop with four elements per lane in
+// flight, 512 workgroups; STEP selects the single update of a run-1 pass
+// (0, 1, 2) or the merged run (3: run 2, 4: run 3).
+template <int STEP>
+__device__ __forceinline__ void axpby_elem(const double* __restrict__ x, double* __restrict__ y,
+                                           double* __restrict__ z, long i, double a, double b, double c) {
+  const double xv = STEP == 2 ? 0.0 : x[i];
+  double yv = STEP == 1 ? 0.0 : y[i];
+  double zv = STEP == 0 ? 0.0 : z[i];
+  if (STEP == 0 || STEP >= 3) yv = a * xv + b * yv;
+  if (STEP == 1 || STEP >= 3) zv = b * xv + a * zv;
+  if (STEP == 2 || STEP == 4) zv = b * yv + c * zv;
+  if (STEP == 0 || STEP >= 3) __builtin_nontemporal_store(yv, y + i);
+  if (STEP >= 1) __builtin_nontemporal_store(zv, z + i);
+}
+
 template <int STEP>
 __global__ __launch_bounds__(kBlock) void axpby_kernel(const double* __restrict__ x, double* __restrict__ y,
                                                        double* __restrict__ z, long n, double a, double b,
                                                        double c) {
-  const long stride = (long)gridDim.x * kBlock * 2;
-  for (long i = ((long)blockIdx.x * kBlock + threadIdx.x) * 2; i < n; i += stride) {
-    const int m = n - i >= 2 ? 2 : 1;
-    double xv[2], yv[2], zv[2];
-    for (int j = 0; j < m; ++j) {
-      xv[j] = STEP == 2 ? 0.0 : x[i + j];
-      yv[j] = STEP == 1 ? 0.0 : y[i + j];
-      zv[j] = STEP == 0 ? 0.0 : z[i + j];
+  constexpr int U = 4;
+  const long stride = (long)gridDim.x * kBlock;
+  long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    double xv[U], yv[U], zv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = i + u * stride;
+      xv[u] = STEP == 2 ? 0.0 : x[e];
+      yv[u] = STEP == 1 ? 0.0 : y[e];
+      zv[u] = STEP == 0 ? 0.0 : z[e];
     }
-    for (int j = 0; j < m; ++j) {
-      if (STEP == 0 || STEP >= 3) yv[j] = a * xv[j] + b * yv[j];
-      if (STEP == 1 || STEP >= 3) zv[j] = b * xv[j] + a * zv[j];
-      if (STEP == 2 || STEP == 4) zv[j] = b * yv[j] + c * zv[j];
-    }
-    for (int j = 0; j < m; ++j) {
-      if (STEP == 0 || STEP >= 3) __builtin_nontemporal_store(yv[j], y + i + j);
-      if (STEP >= 1) __builtin_nontemporal_store(zv[j], z + i + j);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = i + u * stride;
+      if (STEP == 0 || STEP >= 3) yv[u] = a * xv[u] + b * yv[u];
+      if (STEP == 1 || STEP >= 3) zv[u] = b * xv[u] + a * zv[u];
+      if (STEP == 2 || STEP == 4) zv[u] = b * yv[u] + c * zv[u];
+      if (STEP == 0 || STEP >= 3) __builtin_nontemporal_store(yv[u], y + e);
+      if (STEP >= 1) __builtin_nontemporal_store(zv[u], z + e);
     }
   }
+  for (; i < n; i += stride) axpby_elem<STEP>(x, y, z, i, a, b, c);
 }
 
 hipError_t launch_axpby(int run, const double* x, double* y, double* z, long n, double a, double b, double c,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  long blocks = (n + 2 * kBlock - 1) / (2 * kBlock);
-  if (blocks > 2048) blocks = 2048;
+  long blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 512) blocks = 512;
   const dim3 g((unsigned)blocks), t(kBlock);
   if (run == 1) {
     hipLaunchKernelGGL(axpby_kernel<0>, g, t, 0, s, x, y, z, n, a, b, c);
