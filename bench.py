@@ -587,6 +587,9 @@ def main():
                            "fixed_rhs_it_per_s": round(kk * args.sweep_passes / tt, 1),
                            "fixed_GBps": round(args.sweep_passes * ib / tt / 1e9, 1),
                            "fixed_ms_per_iter": round(tt / args.sweep_passes * 1e3, 4),
+                           # Tab. 5/6's model T = bytes / B with B the measured device copy
+                           "model_ms_per_iter": round(ib / (copy_gbps * 1e9) * 1e3, 4),
+                           "measured_over_model": round(tt / args.sweep_passes / (ib / (copy_gbps * 1e9)), 3),
                            "solve_ms": round(ts * 1e3, 2), "solve_iters_max": int(inf.iters.max()),
                            "solve_rhs_it_per_s": round(float(inf.iters.sum()) / ts, 1),
                            "equal_accuracy": bool(np.all(inf.status == 0) and np.all(inf.relres_true <= 1.1 * args.tol)),
