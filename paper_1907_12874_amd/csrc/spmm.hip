@@ -145,8 +145,8 @@ struct DotEpilogue {
 };
 
 // Y rows of row block L; every finished row (row, its CPL values) goes to epi.
-// KPL = log2(kp); lane c0 = (lane mod kp / CPL) * CPL holds columns c0 ..
-// c0 + CPL - 1 (all below k, or all at or above it: k is even when CPL = 2).
+// KPL = log2(kp); lane c0 = (lane mod (kp / CPL)) * CPL holds columns c0 ..
+// c0 + CPL - 1 (all below k, or all at or above it: CPL divides k).
 template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE, class Epi>
 __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict__ X, T* __restrict__ Y, int k, int L,
                                           Epi& epi) {
