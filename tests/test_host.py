@@ -180,3 +180,44 @@ def test_table1_fixture_is_consistent():
     assert g["elements_moved_per_n"] == {"run1": 9, "run2": 5, "run3": 5}
     for r1, r2, r3 in g["ms"].values():
         assert 1.7 <= r1 / r2 <= 1.8 and abs(r2 - r3) <= 1
+
+
+def _random_system(seed, n, k, density):
+    """A random nonsymmetric sparse matrix with a dominant diagonal (so every
+    method converges) and k right-hand sides."""
+    rng = np.random.default_rng(seed)
+    rows, vals = [], []
+    for i in range(n):
+        cols = np.unique(np.concatenate(([i], rng.choice(n, size=min(n, 1 + int(density * n)), replace=False))))
+        v = rng.uniform(-1, 1, cols.size)
+        v[cols == i] = 0.0
+        v[cols == i] = 1.5 * np.abs(v).sum() + 1.0
+        rows.append(cols)
+        vals.append(v)
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([c.size for c in rows])
+    A = CSR(n, rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals))
+    return A, rng.uniform(-1, 1, (n, k))
+
+
+def test_random_systems_property(host):
+    """Property: on random small systems, every method, form and
+    preconditioner, k in 1..6 and 1..9 row ranges, the host executor equals
+    the oracle run in the executor's summation order bit for bit (fixed
+    passes and converged solves)."""
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    @settings(max_examples=40, deadline=None, suppress_health_check=list(HealthCheck))
+    @given(seed=st.integers(0, 10**6), n=st.integers(1, 60), k=st.integers(1, 6), T=st.integers(1, 9),
+           method=st.sampled_from(METHODS), tol=st.sampled_from([0.0, 1e-9]), density=st.floats(0.0, 0.2))
+    def check(seed, n, k, T, method, tol, density):
+        A, b = _random_system(seed, n, k, density)
+        v, f, p = method
+        maxit = 12 if tol == 0.0 else 300
+        x, info = _solve(host, A, b, v, f, p, T, tol, maxit)
+        ref = _ref(A, b, v, f, p, T, tol, maxit)
+        assert np.array_equal(info.iters, ref.iters) and np.array_equal(info.status, ref.status)
+        assert np.array_equal(x, ref.x, equal_nan=True)
+
+    check()
