@@ -591,3 +591,46 @@ def test_table1_updates_gpu(lib):
     lib.axpby_tab1(3, e, e.clone(), e.clone(), 1.0, 1.0, 1.0)
     with pytest.raises(lib.BicgstabError):
         lib.axpby_tab1(4, xt, xt.clone(), xt.clone(), 1.0, 1.0, 1.0)
+
+
+# ------------------------------------------------------- property test ---
+
+def test_random_systems_property_gpu(lib):
+    """Property: on random nonsymmetric systems with a dominant diagonal
+    (n 1..3000, k 1..9, every method and form but the fused one, both
+    preconditioners, fixed passes or a converged solve), the GPU equals the
+    oracle run in the kernels' summation order bit for bit."""
+    import torch
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+
+    def system(seed, n, k):
+        rng = np.random.default_rng(seed)
+        rows, vals = [], []
+        for i in range(n):
+            cols = np.unique(np.concatenate(([i], rng.choice(n, size=min(n, 4), replace=False))))
+            v = rng.uniform(-1, 1, cols.size)
+            v[cols == i] = 0.0
+            v[cols == i] = 1.5 * np.abs(v).sum() + 1.0
+            rows.append(cols)
+            vals.append(v)
+        rp = np.zeros(n + 1, np.int32)
+        rp[1:] = np.cumsum([c.size for c in rows])
+        return CSR(n, rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals)), rng.uniform(-1, 1, (n, k))
+
+    @settings(max_examples=25, deadline=None, suppress_health_check=list(HealthCheck))
+    @given(seed=st.integers(0, 10**6), n=st.integers(1, 3000), k=st.integers(1, 9), method=st.sampled_from(BITWISE),
+           tol=st.sampled_from([0.0, 1e-9]))
+    def check(seed, n, k, method, tol):
+        v, f, p = method
+        A, b = system(seed, n, k)
+        maxit = 10 if tol == 0.0 else 400
+        say(f"property n={n} k={k} {v}/{f}/{p} tol={tol}")
+        s = gpu_solver(lib, A, k, v, f, p)
+        x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=maxit)
+        with oracle_dot(group_dot(A.n, k)):
+            ref = oracle.solve(A.to_scipy(), b, variant=v, formulation=f, precond=p, tol=tol, maxit=maxit)
+        assert np.array_equal(info.iters, ref.iters) and np.array_equal(info.status, ref.status)
+        assert np.array_equal(to_np(x), ref.x, equal_nan=True)
+
+    check()
