@@ -468,7 +468,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it would shard); "
+        print("bench.py measures one GPU: the library solves on one device and has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
