@@ -56,8 +56,9 @@ def spmm_bytes(n, nnz, k, elem=8):
 
 def iteration_bytes(n, nnz, k, traffic, elem=8):
     """Algorithmic bytes of one iteration: two products, the vector passes'
-    block reads and writes (Table 2 counting) and the Jacobi applications
-    (block in, block out, diagonal)."""
+    block reads and writes (Table 2 counting, with the product epilogues'
+    operands and scaled copies) and the Jacobi applications (block in, block
+    out, diagonal)."""
     blk = elem * n * k
     return (traffic["spmms"] * spmm_bytes(n, nnz, k, elem) + (traffic["reads"] + traffic["writes"]) * blk
             + traffic["precond_apps"] * (2 * blk + elem * n))
@@ -67,8 +68,12 @@ def step_bytes(step, n, nnz, k):
     blk = 8 * n * k
     if step["kind"] == "spmm":
         return spmm_bytes(n, nnz, k)
-    if step["kind"] == "spmm_dot":  # the product plus the epilogue's second operand
-        return spmm_bytes(n, nnz, k) + blk
+    if step["kind"] == "spmm_dot":
+        # the product, plus the epilogue's second operand (dots) and / or its
+        # Jacobi-scaled copy with the diagonal (E_PREC, E_DOT_W_PREC)
+        epi = step["op"]
+        extra = (blk if epi in (0, 1, 3) else 0) + (blk + 8 * n if epi in (2, 3) else 0)
+        return spmm_bytes(n, nnz, k) + extra
     if step["kind"] == "prec":
         return 2 * blk + 8 * n
     return (step["nin"] + step["nout"]) * blk
@@ -78,7 +83,7 @@ def kernel_name(step):
     if step["kind"] == "spmm":
         return "spmm_kernel"
     if step["kind"] == "spmm_dot":
-        return "spmm_dot_kernel<" + ("dot_w", "ppt")[step["op"]] + ">"
+        return "spmm_dot_kernel<" + ("dot_w", "ppt", "prec", "dot_w_prec")[step["op"]] + ">"
     if step["kind"] == "prec":
         return "prec_kernel"
     return "group_kernel<" + OP_NAMES[step["op"]] + ">"
@@ -566,7 +571,7 @@ def main():
             xk = torch.empty_like(bk)
             variants = ("classical", "reordered", "pipelined") + (("improved",) if args.precond == "none" else ())
             for variant in variants:
-                for form in ("merged", "basic", "fused") if variant == "classical" else ("merged", "basic"):
+                for form in ("merged", "basic", "fused") if variant in ("classical", "reordered") else ("merged", "basic"):
                     sv = pk.Solver.from_csr(A, kk, variant=variant, formulation=form, precond=args.precond, device=dev)
                     tr = pk.plan_traffic(variant, form, args.precond)
                     ib = iteration_bytes(n, nnz, kk, tr)

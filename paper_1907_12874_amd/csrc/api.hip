@@ -281,9 +281,13 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* 
       const SpmmMat Mt = mat_of(h, M.blk == h->blk ? 1 : 0, fp32);
       return launch_spmm(Mt, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
     }
-    case K_SPMM_DOT:
-      return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], vp[st.in[1]], st.op, h->k, fp32, ctl, st.slot, st.fin,
-                             M.bpart, s);
+    case K_SPMM_DOT: {
+      const void* w = epilogue_dots(st.op) > 0 ? vp[st.in[1]] : nullptr;
+      void* yh = epilogue_prec(st.op) ? vp[st.out[1]] : nullptr;
+      const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
+      return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], w, yh, diag, st.op, h->k, fp32, ctl, st.slot, st.fin,
+                             M.bpart, g, s);
+    }
     case K_PREC:
       return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
                          (int)h->n, h->k, fp32, g, s);
@@ -609,8 +613,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) return fail(BICGSTAB_EINVAL, "nnz must fit int32");
   if (precision != BICGSTAB_FP64 && precision != BICGSTAB_FP32_REFINE)
     return fail(BICGSTAB_EINVAL, "unknown precision");
-  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL)
-    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical method only");
+  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL && variant != BICGSTAB_REORDERED)
+    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical and Reordered methods only");
   if (variant == BICGSTAB_IMPROVED && precond != BICGSTAB_PRECOND_NONE)
     return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
   if (variant == BICGSTAB_IMPROVED && precision != BICGSTAB_FP64)
@@ -885,8 +889,15 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
       ++pa;
     } else if (s.kind == K_SPMM_DOT) {
       ++sp;
-      r += 1;         // the epilogue's second operand (the product's own traffic is counted apart)
-      ++fin_kernels;  // its finalize kernel
+      // the epilogue's second operand and scaled copy (the product's own
+      // traffic is counted apart); the partial-sum and finalize kernels
+      if (epilogue_dots(s.op) > 0) {
+        r += 1;
+        fin_kernels += 2;
+      } else if (s.fin != F_NONE) {
+        fin_kernels += 1;
+      }
+      if (epilogue_prec(s.op)) w += 1;
     } else {
       ++sp;
     }

@@ -113,10 +113,12 @@ void spmm(const Ctx& h, const std::vector<int32_t>& rp, const std::vector<int32_
   });
 }
 
-// The product with a dot epilogue: (y, w), or (y, w), (y, y), (w, w).
-void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, int epi, int slot, int fin) {
+// The product with an epilogue: the dots (y, w), or (y, w), (y, y), (w, w),
+// and / or the Jacobi-scaled copy yh = y / a_ii.
+void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, int epi, int slot, int fin) {
   const int k = h.k;
-  const int nd = epi == E_DOT_W ? 1 : 3;
+  const int nd = epilogue_dots(epi);
+  const bool scaled = epilogue_prec(epi);
   for_ranges(h, [&](int t, int64_t r0, int64_t r1) {
     double acc[kMaxK];
     double* part = &h.red[(size_t)t * 7 * k];
@@ -129,18 +131,22 @@ void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, int epi, int 
         for (int c = 0; c < k; ++c) acc[c] += a * xr[c];
       }
       double* yr = Y + (size_t)i * k;
-      const double* wr = W + (size_t)i * k;
-      for (int c = 0; c < k; ++c) {
-        yr[c] = acc[c];
-        part[c] += acc[c] * wr[c];
-        if (nd == 3) {
-          part[k + c] += acc[c] * acc[c];
-          part[2 * k + c] += wr[c] * wr[c];
+      for (int c = 0; c < k; ++c) yr[c] = acc[c];
+      if (scaled)
+        for (int c = 0; c < k; ++c) Yh[(size_t)i * k + c] = acc[c] / h.diag[i];
+      if (nd > 0) {
+        const double* wr = W + (size_t)i * k;
+        for (int c = 0; c < k; ++c) {
+          part[c] += acc[c] * wr[c];
+          if (nd == 3) {
+            part[k + c] += acc[c] * acc[c];
+            part[2 * k + c] += wr[c] * wr[c];
+          }
         }
       }
     }
   });
-  finish_dots(h, nd, slot, fin);
+  if (nd > 0 || fin != F_NONE) finish_dots(h, nd, slot, fin);
 }
 
 void prec(const Ctx& h, const double* in, double* out) {
@@ -252,7 +258,10 @@ int run_step(Ctx& h, const Step& st, double* const* vp, bool early_exit = true) 
   switch (st.kind) {
     case K_SPMM: spmm(h, h.rp, h.col, h.val, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
     case K_SPMM_T: spmm(h, h.rpt, h.colt, h.valt, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
-    case K_SPMM_DOT: spmm_dot(h, vp[st.in[0]], vp[st.out[0]], vp[st.in[1]], st.op, st.slot, st.fin); return BICGSTAB_OK;
+    case K_SPMM_DOT:
+      spmm_dot(h, vp[st.in[0]], vp[st.out[0]], epilogue_dots(st.op) > 0 ? vp[st.in[1]] : nullptr,
+               epilogue_prec(st.op) ? vp[st.out[1]] : nullptr, st.op, st.slot, st.fin);
+      return BICGSTAB_OK;
     case K_PREC: prec(h, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
     case K_GROUP: return run_group(h, st, vp);
   }
@@ -292,8 +301,8 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
   if (threads < 1 || threads > 1024) return fail(BICGSTAB_EINVAL, "threads must be in [1, 1024]");
   if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values))))
     return fail(BICGSTAB_EINVAL, "null matrix array");
-  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL)
-    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical method only");
+  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL && variant != BICGSTAB_REORDERED)
+    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical and Reordered methods only");
   if (variant == BICGSTAB_IMPROVED && precond != BICGSTAB_PRECOND_NONE)
     return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
   std::unique_ptr<Ctx> h(new Ctx);
@@ -315,7 +324,7 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
   h->val.assign(A->values, A->values + A->nnz);
   for (int32_t c : h->col)
     if (c < 0 || c >= n) return fail(BICGSTAB_EINVAL, "column index out of range");
-  if (precond == BICGSTAB_PRECOND_JACOBI || formulation == BICGSTAB_FUSED) {
+  if (precond == BICGSTAB_PRECOND_JACOBI) {
     h->diag.assign(n, 0.0);
     int64_t zero = 0;
     for (int64_t i = 0; i < n; ++i) {

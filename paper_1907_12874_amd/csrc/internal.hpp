@@ -34,12 +34,15 @@ struct SpmmPartition {
 
 hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp32, const Globals* glob,
                        hipStream_t s);
-// Sparse product with a dot epilogue (SpmmEpilogue epi, second operand W):
-// one workgroup per row block stores its partial sums in bpart (nblk x 3k
-// doubles at most), a second kernel sums runs of blocks into ctl.partials, and
-// the finalize kernel sums the runs and runs step `fin` on dot slots slot.. .
-hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k, bool fp32,
-                           const Ctl& ctl, int slot, int fin, double* bpart, hipStream_t s);
+// Sparse product with an epilogue (SpmmEpilogue epi): dot products against W
+// (one workgroup per row block stores its partial sums in bpart, nblk x 3k
+// doubles at most, a second kernel sums runs of blocks into ctl.partials, and
+// the finalize kernel sums the runs and runs step `fin` on dot slots slot..)
+// and/or the Jacobi-scaled copy Yh = Y / diag. glob: early exit when no
+// column runs.
+hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, void* Yh, const void* diag,
+                           int epi, int k, bool fp32, const Ctl& ctl, int slot, int fin, double* bpart,
+                           const Globals* glob, hipStream_t s);
 // Runs of row blocks the epilogue partials are first summed over (<= 256).
 int spmm_dot_runs(int nblk);
 // The one-workgroup finalize kernel after a reduction pass of nb workgroups

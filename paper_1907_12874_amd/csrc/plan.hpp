@@ -144,15 +144,22 @@ enum VecId {
   V_NUM
 };
 
-// K_SPMM_DOT: a sparse product whose epilogue also forms dot products of the
-// rows it writes (op = SpmmEpilogue, in[1] = the second operand).
+// K_SPMM_DOT: a sparse product with an epilogue on the rows it writes
+// (op = SpmmEpilogue): dot products against a second operand (in[1]) and/or
+// the Jacobi-scaled copy y / a_ii (out[1]).
 // K_SPMM_T: the product with the transposed matrix (Alg. 3's f0 = A^T r0).
 enum StepKind { K_SPMM = 0, K_PREC, K_GROUP, K_SPMM_DOT, K_SPMM_T };
 
 enum SpmmEpilogue {
-  E_DOT_W = 0,  // y = A x; dot (y, w)
-  E_PPT,        // y = A x; dots (y, w), (y, y), (w, w)
+  E_DOT_W = 0,   // y = A x; dot (y, w)
+  E_PPT,         // y = A x; dots (y, w), (y, y), (w, w)
+  E_PREC,        // y = A x; yh = y / a_ii
+  E_DOT_W_PREC,  // y = A x; yh = y / a_ii; dot (y, w)
+  E_NUM
 };
+// Dot products and scaled-copy output of an epilogue.
+constexpr int epilogue_dots(int epi) { return epi == E_PPT ? 3 : (epi == E_DOT_W || epi == E_DOT_W_PREC) ? 1 : 0; }
+constexpr bool epilogue_prec(int epi) { return epi == E_PREC || epi == E_DOT_W_PREC; }
 
 struct Step {
   StepKind kind;

@@ -93,6 +93,15 @@ Step SPMM_DOT(int x, int y, int epi, int w, int slot, int fin) {
   return s;
 }
 
+// Sparse product y = A x that also writes yh = y / a_ii, with the dot
+// (y, w) in its epilogue when w is given.
+Step SPMM_PREC(int x, int y, int yh, int w = V_NONE, int slot = 0, int fin = F_NONE) {
+  Step s = w == V_NONE ? G(OP_COPY, {x}, {y, yh}, slot, fin) : G(OP_COPY, {x, w}, {y, yh}, slot, fin);
+  s.kind = K_SPMM_DOT;
+  s.op = w == V_NONE ? E_PREC : E_DOT_W_PREC;
+  return s;
+}
+
 // y = A^T x (the transposed matrix).
 Step SPMM_T(int in, int out) {
   Step s = G(OP_COPY, {in}, {out});
@@ -190,6 +199,27 @@ void classical(int formulation, int precond, Plan* P) {
 }
 
 // ------------------------------------------------------------- reordered ---
+// Fused form of Alg. 6 (one device, beyond the paper's grouping): delta =
+// (v, r0) is formed in the epilogue of v = A vh, and with Jacobi the two
+// preconditioner applications s = v / a_ii and q = t / a_ii are written by
+// the products that make v and t, so no pass reads v or t back for them.
+void reordered_fused(int precond, Plan* P) {
+  const bool jac = precond == 1;
+  auto& it = P->iter;
+  if (jac)
+    it.push_back(SPMM_PREC(V_VH, V_V, V_S, V_R0, 0, F_ALPHA));  // v = A vh, s = v / a_ii, delta
+  else
+    it.push_back(SPMM_DOT(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
+  it.push_back(G(OP_SUB_ALPHA, {V_Z, V_S}, {V_TH}));             // t-hat = z - alpha s
+  if (jac)
+    it.push_back(SPMM_PREC(V_TH, V_T, V_Q));                    // t = A th, q = t / a_ii
+  else
+    it.push_back(SPMM(V_TH, V_T));
+  it.push_back(G(OP_R_G3, {V_R, V_V, V_T, V_R0}, {V_RT}, 0, F_RE_OMEGA));
+  it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));             // r = rt - omega t
+  it.push_back(G(OP_R_XZV, {V_X, V_VH, V_TH, V_Q, V_S}, {V_X, V_Z, V_VH}, 0, F_END));
+}
+
 void reordered(int formulation, int precond, Plan* P) {
   const bool jac = precond == 1;
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
@@ -199,6 +229,9 @@ void reordered(int formulation, int precond, Plan* P) {
     P->init.push_back(G(OP_COPY, {V_R}, {V_Z}));
   P->init.push_back(G(OP_COPY, {V_Z}, {V_VH}));  // v-hat_0 = z_0
   auto& it = P->iter;
+  if (formulation == 2) {
+    reordered_fused(precond, P);
+  } else {
   it.push_back(SPMM(V_VH, V_V));
   it.push_back(G(OP_DOT, {V_V, V_R0}, {}, 0, F_ALPHA));  // delta
   if (jac) it.push_back(PREC(V_V, V_S));                 // s = M^{-1} v (alias of v when M = I)
@@ -221,6 +254,7 @@ void reordered(int formulation, int precond, Plan* P) {
     it.push_back(G(OP_SUB_OMEGA, {V_TH, V_Q}, {V_Z}));   // z = th - omega q
     Step s = G(OP_PUPD, {V_Z, V_VH, V_S}, {V_VH}, 0, F_END);  // vh = z + beta (vh - omega s)
     it.push_back(s);
+  }
   }
   P->vecs = {V_R, V_R0, V_V, V_T, V_Z, V_TH, V_RT, V_VH};
   if (jac) {
@@ -378,8 +412,8 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
     *err = "unknown formulation";
     return false;
   }
-  if (formulation == 2 && variant != 0) {
-    *err = "the fused formulation is built for the classical method only";
+  if (formulation == 2 && variant != 0 && variant != 1) {
+    *err = "the fused formulation is built for the classical and Reordered methods only";
     return false;
   }
   if (variant == 3 && precond != 0) {
@@ -414,8 +448,10 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
           return false;
         }
       } else if (s.kind == K_SPMM_DOT) {
-        if (s.nin != 2 || s.nout != 1 || (s.op != E_DOT_W && s.op != E_PPT) || s.slot + (s.op == E_PPT ? 3 : 1) > 7) {
-          *err = "plan step: product with dot epilogue needs x, w, y and a known epilogue";
+        const bool known = s.op >= 0 && s.op < E_NUM;
+        if (!known || s.nin != 1 + (epilogue_dots(s.op) > 0 ? 1 : 0) || s.nout != 1 + (epilogue_prec(s.op) ? 1 : 0) ||
+            s.slot + epilogue_dots(s.op) > 7) {
+          *err = "plan step: product with an epilogue needs x, y, the epilogue's operands and a known epilogue";
           return false;
         }
       } else if (s.nin != 1 || s.nout != 1) {

@@ -116,29 +116,43 @@ struct NoEpilogue {
 
 // Dots of the written rows against W (E_DOT_W: (y, w); E_PPT: (y, w), (y, y),
 // (w, w)), per lane in the order the lane writes its rows.
-// acc[d * CPL + h]: dot d of column c + h.
+// The product's epilogue on each finished row: the dots of the row against
+// W (E_DOT_W: (y, w); E_PPT: (y, w), (y, y), (w, w)), acc[d * CPL + h]
+// holding dot d of column c + h, and / or the Jacobi-scaled copy
+// Yh = y / a_ii (E_PREC, E_DOT_W_PREC).
 template <class T, int EPI, int CPL>
 struct DotEpilogue {
   const T* W;
+  T* Yh;
+  const T* diag;
   int k, c;
   double acc[3 * CPL];
   __device__ __forceinline__ void operator()(int row, const T (&y)[CPL]) {
-    T w[CPL];
-    if constexpr (CPL == 1) {
-      w[0] = W[(size_t)row * k + c];
-    } else {
-      const typename VecOf<T, CPL>::type t = *(const typename VecOf<T, CPL>::type*)(W + (size_t)row * k + c);
+    if constexpr (epilogue_prec(EPI)) {
+      const T d = diag[row];
+      T yh[CPL];
 #pragma unroll
-      for (int h = 0; h < CPL; ++h) w[h] = t[h];
+      for (int h = 0; h < CPL; ++h) yh[h] = y[h] / d;
+      store_y<T, CPL>(Yh, row, k, c, yh);
     }
+    if constexpr (epilogue_dots(EPI) > 0) {
+      T w[CPL];
+      if constexpr (CPL == 1) {
+        w[0] = W[(size_t)row * k + c];
+      } else {
+        const typename VecOf<T, CPL>::type t = *(const typename VecOf<T, CPL>::type*)(W + (size_t)row * k + c);
 #pragma unroll
-    for (int h = 0; h < CPL; ++h) {
-      const double yv = (double)y[h];
-      const double wv = (double)w[h];
-      acc[h] += yv * wv;
-      if (EPI == E_PPT) {
-        acc[CPL + h] += yv * yv;
-        acc[2 * CPL + h] += wv * wv;
+        for (int h = 0; h < CPL; ++h) w[h] = t[h];
+      }
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) {
+        const double yv = (double)y[h];
+        const double wv = (double)w[h];
+        acc[h] += yv * wv;
+        if (EPI == E_PPT) {
+          acc[CPL + h] += yv * yv;
+          acc[2 * CPL + h] += wv * wv;
+        }
       }
     }
   }
@@ -341,21 +355,22 @@ __global__ __launch_bounds__(BS) void spmm_kernel(SpmmMat A, const T* __restrict
   row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, block_of(blockIdx.x, A.nblk, A.xcd_chunk), none);
 }
 
-// The product with a dot epilogue: one workgroup per row block, as the plain
-// product; the block's ND x k partial sums go to bpart[L * P + d * k + c]
-// (block-major, P = ND * k).
+// The product with an epilogue: one workgroup per row block, as the plain
+// product; the block's ND x k partial sums (if the epilogue forms dots) go to
+// bpart[L * P + d * k + c] (block-major, P = ND * k).
 template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE, int EPI>
 __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __restrict__ X, T* __restrict__ Y,
-                                                      const T* __restrict__ W, int k, double* __restrict__ bpart,
+                                                      const T* __restrict__ W, T* __restrict__ Yh,
+                                                      const T* __restrict__ diag, int k, double* __restrict__ bpart,
                                                       const Globals* glob) {
-  if (glob->nrun == 0) return;
-  constexpr int ND = EPI == E_DOT_W ? 1 : 3;
+  if (glob && glob->nrun == 0) return;
+  constexpr int ND = epilogue_dots(EPI);
   constexpr int LPL = KPL - (CPL == 4 ? 2 : CPL == 2 ? 1 : 0);
   const int L = block_of(blockIdx.x, A.nblk, A.xcd_chunk);
-  DotEpilogue<T, EPI, CPL> epi{W, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
+  DotEpilogue<T, EPI, CPL> epi{W, Yh, diag, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
   row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
   // lanes past k returned from the row loop with their sums still zero
-  store_block_partials_strided<ND, BS, CPL>(epi.acc, bpart + (size_t)L * ND * k, k, LPL, 1);
+  if constexpr (ND > 0) store_block_partials_strided<ND, BS, CPL>(epi.acc, bpart + (size_t)L * ND * k, k, LPL, 1);
 }
 
 // Sums the block-major partials of nb row blocks over G runs of consecutive
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __rest
 // order; the finalize kernel then sums the G runs of each pair in run order.
 __global__ __launch_bounds__(256) void reduce_runs_kernel(const double* __restrict__ bpart, int nb, int P,
                                                           double* __restrict__ out, int G, const Globals* glob) {
-  if (glob->nrun == 0) return;
+  if (glob && glob->nrun == 0) return;
   const int g = blockIdx.x;
   const int b0 = (int)((long)nb * g / G), b1 = (int)((long)nb * (g + 1) / G);
   for (int p = threadIdx.x; p < P; p += blockDim.x) {
@@ -400,7 +415,7 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
 }
 
 template <class T, int CPL, int BS, bool OFF32, int STYLE, int EPI>
-hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k, double* bpart,
+hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, T* yh, const T* diag, int k, double* bpart,
                            const Globals* glob, hipStream_t s) {
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
@@ -411,7 +426,7 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, int k
 #define SPMM_DOT_CASE(KP, KPL)                                                                                    \
   case KP:                                                                                                        \
     hipLaunchKernelGGL((spmm_dot_kernel<T, KPL, (KP >= CPL ? CPL : 1), BS, OFF32, STYLE, EPI>), dim3(grid), dim3(BS), \
-                       lds, s, A, x, y, w, k, bpart, glob);                                                       \
+                       lds, s, A, x, y, w, yh, diag, k, bpart, glob);                                             \
     break;
     SPMM_DOT_CASE(1, 0)
     SPMM_DOT_CASE(2, 1)
@@ -457,31 +472,40 @@ hipError_t spmm_dispatch(const SpmmMat& A, const void* X, void* Y, int k, const 
   }
 }
 
+template <class T, int CPL, int EPI>
+hipError_t spmm_epi_launch(const SpmmMat& A, const T* x, T* y, const T* w, T* yh, const T* diag, int k,
+                           double* bpart, const Globals* glob, hipStream_t s) {
+  return off32(A, k, sizeof(T)) ? spmm_dot_launch<T, CPL, kSpmmBlock, true, 1, EPI>(A, x, y, w, yh, diag, k, bpart, glob, s)
+                                : spmm_dot_launch<T, CPL, kSpmmBlock, false, 1, EPI>(A, x, y, w, yh, diag, k, bpart, glob,
+                                                                                    s);
+}
+
 template <class T, int CPL>
-hipError_t spmm_dot_dispatch_cpl(const SpmmMat& A, const T* x, T* y, const T* w, int epi, int k, double* bpart,
-                                 const Globals* glob, hipStream_t s) {
-  const bool o32 = off32(A, k, sizeof(T));
-  if (epi == E_DOT_W)
-    return o32 ? spmm_dot_launch<T, CPL, kSpmmBlock, true, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s)
-               : spmm_dot_launch<T, CPL, kSpmmBlock, false, 1, E_DOT_W>(A, x, y, w, k, bpart, glob, s);
-  if (epi == E_PPT)
-    return o32 ? spmm_dot_launch<T, CPL, kSpmmBlock, true, 1, E_PPT>(A, x, y, w, k, bpart, glob, s)
-               : spmm_dot_launch<T, CPL, kSpmmBlock, false, 1, E_PPT>(A, x, y, w, k, bpart, glob, s);
-  return hipErrorInvalidValue;
+hipError_t spmm_dot_dispatch_cpl(const SpmmMat& A, const T* x, T* y, const T* w, T* yh, const T* diag, int epi, int k,
+                                 double* bpart, const Globals* glob, hipStream_t s) {
+  switch (epi) {
+    case E_DOT_W: return spmm_epi_launch<T, CPL, E_DOT_W>(A, x, y, w, yh, diag, k, bpart, glob, s);
+    case E_PPT: return spmm_epi_launch<T, CPL, E_PPT>(A, x, y, w, yh, diag, k, bpart, glob, s);
+    case E_PREC: return spmm_epi_launch<T, CPL, E_PREC>(A, x, y, w, yh, diag, k, bpart, glob, s);
+    case E_DOT_W_PREC: return spmm_epi_launch<T, CPL, E_DOT_W_PREC>(A, x, y, w, yh, diag, k, bpart, glob, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class T>
-hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k,
-                             double* bpart, const Globals* glob, hipStream_t s) {
+hipError_t spmm_dot_dispatch(const SpmmMat& A, const void* X, void* Y, const void* W, void* Yh, const void* Diag,
+                             int epi, int k, double* bpart, const Globals* glob, hipStream_t s) {
   const T* x = static_cast<const T*>(X);
   T* y = static_cast<T*>(Y);
   const T* w = static_cast<const T*>(W);
-  switch (lane_cols<T>(k, {X, Y, W})) {
+  T* yh = static_cast<T*>(Yh);
+  const T* diag = static_cast<const T*>(Diag);
+  switch (lane_cols<T>(k, {X, Y, W, Yh})) {
     case 4:
-      if constexpr (sizeof(T) == 4) return spmm_dot_dispatch_cpl<T, 4>(A, x, y, w, epi, k, bpart, glob, s);
+      if constexpr (sizeof(T) == 4) return spmm_dot_dispatch_cpl<T, 4>(A, x, y, w, yh, diag, epi, k, bpart, glob, s);
       return hipErrorInvalidValue;
-    case 2: return spmm_dot_dispatch_cpl<T, 2>(A, x, y, w, epi, k, bpart, glob, s);
-    default: return spmm_dot_dispatch_cpl<T, 1>(A, x, y, w, epi, k, bpart, glob, s);
+    case 2: return spmm_dot_dispatch_cpl<T, 2>(A, x, y, w, yh, diag, epi, k, bpart, glob, s);
+    default: return spmm_dot_dispatch_cpl<T, 1>(A, x, y, w, yh, diag, epi, k, bpart, glob, s);
   }
 }
 
@@ -523,21 +547,26 @@ hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp3
 
 int spmm_dot_runs(int nblk) { return std::max(1, std::min(nblk, 256)); }
 
-hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, int epi, int k, bool fp32,
-                           const Ctl& ctl, int slot, int fin, double* bpart, hipStream_t s) {
-  const int nd = epi == E_DOT_W ? 1 : 3;
-  const int P = nd * k;
+hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, void* Yh, const void* diag,
+                           int epi, int k, bool fp32, const Ctl& ctl, int slot, int fin, double* bpart,
+                           const Globals* glob, hipStream_t s) {
+  if (epi < 0 || epi >= E_NUM || (epilogue_dots(epi) > 0 && !W) || (epilogue_prec(epi) && (!Yh || !diag)))
+    return hipErrorInvalidValue;
+  const int P = epilogue_dots(epi) * k;
   const int G = spmm_dot_runs(A.nblk);
   if (A.nblk > 0) {
-    hipError_t e = fp32 ? spmm_dot_dispatch<float>(A, X, Y, W, epi, k, bpart, ctl.glob, s)
-                        : spmm_dot_dispatch<double>(A, X, Y, W, epi, k, bpart, ctl.glob, s);
+    hipError_t e = fp32 ? spmm_dot_dispatch<float>(A, X, Y, W, Yh, diag, epi, k, bpart, glob, s)
+                        : spmm_dot_dispatch<double>(A, X, Y, W, Yh, diag, epi, k, bpart, glob, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_runs_kernel, dim3(G), dim3(256), 0, s, bpart, A.nblk, P, ctl.partials, G, ctl.glob);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (P > 0) {
+      hipLaunchKernelGGL(reduce_runs_kernel, dim3(G), dim3(256), 0, s, bpart, A.nblk, P, ctl.partials, G, glob);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
+  if (P == 0 && fin == F_NONE) return hipSuccess;
   // with no rows the partials are not written: the finalize then sums nothing
-  return launch_finalize(ctl, A.nblk > 0 ? P : 0, G, slot, fin, true, s);
+  return launch_finalize(ctl, A.nblk > 0 ? P : 0, G, slot, fin, glob != nullptr, s);
 }
 
 }  // namespace bcg

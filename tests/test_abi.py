@@ -120,16 +120,29 @@ def test_fused_plan_traffic(L):
     block each, the Jacobi division rides on the passes that produce p and s,
     and the solution update joins {r, rho'}: 12 reads / 4 writes without a
     preconditioner (merged: 14 / 4) and 13 / 6 with Jacobi and no separate
-    preconditioner pass (merged: 15 / 4 plus two passes of 1 / 1)."""
+    preconditioner pass (merged: 15 / 4 plus two passes of 1 / 1). Fused
+    Reordered form below."""
     from paper_1907_12874_amd import plan_traffic
 
     a = plan_traffic("classical", "fused", "none")
     b = plan_traffic("classical", "fused", "jacobi")
-    assert (a["reads"], a["writes"], a["spmms"], a["precond_apps"], a["launches"]) == (12, 4, 2, 0, 8)
-    assert (b["reads"], b["writes"], b["spmms"], b["precond_apps"], b["launches"]) == (13, 6, 2, 0, 8)
+    # launches: five passes, the two products' partial-sum and finalize kernels, one more finalize
+    assert (a["reads"], a["writes"], a["spmms"], a["precond_apps"], a["launches"]) == (12, 4, 2, 0, 10)
+    assert (b["reads"], b["writes"], b["spmms"], b["precond_apps"], b["launches"]) == (13, 6, 2, 0, 10)
     m = plan_traffic("classical", "merged", "jacobi")
     assert b["reads"] + b["writes"] < m["reads"] + m["writes"] + 2 * m["precond_apps"]
     assert b["launches"] < m["launches"]
+    # fused Alg. 6: delta in the first product's epilogue (14 / 6 against the
+    # merged 15 / 6); with Jacobi the products also write s = v / a_ii and
+    # q = t / a_ii (14 / 8 and no preconditioner pass, against 15 / 6 plus two
+    # passes of 1 / 1)
+    c = plan_traffic("reordered", "fused", "none")
+    d = plan_traffic("reordered", "fused", "jacobi")
+    assert (c["reads"], c["writes"], c["spmms"], c["precond_apps"]) == (14, 6, 2, 0)
+    assert (d["reads"], d["writes"], d["spmms"], d["precond_apps"]) == (14, 8, 2, 0)
+    mr = plan_traffic("reordered", "merged", "jacobi")
+    assert d["reads"] + d["writes"] == mr["reads"] + mr["writes"] + 2 * mr["precond_apps"] - 3
+    assert d["launches"] < mr["launches"]
     from paper_1907_12874_amd import _lib
 
     r = ctypes.c_int32()
@@ -139,7 +152,7 @@ def test_fused_plan_traffic(L):
     for formulation, precond, precision in ((0, 1, 0), (2, 0, 0), (0, 0, 1)):
         assert L.bicgstab_create(ctypes.byref(desc), 4, 1, 3, formulation, precond, precision, None,
                                  ctypes.byref(h)) == _lib.EUNSUPPORTED
-    for variant in (1, 2):  # not built for the Reordered and Pipelined methods
+    for variant in (2,):  # not built for the Pipelined method
         assert L.bicgstab_plan_traffic(variant, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
         desc = _lib.CSRDesc(4, 0, None, None, None)
         h = ctypes.c_void_p()

@@ -38,8 +38,8 @@ from workloads import conv_diff, config_problem, manufactured_rhs, random_sparse
 pytestmark = pytest.mark.gpu
 
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
-# the fused form exists for the classical method; its oracle is the merged listing
-METHODS += [("classical", "fused", p) for p in ("none", "jacobi")]
+# the fused form exists for the classical and Reordered methods; its oracle is the merged listing
+METHODS += [(v, "fused", p) for v in ("classical", "reordered") for p in ("none", "jacobi")]
 # Improved BiCGStab (Alg. 3) has no preconditioned form
 METHODS += [("improved", f, "none") for f in ("merged", "basic")]
 
@@ -490,19 +490,24 @@ def test_bitwise_converged(lib, variant, formulation, precond):
         assert np.array_equal(to_np(x), ref.x)
 
 
-def fused_dot(A, k):
-    """The fused classical form's dot sequence: (r, r), (b, b) from the start
-    pass, then per pass delta from the first product's epilogue, phi, psi,
-    theta from the second's, and rho' from the vector pass."""
+def fused_dot(A, k, variant="classical"):
+    """A fused form's dot sequence: (r, r), (b, b) from the start pass, then
+    per pass: classical, delta from the first product's epilogue, phi, psi,
+    theta from the second's and rho' from a vector pass; Reordered, delta from
+    the first product's epilogue and theta, phi, psi, eta from a vector
+    pass."""
     g = group_dot(A.n, k)
     e = spmm_epilogue_dot(A.row_ptr, k)
+    if variant == "reordered":
+        return scheduled_dot([g, g], [e, g, g, g, g])
     return scheduled_dot([g, g], [e, e, e, e, g])
 
 
+@pytest.mark.parametrize("variant", ["classical", "reordered"])
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("k", [5, 6])
-def test_bitwise_fused(lib, precond, k):
-    """The fused classical form, 20 fixed passes and a converged solve, per
+def test_bitwise_fused(lib, variant, precond, k):
+    """The fused forms, 20 fixed passes and a converged solve, per
     column (each column's oracle run gets its own dot schedule): iterates,
     pass counts and statuses equal the oracle's in the kernels' order. Odd k
     runs the product one column per lane, even k two (k = 6: a padded lane
@@ -513,13 +518,13 @@ def test_bitwise_fused(lib, precond, k):
     b, _ = manufactured_rhs(A, k, seed=22)
     S = A.to_scipy()
     for tol, maxit in ((0.0, 20), (1e-10, 3000)):
-        say(f"bitwise fused {precond} k={k} tol={tol}")
-        s = gpu_solver(lib, A, k, "classical", "fused", precond)
+        say(f"bitwise fused {variant} {precond} k={k} tol={tol}")
+        s = gpu_solver(lib, A, k, variant, "fused", precond)
         x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=maxit)
         X = to_np(x)
         for c in range(k):
-            with oracle_dot(fused_dot(A, k)):
-                ref = oracle.solve_column(S, b[:, c], None, "classical", "fused", precond, tol, maxit)
+            with oracle_dot(fused_dot(A, k, variant)):
+                ref = oracle.solve_column(S, b[:, c], None, variant, "fused", precond, tol, maxit)
             assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), (c, info.iters[c], ref.iters)
             assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
 
@@ -544,13 +549,14 @@ def test_full_size_cfg1_sampled(lib):
     Y = to_np(s.spmm(bt))
     rows = np.random.default_rng(0).choice(A.n, 2000, replace=False)
     assert np.array_equal(Y[rows], S[rows] @ b)
-    for v, f in (("classical", "merged"), ("reordered", "merged"), ("pipelined", "merged"), ("classical", "fused")):
+    for v, f in (("classical", "merged"), ("reordered", "merged"), ("pipelined", "merged"), ("classical", "fused"),
+                 ("reordered", "fused")):
         say(f"  3 passes {v} {f} (bitwise)")
         s3 = gpu_solver(lib, A, 32, v, f, "jacobi")
         x, info = s3.solve(bt, tol=0.0, maxit=3)
         X = to_np(x)
         for c in (0, 31):
-            with oracle_dot(fused_dot(A, 32) if f == "fused" else group_dot(A.n, 32)):
+            with oracle_dot(fused_dot(A, 32, v) if f == "fused" else group_dot(A.n, 32)):
                 ref = oracle.solve_column(S, b[:, c], None, v, f, "jacobi", 0.0, 3)
             assert np.array_equal(X[:, c], ref.x), (v, f, c)
         del s3
@@ -633,7 +639,7 @@ def test_random_systems_property_gpu(lib):
             # each column's oracle run gets the fused plan's dot schedule
             S = A.to_scipy()
             for c in range(k):
-                with oracle_dot(fused_dot(A, k)):
+                with oracle_dot(fused_dot(A, k, v)):
                     ref = oracle.solve_column(S, b[:, c], None, v, f, p, tol, maxit)
                 assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), c
                 assert np.array_equal(X[:, c], ref.x, equal_nan=True), c

@@ -25,7 +25,7 @@ def say(*a):
 
 @pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
                                                          ("pipelined", "none", "merged"), ("reordered", "jacobi", "merged"),
-                                                         ("classical", "jacobi", "fused")])
+                                                         ("classical", "jacobi", "fused"), ("reordered", "jacobi", "fused")])
 def test_precision_tier_matches_refinement_oracle(lib, variant, precond, formulation):
     """27-point random matrix (the precision-tier recipe at 20^3), k = 8,
     tol 1e-10: every column converges in FP64 terms, the number of FP64
@@ -110,7 +110,8 @@ def test_grad_values_kernel(lib):
 
 
 @pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
-                                                         ("classical", "jacobi", "fused"), ("improved", "none", "merged")])
+                                                         ("classical", "jacobi", "fused"), ("improved", "none", "merged"),
+                                                         ("reordered", "jacobi", "fused")])
 def test_transpose_solve(lib, variant, precond, formulation):
     """A^T Lambda = G by the same method on the device-built transposed CSR
     (nonsymmetric matrix, so A vs A^T matters)."""

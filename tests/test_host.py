@@ -19,7 +19,8 @@ from workloads import CSR, conv_diff, manufactured_rhs, random_sparse  # noqa: E
 
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic")
            for p in ("none", "jacobi")] + [("improved", "merged", "none"), ("improved", "basic", "none"),
-                                            ("classical", "fused", "none"), ("classical", "fused", "jacobi")]
+                                            ("classical", "fused", "none"), ("classical", "fused", "jacobi"),
+                                            ("reordered", "fused", "none"), ("reordered", "fused", "jacobi")]
 
 
 @pytest.fixture(scope="module")
@@ -103,6 +104,9 @@ def test_errors(host):
     assert e.value.code == EUNSUPPORTED
     with pytest.raises(BicgstabError) as e:
         host.HostSolver.from_csr(A, 2, variant="pipelined", formulation="fused")
+    assert e.value.code == EUNSUPPORTED
+    with pytest.raises(BicgstabError) as e:
+        host.HostSolver.from_csr(A, 2, variant="improved", formulation="fused")
     assert e.value.code == EUNSUPPORTED
     bad = CSR(A.n, A.row_ptr, A.col_idx.copy(), A.values)
     bad.col_idx[3] = A.n
