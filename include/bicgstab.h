@@ -62,9 +62,11 @@ enum {
  * FP64 only; other combinations return BICGSTAB_EUNSUPPORTED. */
 enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2, BICGSTAB_IMPROVED = 3 };
 /* Formulations: merged = Table 2 "Merged" grouping, basic = Table 2 "Basic";
- * fused = the merged grouping with the further fusions only a single device
- * allows (the Jacobi scaling folded into the products and updates, adjacent
- * passes of one scalar phase joined). */
+ * fused = the merged statements with the further fusions only a single device
+ * allows: dot products formed in the sparse products' epilogues, the Jacobi
+ * scaling written by the pass or product that makes its input, adjacent
+ * passes of one scalar phase joined. Built for the classical and Reordered
+ * methods; fused Pipelined or Improved returns BICGSTAB_EUNSUPPORTED. */
 enum { BICGSTAB_MERGED = 0, BICGSTAB_BASIC = 1, BICGSTAB_FUSED = 2 };
 /* Preconditioners: none, or Jacobi M = diag(A) applied as u / a_ii. */
 enum { BICGSTAB_PRECOND_NONE = 0, BICGSTAB_PRECOND_JACOBI = 1 };
