@@ -613,8 +613,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) return fail(BICGSTAB_EINVAL, "nnz must fit int32");
   if (precision != BICGSTAB_FP64 && precision != BICGSTAB_FP32_REFINE)
     return fail(BICGSTAB_EINVAL, "unknown precision");
-  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL && variant != BICGSTAB_REORDERED)
-    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical and Reordered methods only");
+  if (formulation == BICGSTAB_FUSED && variant == BICGSTAB_IMPROVED)
+    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is not built for Improved BiCGStab");
   if (variant == BICGSTAB_IMPROVED && precond != BICGSTAB_PRECOND_NONE)
     return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
   if (variant == BICGSTAB_IMPROVED && precision != BICGSTAB_FP64)

@@ -248,6 +248,8 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_IB_Z, KIbZ)
     G(OP_IB_V, KIbV)
     G(OP_IB_X, KIbX)
+    G(OP_F_PP_G2H, KPPG2H)
+    G(OP_F_PP_G4H, KPPG4H)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }
@@ -301,8 +303,8 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
   if (threads < 1 || threads > 1024) return fail(BICGSTAB_EINVAL, "threads must be in [1, 1024]");
   if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values))))
     return fail(BICGSTAB_EINVAL, "null matrix array");
-  if (formulation == BICGSTAB_FUSED && variant != BICGSTAB_CLASSICAL && variant != BICGSTAB_REORDERED)
-    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is built for the classical and Reordered methods only");
+  if (formulation == BICGSTAB_FUSED && variant == BICGSTAB_IMPROVED)
+    return fail(BICGSTAB_EUNSUPPORTED, "the fused formulation is not built for Improved BiCGStab");
   if (variant == BICGSTAB_IMPROVED && precond != BICGSTAB_PRECOND_NONE)
     return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
   std::unique_ptr<Ctx> h(new Ctx);

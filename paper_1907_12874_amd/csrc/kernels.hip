@@ -264,6 +264,8 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_IB_Z: return launch_op<KIbZ, T>(a, grid_cap, s);
     case OP_IB_V: return launch_op<KIbV, T>(a, grid_cap, s);
     case OP_IB_X: return launch_op<KIbX, T>(a, grid_cap, s);
+    case OP_F_PP_G2H: return launch_op<KPPG2H, T>(a, grid_cap, s);
+    case OP_F_PP_G4H: return launch_op<KPPG4H, T>(a, grid_cap, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -240,6 +240,38 @@ struct KPPG4 {  // in: q, y, t, v, r0, z, s ; out: r, w ; (r0,r), (r0,z), (r0,w)
     a[3] += v[4] * v[6];
   }
 };
+// Fused Alg. 7: the passes that make z and w also write their Jacobi copies.
+struct KPPG2H {  // in: w, s, z, t, v, r (+ a_ii) ; out: s, z, q, y, zh ; (q, y), (y, y), (q, q)
+  OP_HEAD_D(6, 5, 3, 0, 0, PART_RUN, true)
+  OP_F {
+    double s = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
+    double z = R(v[3] + c.beta * (v[2] - c.omega * v[4]));
+    double q = R(v[5] - c.alpha * s);
+    double y = R(v[0] - c.alpha * z);
+    o[0] = s;
+    o[1] = z;
+    o[2] = q;
+    o[3] = y;
+    o[4] = z / v[6];
+    a[0] += q * y;
+    a[1] += y * y;
+    a[2] += q * q;
+  }
+};
+struct KPPG4H {  // in: q, y, t, v, r0, z, s (+ a_ii) ; out: r, w, wh ; (r0,r), (r0,z), (r0,w), (r0,s)
+  OP_HEAD_D(7, 3, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    double r = R(v[0] - c.omega * v[1]);
+    double w = R(v[1] - c.omega * (v[2] - c.alpha * v[3]));
+    o[0] = r;
+    o[1] = w;
+    o[2] = w / v[7];
+    a[0] += v[4] * r;
+    a[1] += v[4] * v[5];
+    a[2] += v[4] * w;
+    a[3] += v[4] * v[6];
+  }
+};
 // Refinement passes (outer loop of the FP32 tier). Inputs/outputs marked in
 // XIN/XOUT are FP64; the rest are the inner (FP32) Krylov type.
 struct KRefResid {  // in: b, z (FP64) ; out: r (FP64) ; (r, r), (b, b)

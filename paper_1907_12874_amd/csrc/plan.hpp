@@ -132,6 +132,8 @@ enum OpId {
   OP_IB_Z,           // Alg. 3 basic: z = alpha r + c1 z - c2 v
   OP_IB_V,           // Alg. 3 basic: v = u + beta v - delta q
   OP_IB_X,           // Alg. 3 basic: x = x + z + omega s
+  OP_F_PP_G2H,       // fused Jacobi, Alg. 7: OP_PP_G2 that also writes zh = z / a_ii
+  OP_F_PP_G4H,       // fused Jacobi, Alg. 7: OP_PP_G4 that also writes wh = w / a_ii
   OP_NUM
 };
 

@@ -57,6 +57,8 @@ const OpInfo kOps[OP_NUM] = {
     {3, 1, 0, "ib_z"},           // OP_IB_Z
     {3, 1, 0, "ib_v"},           // OP_IB_V
     {3, 1, 0, "ib_x"},           // OP_IB_X
+    {6, 5, 3, "f_pp_g2h"},       // OP_F_PP_G2H
+    {7, 3, 4, "f_pp_g4h"},       // OP_F_PP_G4H
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -290,7 +292,8 @@ void pipelined(int formulation, int precond, Plan* P) {
 
   auto& it = P->iter;
   if (!jac) {
-    if (formulation == 0) {
+    // without a preconditioner there is nothing to fold: fused = merged
+    if (formulation == 0 || formulation == 2) {
       it.push_back(G(OP_P_G1, {V_R, V_P, V_S, V_W, V_Z, V_T, V_V}, {V_P, V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
       it.push_back(SPMM(V_Z, V_V));
       it.push_back(G(OP_P_G2, {V_X, V_P, V_Q, V_Y}, {V_X, V_R}));
@@ -326,6 +329,14 @@ void pipelined(int formulation, int precond, Plan* P) {
       it.push_back(G(OP_PP_G3, {V_X, V_PH, V_QH, V_WH, V_ZH}, {V_X, V_RH}));
       it.push_back(G(OP_PP_G4, {V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_R, V_W}, 3, F_PIPE_BETA_END));
       it.push_back(PREC(V_W, V_WH));
+      it.push_back(SPMM(V_WH, V_T));
+    } else if (formulation == 2) {
+      // fused (one device): the passes that make z and w also write zh and wh
+      it.push_back(G(OP_PP_G1, {V_RH, V_PH, V_SH, V_WH, V_ZH}, {V_PH, V_SH, V_QH}));
+      it.push_back(G(OP_F_PP_G2H, {V_W, V_S, V_Z, V_T, V_V, V_R}, {V_S, V_Z, V_Q, V_Y, V_ZH}, 0, F_PIPE_OMEGA));
+      it.push_back(SPMM(V_ZH, V_V));
+      it.push_back(G(OP_PP_G3, {V_X, V_PH, V_QH, V_WH, V_ZH}, {V_X, V_RH}));
+      it.push_back(G(OP_F_PP_G4H, {V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_R, V_W, V_WH}, 3, F_PIPE_BETA_END));
       it.push_back(SPMM(V_WH, V_T));
     } else {
       it.push_back(G(OP_PUPD, {V_RH, V_PH, V_SH}, {V_PH}));  // ph = rh + beta (ph - omega sh)
@@ -412,8 +423,8 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
     *err = "unknown formulation";
     return false;
   }
-  if (formulation == 2 && variant != 0 && variant != 1) {
-    *err = "the fused formulation is built for the classical and Reordered methods only";
+  if (formulation == 2 && variant == 3) {
+    *err = "the fused formulation is not built for Improved BiCGStab";
     return false;
   }
   if (variant == 3 && precond != 0) {

@@ -152,11 +152,16 @@ def test_fused_plan_traffic(L):
     for formulation, precond, precision in ((0, 1, 0), (2, 0, 0), (0, 0, 1)):
         assert L.bicgstab_create(ctypes.byref(desc), 4, 1, 3, formulation, precond, precision, None,
                                  ctypes.byref(h)) == _lib.EUNSUPPORTED
-    for variant in (2,):  # not built for the Pipelined method
-        assert L.bicgstab_plan_traffic(variant, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
-        desc = _lib.CSRDesc(4, 0, None, None, None)
-        h = ctypes.c_void_p()
-        assert L.bicgstab_create(ctypes.byref(desc), 4, 1, variant, 2, 0, 0, None, ctypes.byref(h)) == _lib.EUNSUPPORTED
+    assert L.bicgstab_plan_traffic(3, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
+    # fused Alg. 7 with Jacobi: the passes that make z and w also write zh and
+    # wh (23 / 13, no preconditioner pass, against 23 / 11 plus two passes of
+    # 1 / 1); without a preconditioner nothing is folded (fused = merged)
+    e = plan_traffic("pipelined", "fused", "jacobi")
+    mp = plan_traffic("pipelined", "merged", "jacobi")
+    assert (e["reads"], e["writes"], e["spmms"], e["precond_apps"]) == (23, 13, 2, 0)
+    assert (mp["reads"], mp["writes"], mp["precond_apps"]) == (23, 11, 2)
+    assert e["launches"] == mp["launches"] - 2
+    assert plan_traffic("pipelined", "fused", "none") == plan_traffic("pipelined", "merged", "none")
 
 
 def test_invalid_arguments_are_errors(L):

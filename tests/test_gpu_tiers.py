@@ -25,7 +25,8 @@ def say(*a):
 
 @pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
                                                          ("pipelined", "none", "merged"), ("reordered", "jacobi", "merged"),
-                                                         ("classical", "jacobi", "fused"), ("reordered", "jacobi", "fused")])
+                                                         ("classical", "jacobi", "fused"), ("reordered", "jacobi", "fused"),
+                                                         ("pipelined", "jacobi", "fused")])
 def test_precision_tier_matches_refinement_oracle(lib, variant, precond, formulation):
     """27-point random matrix (the precision-tier recipe at 20^3), k = 8,
     tol 1e-10: every column converges in FP64 terms, the number of FP64

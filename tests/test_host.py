@@ -20,7 +20,8 @@ from workloads import CSR, conv_diff, manufactured_rhs, random_sparse  # noqa: E
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic")
            for p in ("none", "jacobi")] + [("improved", "merged", "none"), ("improved", "basic", "none"),
                                             ("classical", "fused", "none"), ("classical", "fused", "jacobi"),
-                                            ("reordered", "fused", "none"), ("reordered", "fused", "jacobi")]
+                                            ("reordered", "fused", "none"), ("reordered", "fused", "jacobi"),
+                                            ("pipelined", "fused", "none"), ("pipelined", "fused", "jacobi")]
 
 
 @pytest.fixture(scope="module")
@@ -101,9 +102,6 @@ def test_errors(host):
     A = conv_diff(5, 2, (1.0, 0.5))
     with pytest.raises(BicgstabError) as e:
         host.HostSolver.from_csr(A, 2, variant="improved", precond="jacobi")
-    assert e.value.code == EUNSUPPORTED
-    with pytest.raises(BicgstabError) as e:
-        host.HostSolver.from_csr(A, 2, variant="pipelined", formulation="fused")
     assert e.value.code == EUNSUPPORTED
     with pytest.raises(BicgstabError) as e:
         host.HostSolver.from_csr(A, 2, variant="improved", formulation="fused")
