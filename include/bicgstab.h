@@ -65,8 +65,9 @@ enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2, B
  * fused = the merged statements with the further fusions only a single device
  * allows: dot products formed in the sparse products' epilogues, the Jacobi
  * scaling written by the pass or product that makes its input, adjacent
- * passes of one scalar phase joined. Built for the classical and Reordered
- * methods; fused Pipelined or Improved returns BICGSTAB_EUNSUPPORTED. */
+ * passes of one scalar phase joined. Built for the classical, Reordered and
+ * Pipelined methods (Pipelined without a preconditioner: the merged plan);
+ * fused Improved returns BICGSTAB_EUNSUPPORTED. */
 enum { BICGSTAB_MERGED = 0, BICGSTAB_BASIC = 1, BICGSTAB_FUSED = 2 };
 /* Preconditioners: none, or Jacobi M = diag(A) applied as u / a_ii. */
 enum { BICGSTAB_PRECOND_NONE = 0, BICGSTAB_PRECOND_JACOBI = 1 };
