@@ -19,6 +19,9 @@ The JSON line also carries:
   sweep         merged vs basic for every method at k = 1..32: fixed-pass
                 throughput (RHS-iterations/s, algorithmic GB/s) and solves to
                 the same tolerance (equal accuracy, checked per column);
+  random_sparse the same per k = 1, 8, 32 on a random sparse matrix of the
+                same size (15 random columns per row), with the sparse
+                product's rate against compulsory and gathered bytes;
   tiers         precision (27-point random 100^3, k = 32: FP64 vs FP32 inner
                 solves + FP64 refinement at equal final accuracy), batched (64
                 systems of log-uniform size in one persistent launch, tuned,
@@ -302,6 +305,68 @@ def tier_autograd(pk, dev, maxit):
             "backward_over_forward": round((tb - tf) / tf, 3), "grad_finite": bool(torch.isfinite(g).all())}
 
 
+def random_sparse_section(pk, dev, copy_gbps, ks=(1, 8, 32), passes=20, tol=1e-8, maxit=2000):
+    """BiCGStab on a random sparse matrix as large as the stencil (n = 2^21,
+    diagonal plus 15 distinct uniformly random columns per row, 1.05x
+    dominant diagonal): per k, classical merged and basic with Jacobi at
+    fixed passes (RHS-iterations/s, algorithmic GB/s and its fraction of the
+    HBM peak), a merged solve to `tol`, and the sparse product's rate both
+    against its compulsory bytes and against the bytes its gathers touch
+    when no X row is reused (nnz x 8k: an entry's column is a random row)."""
+    import torch
+
+    from workloads import manufactured_rhs, random_sparse
+
+    A = random_sparse(2**21, 15, seed=0)
+    n, nnz = A.n, A.nnz
+    b_all, _ = manufactured_rhs(A, max(ks), seed=0)
+    rows = []
+    for kk in ks:
+        b = torch.from_numpy(np.ascontiguousarray(b_all[:, :kk])).to(dev)
+        x0 = torch.zeros_like(b)
+        x = torch.empty_like(b)
+        row = {"k": kk}
+        for form in ("merged", "basic"):
+            sv = pk.Solver.from_csr(A, kk, variant="classical", formulation=form, precond="jacobi", device=dev)
+            ib = iteration_bytes(n, nnz, kk, pk.plan_traffic("classical", form, "jacobi"))
+            sv.solve(b, x0, tol=0.0, maxit=2, out=x)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sv.solve(b, x0, tol=0.0, maxit=passes, out=x)
+            torch.cuda.synchronize()
+            tt = (time.perf_counter() - ta) / passes
+            row[form] = {"ms_per_iter": round(tt * 1e3, 4), "rhs_it_per_s": round(kk / tt, 1),
+                         "algorithmic_GBps": round(ib / tt / 1e9, 1),
+                         "frac_of_peak": round(ib / tt / 1e9 / PEAK_HBM_GBPS, 4)}
+            if form == "merged":
+                _, kernels, _ = roofline_of(sv, b, n, nnz, kk)
+                sp = kernels["spmm_kernel"]
+                row["spmm"] = {"avg_ms": round(sp["avg_ms"], 4), "GBps": round(sp["GBps"], 1),
+                               "frac_of_peak": round(sp["GBps"] / PEAK_HBM_GBPS, 4),
+                               "gathered_GBps_no_reuse": round(
+                                   (12.0 * nnz + 4.0 * (n + 1) + 8.0 * nnz * kk + 8.0 * n * kk)
+                                   / (sp["avg_ms"] * 1e-3) / 1e9, 1)}
+                ta = time.perf_counter()
+                _, inf = sv.solve(b, x0, tol=tol, maxit=maxit, out=x)
+                torch.cuda.synchronize()
+                ts = time.perf_counter() - ta
+                row["solve"] = {"ms": round(ts * 1e3, 2), "iters_max": int(inf.iters.max()),
+                                "rhs_it_per_s": round(float(inf.iters.sum()) / ts, 1),
+                                "all_converged": bool(np.all(inf.status == 0)),
+                                "relres_true_max": float(inf.relres_true.max())}
+            sv.close()
+            del sv
+        row["merging_time_reduction"] = round(1 - row["merged"]["ms_per_iter"] / row["basic"]["ms_per_iter"], 4)
+        rows.append(row)
+        print(f"# random sparse k={kk:2d}: merged {row['merged']['ms_per_iter']:.3f} ms/it "
+              f"{row['merged']['algorithmic_GBps']:.0f} GB/s, basic {row['basic']['ms_per_iter']:.3f} ms/it, "
+              f"spmm {row['spmm']['avg_ms']:.3f} ms, solve {row['solve']['iters_max']} it",
+              file=sys.stderr, flush=True)
+    return {"workload": f"random sparse n={n}, nnz={nnz} (diagonal + 15 random columns per row), Jacobi, "
+                        f"classical BiCGStab, tol {tol:g}",
+            "passes": passes, "copy_ceiling_GBps": copy_gbps, "rows": rows}
+
+
 TAB4_METHODS = {  # Table 4 rows -> (variant, preconditioner)
     "BiCGStab": ("classical", "none"),
     "IBiCGStab": ("improved", "none"),
@@ -461,6 +526,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-tiers", action="store_true")
+    ap.add_argument("--no-random", action="store_true", help="skip the random sparse matrix section")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
     ap.add_argument("--host-grid", type=int, default=160)
@@ -617,6 +683,10 @@ def main():
                     fusion[f"{variant}_k{kk}"] = round(1 - mb["fused"]["fixed_ms_per_iter"] / mb["merged"]["fixed_ms_per_iter"], 4)
         out["merging_time_reduction"] = gains
         out["fusion_time_reduction_vs_merged"] = fusion
+
+    # ------------------------------------------------------ random sparse
+    if not args.no_random:
+        out["random_sparse"] = random_sparse_section(pk, dev, copy_gbps, tol=args.tol)
 
     # -------------------------------------------------------------- tiers
     if not args.no_tiers:

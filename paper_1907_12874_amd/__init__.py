@@ -1,5 +1,6 @@
-"""MI355X multi-right-hand-side BiCGStab (classical, Reordered, Pipelined;
-basic and merged), a HIP library for gfx950 behind a C ABI.
+"""MI355X multi-right-hand-side BiCGStab (classical, Reordered, Pipelined,
+Improved; basic, merged and fused forms), a HIP library for gfx950 behind a
+C ABI.
 
 The compute path is the in-tree libbicgstab.so; there is no CPU fallback.
 """

@@ -571,6 +571,38 @@ def test_full_size_cfg1_sampled(lib):
     assert np.all(np.linalg.norm(X - xs, axis=0) / np.linalg.norm(xs, axis=0) < 1e-4)
 
 
+def test_full_size_random_sparse_sampled(lib):
+    """The random sparse matrix of the benchmark (n = 2^21, 15 random columns
+    per row) at k = 32: SpMM rows sampled against the oracle's product, three
+    classical merged Jacobi passes bit for bit against the oracle on columns
+    0 and 31, and a converged solve checked by its recomputed residual."""
+    import torch
+
+    say("full size random sparse 2^21 k=32")
+    A = random_sparse(2**21, 15, seed=0)
+    b, xs = manufactured_rhs(A, 32, seed=0)
+    S = A.to_scipy()
+    bt = torch.from_numpy(b).cuda()
+    s = gpu_solver(lib, A, 32, "classical", "merged", "jacobi")
+    Y = to_np(s.spmm(bt))
+    rows = np.random.default_rng(1).choice(A.n, 2000, replace=False)
+    assert np.array_equal(Y[rows], S[rows] @ b)
+    say("  3 passes (bitwise)")
+    x, _ = s.solve(bt, tol=0.0, maxit=3)
+    X = to_np(x)
+    for c in (0, 31):
+        with oracle_dot(group_dot(A.n, 32)):
+            ref = oracle.solve_column(S, b[:, c], None, "classical", "merged", "jacobi", 0.0, 3)
+        assert np.array_equal(X[:, c], ref.x), c
+    say("  converged solve")
+    x, info = s.solve(bt, tol=1e-8, maxit=500)
+    X = to_np(x)
+    assert np.all(info.status == 0)
+    rt = np.linalg.norm(b - S @ X, axis=0) / np.linalg.norm(b, axis=0)
+    assert np.all(rt <= 1.1e-8) and np.allclose(rt, info.relres_true, rtol=1e-6)
+    assert np.all(np.linalg.norm(X - xs, axis=0) / np.linalg.norm(xs, axis=0) < 1e-5)
+
+
 # ------------------------------------------------------------ Table 1 ---
 
 def test_table1_updates_gpu(lib):
