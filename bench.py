@@ -683,6 +683,14 @@ def main():
                     fusion[f"{variant}_k{kk}"] = round(1 - mb["fused"]["fixed_ms_per_iter"] / mb["merged"]["fixed_ms_per_iter"], 4)
         out["merging_time_reduction"] = gains
         out["fusion_time_reduction_vs_merged"] = fusion
+        # the paper's own merging gains (Tab. 4, its CPU node) beside ours
+        with open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")) as f:
+            tab4 = json.load(f)["table4_merging_effect"]
+        tab4_names = {"jacobi": {"classical": "PBiCGStab", "reordered": "RBiCGStab", "pipelined": "PPipeBiCGStab"},
+                      "none": {"classical": "BiCGStab", "pipelined": "PipeBiCGStab", "improved": "IBiCGStab"}}
+        out["merging_time_reduction_paper"] = {
+            "source": tab4["citation"], "m": tab4["m"],
+            **{v: [r[2] / 100.0 for r in tab4["rows"][nm]] for v, nm in tab4_names.get(args.precond, {}).items()}}
 
     # ------------------------------------------------------ random sparse
     if not args.no_random:
