@@ -19,9 +19,13 @@ The JSON line also carries:
   sweep         merged vs basic for every method at k = 1..32: fixed-pass
                 throughput (RHS-iterations/s, algorithmic GB/s) and solves to
                 the same tolerance (equal accuracy, checked per column);
-  random_sparse the same per k = 1, 8, 32 on a random sparse matrix of the
-                same size (15 random columns per row), with the sparse
-                product's rate against compulsory and gathered bytes;
+  gpu_tab4      Table 4 on the GPU with the paper's matrix (200^3 Poisson,
+                m = 1, 4, 16): per-iteration times, basic vs merged, of the
+                six methods beside the paper's times and gains;
+  random_sparse fixed-pass throughput and a solve per k = 1, 8, 32 on a
+                random sparse matrix as large as the stencil (15 random
+                columns per row), with the sparse product's rate against
+                compulsory and gathered bytes;
   tiers         precision (27-point random 100^3, k = 32: FP64 vs FP32 inner
                 solves + FP64 refinement at equal final accuracy), batched (64
                 systems of log-uniform size in one persistent launch, tuned,
@@ -437,6 +441,71 @@ def host_tab4(pk, grid, reps, threads, run_s=0.25):
             "threads": threads, "reps": reps, "seconds": round(time.perf_counter() - t_all, 1), "rows": rows}
 
 
+def gpu_tab4(pk, dev, grid=200, passes=10, reps=3):
+    """Table 4 on the GPU with the paper's own matrix (7-point Poisson, 200^3)
+    and m = 1, 4, 16: per-iteration time of each method, basic and merged,
+    as (t(2 + passes) - t(2)) / passes of fixed-pass solves (stop test off;
+    start-up passes and exit cancel), each t the best of `reps`, beside the
+    paper's per-iteration times on its CPU node and its merging gains."""
+    import torch
+
+    from workloads import conv_diff
+
+    A = conv_diff(grid, 3, (0.0, 0.0, 0.0))
+    n, nnz = A.n, A.nnz
+    with open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")) as f:
+        paper = json.load(f)["table4_merging_effect"]
+    rng = np.random.default_rng(0)
+    rows = []
+    t_all = time.perf_counter()
+    for m in (1, 4, 16):
+        b = torch.from_numpy(rng.uniform(-1, 1, (n, m))).to(dev)
+        x0 = torch.zeros_like(b)
+        x = torch.empty_like(b)
+        for name, (variant, precond) in TAB4_METHODS.items():
+            r = {"method": name, "m": m}
+            for form in ("basic", "merged"):
+                sv = pk.Solver.from_csr(A, m, variant=variant, formulation=form, precond=precond, device=dev)
+                # the first solve of a handle also prepares it (graph capture,
+                # Alg. 3's transposed matrix): warm up, then the best time of
+                # each pass count over `reps`
+                sv.solve(b, x0, tol=0.0, maxit=2, out=x)
+                tt = {2: float("inf"), 2 + passes: float("inf")}
+                for _ in range(reps):
+                    for p in tt:
+                        torch.cuda.synchronize()
+                        ta = time.perf_counter()
+                        sv.solve(b, x0, tol=0.0, maxit=p, out=x)
+                        torch.cuda.synchronize()
+                        tt[p] = min(tt[p], time.perf_counter() - ta)
+                best = (tt[2 + passes] - tt[2]) / passes
+                sv.close()
+                del sv
+                ib = iteration_bytes(n, nnz, m, pk.plan_traffic(variant, form, precond))
+                r[f"{form}_ms"] = round(best * 1e3, 4)
+                r[f"{form}_GBps"] = round(ib / best / 1e9, 1)
+                r[f"{form}_bytes"] = ib
+            r["improvement"] = round(1 - r["merged_ms"] / r["basic_ms"], 4)
+            r["model_improvement"] = round(1 - r["merged_bytes"] / r["basic_bytes"], 4)
+            mi = paper["m"].index(m)
+            p_basic, p_merged, p_imp = paper["rows"][name][mi]
+            r["paper_basic_ms"] = p_basic * 1e3
+            r["paper_merged_ms"] = p_merged * 1e3
+            r["paper_improvement"] = p_imp / 100.0
+            r["merged_speedup_vs_paper"] = round(p_merged / best, 1)
+            rows.append(r)
+            print(f"# gpu tab4 m={m:2d} {name:14s}: basic {r['basic_ms']:7.3f} ms merged {r['merged_ms']:7.3f} ms "
+                  f"imp {r['improvement']:6.1%} (model {r['model_improvement']:5.1%}, paper "
+                  f"{r['paper_improvement']:4.0%}), {r['merged_GBps']:.0f} GB/s, "
+                  f"{r['merged_speedup_vs_paper']}x the paper's node", file=sys.stderr, flush=True)
+        del b, x0, x
+    return {"workload": f"7-point Poisson {grid}^3 (n={n}, nnz={nnz}), m = 1, 4, 16, {passes} fixed passes; the "
+                        f"preconditioned rows use Jacobi (a uniform scaling here: constant diagonal) where the "
+                        f"paper used the identity",
+            "paper_source": paper["citation"], "reps": reps,
+            "seconds": round(time.perf_counter() - t_all, 1), "rows": rows}
+
+
 def host_baseline(A, b, variant, formulation, precond, threads, run_s=1.0):
     """The host executor on the headline workload (same matrix, k and
     method): fixed passes on `threads` cores, RHS-iterations/s of the
@@ -527,6 +596,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--no-random", action="store_true", help="skip the random sparse matrix section")
+    ap.add_argument("--no-tab4", action="store_true", help="skip Table 4 on the GPU (200^3 Poisson)")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
     ap.add_argument("--host-grid", type=int, default=160)
@@ -691,6 +761,10 @@ def main():
         out["merging_time_reduction_paper"] = {
             "source": tab4["citation"], "m": tab4["m"],
             **{v: [r[2] / 100.0 for r in tab4["rows"][nm]] for v, nm in tab4_names.get(args.precond, {}).items()}}
+
+    # ------------------------------------------- Table 4 on the GPU
+    if not args.no_tab4:
+        out["gpu_tab4"] = gpu_tab4(pk, dev)
 
     # ------------------------------------------------------ random sparse
     if not args.no_random:
