@@ -583,6 +583,32 @@ def axpby_tab1_host(n=10**8, threads=16, reps=3):
     return out
 
 
+def profile_run(pk, dev, what, maxit):
+    """One tier workload after a warm-up, for the tier kernel traces under
+    rocprofv3: the precision tier's matrix solved in FP64 or FP32 + FP64
+    refinement, or the batched tier's 64 systems (autotuned, then solved)."""
+    import torch
+
+    from workloads import config_problem
+
+    if what in ("fp64", "fp32_refine"):
+        cfg = config_problem(2, seed=0)
+        b = torch.from_numpy(cfg["b"]).to(dev)
+        s = pk.Solver.from_csr(cfg["A"], cfg["k"], precision=what, device=dev)
+        s.solve(b, tol=cfg["tol"], maxit=maxit)
+        t, (_, info) = timed(lambda: s.solve(b, tol=cfg["tol"], maxit=maxit))
+        print(what, "ms", round(t * 1e3, 2), "passes", int(info.iters.max()), flush=True)
+        s.close()
+    else:
+        cfg = config_problem(3, seed=0)
+        rhs = [torch.from_numpy(b).to(dev) for b, _ in cfg["rhs"]]
+        bs = pk.BatchedSolver(cfg["systems"], device=dev)
+        bs.tune(rhs, tol=cfg["tol"], maxit=maxit)
+        t, _ = timed(lambda: bs.solve(rhs, tol=cfg["tol"], maxit=maxit))
+        print("batched ms", round(t * 1e3, 2), "config", bs.config(), flush=True)
+        bs.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -600,6 +626,9 @@ def main():
     ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--no-random", action="store_true", help="skip the random sparse matrix section")
     ap.add_argument("--no-tab4", action="store_true", help="skip Table 4 on the GPU (200^3 Poisson)")
+    ap.add_argument("--profile-run", choices=("fp64", "fp32_refine", "batched"),
+                    help="run one tier workload after a warm-up and exit without the JSON line (the command "
+                         "behind the tier kernel traces)")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
     ap.add_argument("--host-grid", type=int, default=160)
@@ -624,6 +653,9 @@ def main():
     pk.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_run:
+        profile_run(pk, dev, args.profile_run, min(args.maxit, 3000))
+        return
     copy_gbps = copy_probe()
     print(f"# plain 1 GiB device copy: {copy_gbps} GB/s (read + write)", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()

@@ -376,16 +376,44 @@ __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __rest
 // Sums the block-major partials of nb row blocks over G runs of consecutive
 // blocks: out[p * G + g] = sum of bpart[b * P + p] for b in run g, in block
 // order; the finalize kernel then sums the G runs of each pair in run order.
+// Each workgroup sums one run of row blocks, pair by pair, in block order.
+// The run is staged through LDS in chunks that all 256 threads load (up to
+// kRunLoads independent loads each), so the pass is not bound by the latency
+// of one thread's chain of loads; thread p then adds the chunk's partials of
+// pair p in block order, the same order as a plain loop over the run.
+constexpr int kRunLoads = 24;
+constexpr int kRunChunk = 256 * kRunLoads;  // doubles per chunk (48 KB)
+
 __global__ __launch_bounds__(256) void reduce_runs_kernel(const double* __restrict__ bpart, int nb, int P,
                                                           double* __restrict__ out, int G, const Globals* glob) {
   if (glob && glob->nrun == 0) return;
+  __shared__ double s_chunk[kRunChunk];
   const int g = blockIdx.x;
+  const int t = threadIdx.x;
   const int b0 = (int)((long)nb * g / G), b1 = (int)((long)nb * (g + 1) / G);
-  for (int p = threadIdx.x; p < P; p += blockDim.x) {
-    double v = 0.0;
-    for (int b = b0; b < b1; ++b) v += bpart[(size_t)b * P + p];
-    out[(size_t)p * G + g] = v;
+  const int per = kRunChunk / P;  // whole blocks per chunk (P <= 256 by the launcher)
+  double v = 0.0;
+  for (int c0 = b0; c0 < b1; c0 += per) {
+    const int nbk = min(per, b1 - c0);
+    const int cnt = nbk * P;
+    const double* src = bpart + (size_t)c0 * P;
+    double tmp[kRunLoads];
+#pragma unroll
+    for (int j = 0; j < kRunLoads; ++j) {
+      const int i = t + 256 * j;
+      tmp[j] = i < cnt ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRunLoads; ++j) {
+      const int i = t + 256 * j;
+      if (i < cnt) s_chunk[i] = tmp[j];
+    }
+    __syncthreads();
+    if (t < P)
+      for (int j = 0; j < nbk; ++j) v += s_chunk[j * P + t];
+    __syncthreads();
   }
+  if (t < P) out[(size_t)t * G + g] = v;
 }
 
 template <class T, int CPL, int BS, bool OFF32, int STYLE>
@@ -553,6 +581,7 @@ hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void*
   if (epi < 0 || epi >= E_NUM || (epilogue_dots(epi) > 0 && !W) || (epilogue_prec(epi) && (!Yh || !diag)))
     return hipErrorInvalidValue;
   const int P = epilogue_dots(epi) * k;
+  if (P > 256) return hipErrorInvalidValue;  // one thread per pair in reduce_runs_kernel
   const int G = spmm_dot_runs(A.nblk);
   if (A.nblk > 0) {
     hipError_t e = fp32 ? spmm_dot_dispatch<float>(A, X, Y, W, Yh, diag, epi, k, bpart, glob, s)
