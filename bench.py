@@ -126,12 +126,14 @@ def roofline_of(solver, b, n, nnz, k, iters=10):
 
 
 def kernel_source_sha():
-    """Hash of the kernel sources; counter-derived traffic is reported only for
-    the source it was measured on."""
+    """Hash of the kernel sources and of the files that fix their launch
+    shapes and plans; counter-derived traffic is reported only for the source
+    it was measured on."""
     import hashlib
 
     h = hashlib.sha256()
-    for fn in ("spmm.hip", "kernels.hip", "method.hpp", "reduce.hpp"):
+    for fn in ("spmm.hip", "kernels.hip", "method.hpp", "reduce.hpp", "api.hip", "plans.cpp", "plan.hpp",
+               "internal.hpp"):
         with open(os.path.join(ROOT, "paper_1907_12874_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

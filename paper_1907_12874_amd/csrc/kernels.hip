@@ -305,7 +305,20 @@ __global__ __launch_bounds__(kBlock) void prec_kernel(const T* __restrict__ in, 
   if (c >= k) return;
   const int rpb = kBlock >> kpl;
   const long stride = (long)gridDim.x * rpb;
-  for (long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl); row < n; row += stride) {
+  long row = (long)blockIdx.x * rpb + (threadIdx.x >> kpl);
+  // four rows per step, every load of the step issued before the divisions
+  constexpr int U = 4;
+  for (; row + (U - 1) * stride < n; row += U * stride) {
+    T v[U], d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = in[(size_t)(row + u * stride) * k + c];
+      d[u] = diag[row + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u] / d[u], out + (size_t)(row + u * stride) * k + c);
+  }
+  for (; row < n; row += stride) {
     const size_t e = (size_t)row * k + c;
     __builtin_nontemporal_store(in[e] / diag[row], out + e);
   }
@@ -318,7 +331,7 @@ hipError_t launch_prec(const void* in, void* out, const void* diag, int n, int k
   while ((1 << kpl) < kp) ++kpl;
   const int rpb = kBlock >> kpl;
   long blocks = (n + rpb - 1) / rpb;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 512) blocks = 512;  // the streaming passes' grid: two waves per SIMD, four rows per step
   if (blocks < 1) blocks = 1;
   if (fp32)
     hipLaunchKernelGGL(prec_kernel<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const float*)in, (float*)out,
