@@ -531,6 +531,28 @@ def test_bitwise_fused(lib, variant, precond, k):
             assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
 
 
+@pytest.mark.parametrize("variant", ["classical", "reordered", "pipelined"])
+def test_bitwise_fused_k64_multichunk(lib, variant):
+    """k = 64 (the largest), Jacobi, on 52^3 rows: the products' epilogue
+    partials of up to 3 x 64 pairs are summed in runs of about 34 row blocks,
+    more than one LDS chunk (32 blocks at 192 pairs) each. Three fused passes
+    equal the oracle's in the kernels' order on the first and last column."""
+    import torch
+
+    say(f"bitwise fused k=64 multichunk {variant}")
+    A = conv_diff(52, 3, (1.0, 0.7, 0.3))
+    k = 64
+    b, _ = manufactured_rhs(A, k, seed=23)
+    S = A.to_scipy()
+    s = gpu_solver(lib, A, k, variant, "fused", "jacobi")
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=0.0, maxit=3)
+    X = to_np(x)
+    for c in (0, k - 1):
+        with oracle_dot(fused_dot(A, k, variant)):
+            ref = oracle.solve_column(S, b[:, c], None, variant, "fused", "jacobi", 0.0, 3)
+        assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
+
+
 # ---------------------------------------------------- full-size checks ---
 
 def test_full_size_cfg1_sampled(lib):
