@@ -11,14 +11,23 @@ with the matrix, b and x0 already in HBM. The headline is the classical merged
 form at k = 32, in RHS-iterations per second (sum over columns of the passes
 each column ran, divided by the step time).
 
-The JSON line also carries:
+Output: the full report (every section below) is written as JSON to
+--report (default gpurun_out/bench_report.json); stdout gets ONE compact JSON
+line (under 4 KB) with the contract's keys and a summary of each section.
+Progress lines go to stderr.
+
+The report carries:
   roofline      the dominant kernel of one iteration, timed with HIP events
                 around each launch on the stream it runs on, against 8 TB/s;
   cpu_baseline  the CPU oracle, timed on a bounded sample (one column, fixed
                 passes) on the host;
+  seeds         the headline solve on input seeds 1 and 2 (time, passes);
   sweep         merged vs basic for every method at k = 1..32: fixed-pass
                 throughput (RHS-iterations/s, algorithmic GB/s) and solves to
                 the same tolerance (equal accuracy, checked per column);
+  small_2d      the 64^2 2D system at k = 1 (launch-bound): per-iteration
+                time and launches of classical and Pipelined, basic and
+                merged, and the same system in the persistent batched kernel;
   gpu_tab4      Table 4 on the GPU with the paper's matrix (200^3 Poisson,
                 m = 1, 4, 16): per-iteration times, basic vs merged, of the
                 six methods beside the paper's times and gains;
@@ -585,6 +594,192 @@ def axpby_tab1_host(n=10**8, threads=16, reps=3):
     return out
 
 
+def small_2d_section(pk, dev, passes=100, reps=5, maxit=3000):
+    """The 2D 5-point convection-diffusion system on a 64 x 64 grid (n = 4096,
+    k = 1, no preconditioner, tol 1e-10): a launch-bound size, where the merge
+    criteria of Section 2.2 show up as kernel launches rather than bytes.
+    Per method: fixed-pass time per iteration ((t(2 + passes) - t(2)) /
+    passes, best of `reps`), launches per iteration, and a solve to the
+    tolerance (best of `reps`). Beside them, the same system through the
+    persistent batched kernel (classical merged, one launch for the whole
+    solve, autotuned), which has no per-pass launches."""
+    import torch
+
+    from workloads import config_problem
+
+    cfg = config_problem(0, seed=0)
+    A, tol = cfg["A"], cfg["tol"]
+    b = torch.from_numpy(cfg["b"]).to(dev)
+    x0 = torch.zeros_like(b)
+    x = torch.empty_like(b)
+    rows = []
+    for variant, form in (("classical", "basic"), ("classical", "merged"), ("classical", "fused"),
+                          ("pipelined", "basic"), ("pipelined", "merged")):
+        sv = pk.Solver.from_csr(A, 1, variant=variant, formulation=form, precond="none", device=dev)
+        tr = pk.plan_traffic(variant, form, "none")
+        sv.solve(b, x0, tol=0.0, maxit=2, out=x)
+        tt = {2: float("inf"), 2 + passes: float("inf")}
+        for _ in range(reps):
+            for p in tt:
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                sv.solve(b, x0, tol=0.0, maxit=p, out=x)
+                torch.cuda.synchronize()
+                tt[p] = min(tt[p], time.perf_counter() - ta)
+        per_it = (tt[2 + passes] - tt[2]) / passes
+        ts = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, inf = sv.solve(b, x0, tol=tol, maxit=maxit, out=x)
+            torch.cuda.synchronize()
+            ts = min(ts, time.perf_counter() - ta)
+        rows.append({"variant": variant, "formulation": form, "launches_per_iter": tr["launches"],
+                     "us_per_iter": round(per_it * 1e6, 2), "us_per_launch": round(per_it * 1e6 / tr["launches"], 2),
+                     "fixed_rhs_it_per_s": round(1.0 / per_it, 1), "solve_ms": round(ts * 1e3, 3),
+                     "solve_iters": int(inf.iters[0]), "solve_rhs_it_per_s": round(float(inf.iters[0]) / ts, 1),
+                     "converged": bool(inf.status[0] == 0), "relres_true": float(inf.relres_true[0])})
+        print(f"# small 2d {variant:9s} {form:6s}: {rows[-1]['us_per_iter']:.1f} us/it, {tr['launches']} launches/it, "
+              f"solve {rows[-1]['solve_ms']:.2f} ms, {rows[-1]['solve_iters']} it", file=sys.stderr, flush=True)
+        sv.close()
+    # the persistent batched kernel on this one system
+    bs = pk.BatchedSolver([(A, 1)], device=dev)
+    bs.tune([b], tol=tol, maxit=maxit)
+    tb = float("inf")
+    for _ in range(reps):
+        t, (_, infos) = timed(lambda: bs.solve([b], tol=tol, maxit=maxit))
+        tb = min(tb, t)
+    inf = infos[0]
+    c = bs.config()
+    pers = {"solve_ms": round(tb * 1e3, 3), "kernel_ms": round(c.last_ms, 3), "solve_iters": int(inf.iters[0]),
+            "us_per_iter": round(c.last_ms * 1e3 / max(1, int(inf.iters[0])), 2),
+            "solve_rhs_it_per_s": round(float(inf.iters[0]) / tb, 1), "converged": bool(inf.status[0] == 0),
+            "workgroups": int(c.workgroups.sum()), "variant": c.variant}
+    bs.close()
+    print(f"# small 2d persistent batched kernel: {pers['solve_ms']:.2f} ms, {pers['solve_iters']} it, "
+          f"{pers['us_per_iter']:.1f} us/it on {pers['workgroups']} workgroups", file=sys.stderr, flush=True)
+    return {"workload": f"2D 5-point convection-diffusion 64^2, velocity (1,0.5), n={A.n}, nnz={A.nnz}, k=1, "
+                        f"no preconditioner, tol {tol:g}",
+            "passes": passes, "reps": reps, "rows": rows, "persistent_classical_merged": pers}
+
+
+def seed_spread(pk, dev, A, k, args, seeds=(1, 2)):
+    """The headline solve on the other input seeds (same matrix, x* and so b
+    drawn from another seed): time per solve and pass counts."""
+    import torch
+
+    from workloads import manufactured_rhs
+
+    out = {}
+    s = pk.Solver.from_csr(A, k, variant=args.variant, formulation=args.formulation, precond=args.precond, device=dev)
+    for sd in seeds:
+        bh, _ = manufactured_rhs(A, k, seed=sd)
+        b = torch.from_numpy(bh).to(dev)
+        x0 = torch.zeros_like(b)
+        x = torch.empty_like(b)
+        s.solve(b, x0, tol=args.tol, maxit=args.maxit, out=x)
+        t, (_, info) = timed(lambda: s.solve(b, x0, tol=args.tol, maxit=args.maxit, out=x), reps=2)
+        out[str(sd)] = {"ms": round(t * 1e3, 2), "iters_min": int(info.iters.min()), "iters_max": int(info.iters.max()),
+                        "rhs_it_per_s": round(float(info.iters.sum()) / t, 1),
+                        "all_converged": bool(np.all(info.status == 0)),
+                        "relres_true_max": float(info.relres_true.max())}
+        print(f"# seed {sd}: {out[str(sd)]['ms']:.1f} ms/solve, iters {out[str(sd)]['iters_min']}.."
+              f"{out[str(sd)]['iters_max']}, {out[str(sd)]['rhs_it_per_s']:.0f} RHS-it/s", file=sys.stderr, flush=True)
+        del b, x0, x
+    s.close()
+    return out
+
+
+LINE_MAX_BYTES = 4000
+
+
+def compose_line(rep):
+    """The one JSON line printed last on stdout: the contract's keys, the
+    roofline and CPU baseline, and a compact summary of every section of the
+    full report (which goes to a file). Kept under LINE_MAX_BYTES: optional
+    summaries are dropped, least important first, if it would grow past it."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data")
+    line = {k: rep[k] for k in keys if k in rep}
+    cfg = rep.get("config", {})
+    line["config"] = {k: cfg[k] for k in ("workload", "n", "nnz", "k", "variant", "formulation", "precond", "tol")
+                      if k in cfg}
+    if "roofline" in rep:
+        r = rep["roofline"]
+        line["roofline"] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                              "bytes_per_launch", "avg_launch_ms") if k in r}
+    if "cpu_baseline" in rep:
+        c = rep["cpu_baseline"]
+        line["cpu_baseline"] = {k: c[k] for k in ("value", "unit", "cores", "kind", "sample") if k in c}
+    opt = []  # (key, value), most important first
+    if "solve" in rep:
+        s = rep["solve"]
+        opt.append(("solve", {k: s[k] for k in ("iters_min", "iters_max", "all_converged", "relres_true_max",
+                                                "algorithmic_GBps", "frac_of_peak") if k in s}))
+    if "copy_ceiling_GBps" in rep:
+        opt.append(("copy_GBps", rep["copy_ceiling_GBps"]))
+    if "seeds" in rep:
+        opt.append(("seeds", {sd: [v["ms"], v["iters_max"], v["all_converged"]] for sd, v in rep["seeds"].items()}))
+    if "merging_time_reduction" in rep:
+        # per method, the time reduction of merged over basic at each k of the sweep
+        ks = sorted({r["k"] for r in rep.get("sweep", [])})
+        g = rep["merging_time_reduction"]
+        opt.append(("merged_vs_basic", {"k": ks, **{v: [g.get(f"{v}_k{kk}") for kk in ks]
+                                                    for v in ("classical", "reordered", "pipelined", "improved")
+                                                    if any(f"{v}_k{kk}" in g for kk in ks)}}))
+        f = rep.get("fusion_time_reduction_vs_merged", {})
+        if f:
+            opt.append(("fused_vs_merged", {v: [f.get(f"{v}_k{kk}") for kk in ks]
+                                            for v in ("classical", "reordered", "pipelined")
+                                            if any(f"{v}_k{kk}" in f for kk in ks)}))
+        bad = [f"{r['variant']}/{r['formulation']}/k{r['k']}" for r in rep.get("sweep", []) if not r["equal_accuracy"]]
+        opt.append(("sweep_unequal_accuracy", bad))
+    if "small_2d" in rep:
+        sm = rep["small_2d"]
+        opt.append(("small_2d", {**{f"{r['variant'][:4]}_{r['formulation']}": [r["us_per_iter"], r["launches_per_iter"],
+                                                                                 r["solve_ms"], r["solve_iters"]]
+                                    for r in sm["rows"]},
+                                 "persistent": [sm["persistent_classical_merged"]["us_per_iter"],
+                                                sm["persistent_classical_merged"]["solve_ms"],
+                                                sm["persistent_classical_merged"]["solve_iters"]]}))
+    if "tiers" in rep:
+        t = rep["tiers"]
+        tl = {}
+        if "precision" in t:
+            p = t["precision"]
+            tl["precision"] = {"fp64_ms": p["fp64"]["ms"], "fp32_refine_ms": p["fp32_refine"]["ms"],
+                               "speedup": p["speedup_fp32_refine"],
+                               "err_vs_oracle": {m: p[m].get("err_vs_oracle") for m in ("fp64", "fp32_refine")}}
+        if "batched" in t:
+            bt = t["batched"]
+            tl["batched"] = {"ms": bt["ms"], "rhs_it_per_s": bt["rhs_it_per_s"], "GBps": bt["algorithmic_GBps"],
+                             "speedup_vs_loop": bt["speedup_vs_loop"]}
+        if "autograd" in t:
+            a = t["autograd"]
+            tl["autograd"] = {"fwd_ms": a["forward_ms"], "fwd_bwd_ms": a["forward_backward_ms"]}
+        opt.append(("tiers", tl))
+    if "random_sparse" in rep:
+        opt.append(("random_sparse", {f"k{r['k']}": [r["merged"]["ms_per_iter"], r["merged"]["frac_of_peak"],
+                                                     r["spmm"]["frac_of_peak"]]
+                                      for r in rep["random_sparse"]["rows"]}))
+    if "gpu_tab4" in rep:
+        opt.append(("gpu_tab4_imp", {f"{r['method']}_m{r['m']}": r["improvement"] for r in rep["gpu_tab4"]["rows"]}))
+    if "host_executor_baseline" in rep:
+        h = rep["host_executor_baseline"]
+        opt.append(("host_executor", {"value": h["value"], "cores": h["cores"]}))
+    if "report" in rep:
+        opt.append(("report", rep["report"]))
+    for k, v in opt:
+        line[k] = v
+    # drop the least important summaries until the line fits
+    for k, _ in reversed(opt):
+        if len(json.dumps(line)) <= LINE_MAX_BYTES:
+            break
+        if k != "report":
+            line.pop(k, None)
+    return line
+
+
 def profile_run(pk, dev, what, maxit):
     """One tier workload after a warm-up, for the tier kernel traces under
     rocprofv3: the precision tier's matrix solved in FP64 or FP32 + FP64
@@ -628,6 +823,10 @@ def main():
     ap.add_argument("--no-tiers", action="store_true")
     ap.add_argument("--no-random", action="store_true", help="skip the random sparse matrix section")
     ap.add_argument("--no-tab4", action="store_true", help="skip Table 4 on the GPU (200^3 Poisson)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^2 2D system (k = 1, launch-bound)")
+    ap.add_argument("--no-seeds", action="store_true", help="skip the headline solve on input seeds 1 and 2")
+    ap.add_argument("--report", default=os.path.join(ROOT, "gpurun_out", "bench_report.json"),
+                    help="where the full report goes (JSON); stdout gets one compact line")
     ap.add_argument("--profile-run", choices=("fp64", "fp32_refine", "batched"),
                     help="run one tier workload after a warm-up and exit without the JSON line (the command "
                          "behind the tier kernel traces)")
@@ -732,6 +931,10 @@ def main():
         print(f"# roofline: {roof['kernel']} {roof['achieved']:.0f} GB/s ({roof['frac']:.1%})", file=sys.stderr,
               flush=True)
 
+    # ------------------------------------------------------ other seeds
+    if not args.no_seeds:
+        out["seeds"] = seed_spread(pk, dev, A, k, args)
+
     # ------------------------------------------------------------- sweep
     if not args.no_sweep:
         sweep = []
@@ -804,6 +1007,10 @@ def main():
             "source": tab4["citation"], "m": tab4["m"],
             **{v: [r[2] / 100.0 for r in tab4["rows"][nm]] for v, nm in tab4_names.get(args.precond, {}).items()}}
 
+    # ------------------------------------------- the 64^2 2D system, k = 1
+    if not args.no_small:
+        out["small_2d"] = small_2d_section(pk, dev)
+
     # ------------------------------------------- Table 4 on the GPU
     if not args.no_tab4:
         out["gpu_tab4"] = gpu_tab4(pk, dev)
@@ -844,7 +1051,15 @@ def main():
         out["cpu_baseline"] = cpu_baseline(A, cfg["b"], args.variant, args.formulation, args.precond)
         print(f"# cpu baseline: {out['cpu_baseline']['value']} RHS-it/s", file=sys.stderr, flush=True)
 
-    print(json.dumps(out), flush=True)
+    # the full report to a file, one compact line (under 4 KB) to stdout
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(args.report)), exist_ok=True)
+        with open(args.report, "w") as f:
+            json.dump(out, f, indent=1)
+        out["report"] = os.path.relpath(os.path.abspath(args.report), ROOT)
+    except OSError as e:
+        print(f"# could not write the full report: {e}", file=sys.stderr, flush=True)
+    print(json.dumps(compose_line(out)), flush=True)
 
 
 if __name__ == "__main__":

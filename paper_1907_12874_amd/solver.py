@@ -58,6 +58,9 @@ class Solver:
         self.nnz = int(self.col_idx.numel())
         self.k = int(k)
         self.variant, self.formulation, self.precond, self.precision = variant, formulation, precond, precision
+        # bumped by every update_values: lets a differentiable solve tell
+        # whether the values it was run with are still the solver's
+        self.values_version = 0
         L = lib()
         desc = _lib.CSRDesc(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.values.data_ptr())
         self._desc = desc
@@ -148,6 +151,7 @@ class Solver:
         with torch.cuda.device(self.device):
             self._set_stream()
             check(lib().bicgstab_update_values(self._h), "bicgstab_update_values")
+        self.values_version += 1
 
     def spmm(self, X, out=None):
         X = self._block(X, "X")

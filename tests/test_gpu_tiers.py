@@ -241,3 +241,40 @@ def test_autograd_full_size_64cubed(lib):
     fd = (loss(field + h * d) - loss(field - h * d)) / (2 * h)
     an = grad @ d
     assert abs(fd - an) <= 1e-4 * abs(an), (fd, an)
+
+
+def test_autograd_solver_reused_before_backward(lib):
+    """One solver, two differentiable solves with different matrix values
+    before either backward runs (two solves in one loss): each gradient
+    equals dense FP64 autograd of its own solve, so the adjoint of the first
+    solve runs with the first solve's A^T, not the values the solver held
+    last."""
+    import torch
+
+    from paper_1907_12874_amd import autograd as pag
+
+    say("autograd: one solver, two forwards, then backward")
+    A = conv_diff(6, 3, (3.0, -2.0, 1.5))
+    B = np.random.default_rng(17).uniform(-1, 1, (A.n, 2))
+    s = lib.Solver.from_csr(A, 2)
+    rows = torch.as_tensor(A.row_of_entry())
+    cols = torch.as_tensor(A.col_idx.astype(np.int64))
+    scales = (1.0, 1.7)
+    vs = [torch.tensor(A.values * sc, dtype=torch.float64, device="cuda", requires_grad=True) for sc in scales]
+    Bt = torch.from_numpy(B).cuda()
+    X1 = pag.solve(vs[0], Bt, s, tol=1e-13, maxit=3000)
+    X2 = pag.solve(vs[1], Bt, s, tol=1e-13, maxit=3000)
+    w = torch.linspace(-1, 1, X1.numel(), dtype=torch.float64, device="cuda").view_as(X1)
+    # the first solve's backward alone, while the solver holds the second's values
+    ((X1 * X1).sum() + (w * X1).sum()).backward(retain_graph=True)
+    g1 = vs[0].grad.cpu().numpy().copy()
+    (X2 * X2).sum().backward()
+    g2 = vs[1].grad.cpu().numpy().copy()
+    for sc, g, extra in ((scales[0], g1, True), (scales[1], g2, False)):
+        vc = torch.tensor(A.values * sc, dtype=torch.float64, requires_grad=True)
+        Ad = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((rows, cols), vc)
+        Xc = torch.linalg.solve(Ad, torch.from_numpy(B))
+        loss = (Xc * Xc).sum() + ((w.cpu() * Xc).sum() if extra else 0.0)
+        loss.backward()
+        ref = vc.grad.numpy()
+        assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < 1e-9, (sc, np.linalg.norm(g - ref) / np.linalg.norm(ref))
