@@ -134,6 +134,28 @@ int bicgstab_set_stream(bicgstab_t h, void* stream);
  * every few iterations and returns when every column has stopped. */
 int bicgstab_solve(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit, bicgstab_info* info);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * bicgstab_solve with the same arguments, results and summation orders
+ * (bitwise the same solution, counts and statuses), but the call allocates
+ * nothing. Its workspace is a static device array of
+ * BICGSTAB_NOALLOC_SCRATCH_BYTES inside the library, one per GPU (held from
+ * when the library's device code is loaded on that GPU until the process
+ * ends), instead of the handle's own workspace, which the call leaves
+ * untouched. The handle's set-up data (diagonal, row-block list) is rebuilt
+ * in the array at every call, and iterations are launched directly rather
+ * than from captured graphs.
+ *   - BICGSTAB_ENOMEM if bicgstab_workspace_bytes(h) exceeds the array.
+ *   - BICGSTAB_EUNSUPPORTED for FP32-refinement handles and for Improved
+ *     BiCGStab (it builds a transposed matrix, an allocation).
+ *   - Every call on one GPU shares that GPU's array and finds the previous
+ *     call's contents there: calls that overlap on one GPU (two threads, or
+ *     two streams) race and must be serialised by the caller.
+ *   - bicgstab_history reports no passes after this call. */
+#define BICGSTAB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int bicgstab_solve_noalloc(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit,
+                           bicgstab_info* info);
+
 /* Solve A^T Lambda = G with the same method (the adjoint solve of the
  * gradient of x = A^{-1} b). Builds the transposed CSR on the device at the
  * first call. Same argument conventions as bicgstab_solve. */

@@ -61,6 +61,7 @@ def lib():
     L.bicgstab_set_workspace.argtypes = [H, vp, C.c_size_t]
     L.bicgstab_set_stream.argtypes = [H, vp]
     L.bicgstab_solve.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
+    L.bicgstab_solve_noalloc.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
     L.bicgstab_solve_transpose.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
     L.bicgstab_grad_values.argtypes = [H, vp, vp, vp]
     L.bicgstab_update_values.argtypes = [H]
@@ -108,4 +109,5 @@ def exported_symbols():
         "bicgstab_batched_set_workspace", "bicgstab_batched_set_stream", "bicgstab_batched_solve",
         "bicgstab_batched_tune", "bicgstab_batched_get_config", "bicgstab_batched_set_config",
         "bicgstab_batched_variant_info", "bicgstab_batched_destroy", "bicgstab_axpby_tab1",
+        "bicgstab_solve_noalloc",
     ]

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -104,6 +105,7 @@ struct bicgstab_ctx {
   int spmm_xcd_chunk = 1;    // SpMM row blocks per XCD run (1: round-robin order)
   bool use_graph = true;
   // pinned host mirrors
+  int32_t* h_blk = nullptr;  // the row-block list, the source of its uploads
   int* h_nrun = nullptr;
   double* h_sc = nullptr;
   int* h_ist = nullptr;
@@ -223,7 +225,7 @@ int prepare(bicgstab_ctx* h) {
     h->owned = true;
   }
   layout(h, true);
-  HIPCHK(hipMemcpyAsync(h->blk, h->part.blk.data(), h->part.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
+  HIPCHK(hipMemcpyAsync(h->blk, h->h_blk, h->part.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
   if (h->precond == BICGSTAB_PRECOND_JACOBI || fp32_inner(h)) {
     HIPCHK(hipMemsetAsync(h->glob, 0, sizeof(Globals), h->ws));
     HIPCHK(launch_extract_diag(h->row_ptr, h->col, h->val, h->diag, h->diag32, (int)h->n, h->glob, h->ws));
@@ -598,6 +600,35 @@ int build_transpose(bicgstab_ctx* h) {
   return BICGSTAB_OK;
 }
 
+// ---- allocation-free solve -------------------------------------------------
+// bicgstab_solve_noalloc runs a solve with its workspace in this static array
+// instead of caller-given or hipMalloc'd memory. Each GPU the library runs on
+// holds its own copy (allocated when the code object is loaded, kept until
+// the process ends). The array's name is a host-side stand-in, never a device
+// address: host code uses only the address hipGetSymbolAddress returns, taken
+// once per device with that device current.
+constexpr size_t kScratchBytes = BICGSTAB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `dev`.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(BICGSTAB_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BICGSTAB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BICGSTAB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -648,6 +679,8 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
     return fail(BICGSTAB_EINVAL, err);
   }
   auto bail = [&](int code, const std::string& m) {
+    for (void* p : {(void*)h->h_blk, (void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
+      if (p) hipHostFree(p);
     if (h->ws) hipStreamDestroy(h->ws);
     if (h->ev) hipEventDestroy(h->ev);
     delete h;
@@ -678,11 +711,13 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   }
   h->spmm_opl = std::max(0, std::min(64, env_int("BICGSTAB_SPMM_RPL", 0)));
   h->part = spmm_partition(rp, k, h->spmm_opl);
-  if (hipHostMalloc((void**)&h->h_nrun, 64, hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void**)&h->h_blk, h->part.blk.size() * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_nrun, 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_sc, (size_t)S_NSCAL * kMaxK * 8, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_ist, (size_t)I_NINT * kMaxK * 4, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&h->h_glob, sizeof(Globals), hipHostMallocDefault) != hipSuccess)
     return bail(BICGSTAB_ENOMEM, "pinned host allocation failed");
+  std::memcpy(h->h_blk, h->part.blk.data(), h->part.blk.size() * 4);
   *out = h;
   return BICGSTAB_OK;
 }
@@ -715,6 +750,43 @@ int bicgstab_set_stream(bicgstab_t h, void* stream) {
 
 int bicgstab_solve(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit, bicgstab_info* info) {
   return solve_common(h, 0, d_b, d_x, tol, maxit, info);
+}
+
+int bicgstab_solve_noalloc(bicgstab_t h, const double* d_b, double* d_x, double tol, int32_t maxit,
+                           bicgstab_info* info) {
+  if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (fp32_inner(h)) return fail(BICGSTAB_EUNSUPPORTED, "allocation-free solve: FP64 handles only");
+  if (has_spmm_t(h))
+    return fail(BICGSTAB_EUNSUPPORTED, "allocation-free solve: Improved BiCGStab builds a transposed matrix");
+  HIPCHK(hipSetDevice(h->device));
+  void* sp = nullptr;
+  int rc = scratch_address(h->device, &sp);
+  if (rc) return rc;
+  const size_t need = layout(h, false);
+  if (need > kScratchBytes)
+    return fail(BICGSTAB_ENOMEM, "allocation-free solve: the handle needs " + std::to_string(need) +
+                                     " bytes of workspace, the static scratch holds " + std::to_string(kScratchBytes));
+  // this call's workspace is the scratch: the set-up (diagonal, row-block
+  // list, state) is written there afresh and iterations are launched
+  // directly (a captured graph holds the handle's own workspace addresses)
+  char* const own_base = h->base;
+  const size_t own_bytes = h->bytes;
+  const bool own_owned = h->owned, own_prepared = h->prepared, own_graph = h->use_graph;
+  h->base = (char*)sp;
+  h->bytes = kScratchBytes;
+  h->owned = false;
+  h->prepared = false;
+  h->use_graph = false;
+  rc = solve_common(h, 0, d_b, d_x, tol, maxit, info);
+  // back to the handle's own workspace, which this call did not touch
+  h->base = own_base;
+  h->bytes = own_bytes;
+  h->owned = own_owned;
+  h->use_graph = own_graph;
+  if (h->base) layout(h, true);
+  h->prepared = own_prepared && h->base != nullptr;
+  h->hist_count = 0;  // the history of this call stayed in the scratch
+  return rc;
 }
 
 int bicgstab_solve_transpose(bicgstab_t h, const double* d_g, double* d_lambda, double tol, int32_t maxit,
@@ -856,7 +928,7 @@ int bicgstab_destroy(bicgstab_t h) {
   for (void* p : {(void*)h->rp_t, (void*)h->col_t, (void*)h->perm_t, (void*)h->val_t, (void*)h->val32_t,
                   (void*)h->blk_t, (void*)h->bpart_t})
     if (p) hipFree(p);
-  for (void* p : {(void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
+  for (void* p : {(void*)h->h_blk, (void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
     if (p) hipHostFree(p);
   if (h->ws) hipStreamDestroy(h->ws);
   if (h->ev) hipEventDestroy(h->ev);

@@ -120,6 +120,24 @@ class Solver:
                                        int(maxit), C.byref(info)), "bicgstab_solve")
         return x, SolveInfo(*arrs)
 
+    def solve_noalloc(self, b, x0=None, tol: float = 1e-8, maxit: int = 1000, out=None):
+        """solve() through bicgstab_solve_noalloc: the library's static device
+        scratch is the workspace of the call (no device allocation in the
+        library; the tensors here are the caller's). Returns (X, SolveInfo)."""
+        b = self._block(b, "b")
+        if out is not None:
+            x = out
+            if x0 is not None:
+                x.copy_(self._block(x0, "x0"))
+        else:
+            x = torch.zeros_like(b) if x0 is None else self._block(x0, "x0").clone()
+        info, arrs = self._info_struct()
+        with torch.cuda.device(self.device):
+            self._set_stream()
+            check(lib().bicgstab_solve_noalloc(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                               float(tol), int(maxit), C.byref(info)), "bicgstab_solve_noalloc")
+        return x, SolveInfo(*arrs)
+
     def solve_transpose(self, g, tol: float = 1e-8, maxit: int = 1000):
         """Solve A^T L = G from L = 0. Returns (L, SolveInfo)."""
         g = self._block(g, "g")
