@@ -28,10 +28,27 @@ Section 1):
   stop the column as BREAKDOWN before any update of that pass. psi = 0 (phi = 0
   in Alg. 4, 6, 7) sets omega = 0 instead of dividing; if the stop test then
   fails, the pass's x and r updates are still applied and the column stops as
-  BREAKDOWN. rho_{j+1} = 0 and a zero denominator for alpha_{j+1} (Alg. 4, 7)
-  stop the column as BREAKDOWN after that pass's x and r updates.
+  BREAKDOWN. rho_{j+1} = 0 (Alg. 1, 2, 4, 5, 7) and a zero denominator for
+  alpha_{j+1} (Alg. 4, 7) stop the column as BREAKDOWN after that pass's x and
+  r updates; in Alg. 6 a zero rho_{j+1} is a loss of the recurrence (below).
 * A non-finite alpha, omega, stop estimate, beta or alpha_{j+1} stops the
   column as NONFINITE at the point where that scalar is formed.
+* Alg. 6 forms rho_{j+1} = -omega_j psi_j from the exact-arithmetic
+  orthogonality (r-tilde_j, r_0) = 0. Rounding leaves the stored vectors off
+  that relation by an amount that adds up pass by pass and does not shrink with
+  the residual, so once |rho_{j+1}| falls to that level the recurrence carries
+  no information and alpha is formed from noise (the paper sets such
+  convergence issues of the reordering aside). Reading: a running bound E of
+  the accumulated terms, E_0 = rho_0 and
+  E_{j+1} = E_j + sqrt(rho^) (||r_j|| + 2 sqrt(eta_j) + 2 |omega_j| sqrt(phi_j)),
+  with rho^ = (r_0, r_0) of the current shadow vector and ||r_j|| taken from
+  the previous pass's stop estimate (rho_0 at the first pass). When
+  |rho_{j+1}| <= RESTART_KAPPA * u * E_{j+1} (u = 2^-53; this includes
+  rho_{j+1} = 0) the method restarts after the pass's updates: the shadow
+  vector becomes r_{j+1}, rho_{j+1} = eta_j - omega_j theta_j (the pass's stop
+  estimate, which is (r_{j+1}, r_{j+1}) in exact arithmetic), beta_j = 0 (so
+  v-hat_{j+1} = z_{j+1}), rho^ = rho_{j+1} and E = eta_j. A restart with a
+  stop estimate that is not positive stops the column as BREAKDOWN instead.
 * Alg. 7 typos: the initial line reads w-hat_0 = M^{-1} w_0, and the line after
   the last grouped update reads w-hat_{j+1} = M^{-1} w_{j+1},
   t_{j+1} = A w-hat_{j+1}.
@@ -50,6 +67,7 @@ Section 1):
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -59,6 +77,10 @@ CONVERGED = 0
 MAXIT = 1
 BREAKDOWN = 2
 NONFINITE = 3
+
+# Unit roundoff of FP64 and the factor of the Reordered method's restart test.
+U64 = 2.0**-53
+RESTART_KAPPA = 16.0
 
 STATUS_NAMES = {RUNNING: "running", CONVERGED: "converged", MAXIT: "maxit", BREAKDOWN: "breakdown", NONFINITE: "nonfinite"}
 
@@ -332,7 +354,10 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     v_j and t_j (s_j = M^{-1} v_j, q_j = M^{-1} t_j) so that z_{j+1} = M^{-1}
     r_{j+1} comes from a vector update; rho_{j+1} = -omega_j psi_j uses the
     exact-arithmetic orthogonality (r-tilde_j, r_0) = 0. The z_{j+1} line is
-    taken as printed (it already carries the paper's fix of the original)."""
+    taken as printed (it already carries the paper's fix of the original).
+    When rounding has used up what that relation carries (the restart test of
+    the module docstring), the method restarts with r_{j+1} as the shadow
+    vector."""
     rec = _Recorder(trace, trace_vectors)
     early, x, r, rho, eps2 = _begin(A, b, x0, tol)
     if early is not None:
@@ -340,6 +365,9 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     r0 = r.copy()
     z = Minv(r)
     vh = z.copy()
+    rho_sh = rho      # (r_0, r_0) of the shadow vector
+    err = rho         # E_0
+    est_prev = rho    # ||r_0||^2
     for j in range(maxit):
         v = A @ vh
         delta = dot(v, r0)
@@ -360,23 +388,38 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
             return ColumnResult(x, r, j + 1, NONFINITE, trace)
         stop = est < eps2
         stop_breakdown = False
+        restart = False
         if not stop:
             rho_next = -omega * psi
-            stop_breakdown = omega == 0.0 or rho_next == 0.0
+            stop_breakdown = omega == 0.0
             if not stop_breakdown:
-                beta = (rho_next / rho) * (alpha / omega)
-                if not np.isfinite(beta):
-                    return ColumnResult(x, r, j + 1, NONFINITE, trace)
+                rn = math.sqrt(est_prev) if est_prev > 0.0 else 0.0
+                err = err + math.sqrt(rho_sh) * (rn + 2.0 * math.sqrt(eta) + 2.0 * abs(omega) * math.sqrt(phi))
+                restart = abs(rho_next) <= RESTART_KAPPA * U64 * err
+                if restart:
+                    stop_breakdown = not est > 0.0
+                    rho_next = est
+                    beta = 0.0
+                    rho_sh = est
+                    err = eta
+                else:
+                    beta = (rho_next / rho) * (alpha / omega)
+                    if not np.isfinite(beta):
+                        return ColumnResult(x, r, j + 1, NONFINITE, trace)
         r = rt - omega * t
         x = x + alpha * vh + omega * th
-        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r, rt=rt, r0=r0)
+        rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est, "theta": theta, "phi": phi, "psi": psi,
+                "eta": eta, "err": err, "restart": restart}, x=x, r=r, rt=rt, r0=r0)
         if stop:
             return ColumnResult(x, r, j + 1, CONVERGED, trace)
         if stop_breakdown:
             return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
+        if restart:
+            r0 = r.copy()
         z = th - omega * q
         vh = z + beta * (vh - omega * s)
         rho = rho_next
+        est_prev = est
     return ColumnResult(x, r, maxit, MAXIT, trace)
 
 

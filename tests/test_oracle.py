@@ -108,6 +108,78 @@ def test_reordered_orthogonality():
         assert abs(rt @ r0) <= 1e-10 * np.linalg.norm(rt) * np.linalg.norm(r0)
 
 
+def _reordered_trace(kappa, monkeypatch, g=24, col=19, tol=1e-8):
+    """Alg. 6 on the 3D convection-diffusion system with Jacobi, one column,
+    with the restart factor set to kappa; returns the trace and the result."""
+    monkeypatch.setattr(ob, "RESTART_KAPPA", kappa)
+    A = conv_diff(g, 3, (1.0, 0.7, 0.3))
+    S = A.to_scipy()
+    b = manufactured_rhs(A, 32, seed=0)[0][:, col].copy()
+    tr = []
+    res = solve_column(S, b, None, "reordered", "merged", "jacobi", tol, 2000, trace=tr, trace_vectors=True)
+    return S, b, tr, res
+
+
+def _true_rho_next(tr):
+    """(r_{j+1}, r_0) of every pass, summed exactly (math.fsum) from the stored
+    vectors, beside the recurrence's rho_{j+1} (the next record's rho)."""
+    import math
+
+    out = []
+    for i in range(len(tr) - 1):
+        r, r0 = tr[i]["vec"]["r"], tr[i]["vec"]["r0"]
+        out.append((tr[i + 1]["rho"], math.fsum(r * r0), tr[i]["restart"]))
+    return out
+
+
+def test_reordered_printed_listing_loses_rho(monkeypatch):
+    """Without the restart (factor 0: only an exact zero rho restarts) the
+    listing's rho_{j+1} = -omega_j psi_j drifts from the true (r_{j+1}, r_0)
+    by an offset that does not shrink with the residual, until the
+    recurrence is noise: some pass's rho is off by more than its own size."""
+    _, _, tr, res = _reordered_trace(0.0, monkeypatch)
+    pairs = _true_rho_next(tr)
+    assert not any(rs for _, _, rs in pairs)
+    assert any(abs(rho - true) > abs(rho) for rho, true, _ in pairs)
+
+
+def test_reordered_restart_keeps_rho_informative(monkeypatch):
+    """With the restart test, every pass that carries the recurrence on has
+    rho_{j+1} within 25% of the exactly summed (r_{j+1}, r_0); a restart takes
+    r_{j+1} as the new shadow vector with rho_{j+1} its squared norm (the stop
+    estimate) and beta = 0; the solve converges and agrees with a direct
+    solve."""
+    import math
+
+    S, b, tr, res = _reordered_trace(ob.RESTART_KAPPA, monkeypatch)
+    pairs = _true_rho_next(tr)
+    restarts = [i for i, (_, _, rs) in enumerate(pairs) if rs]
+    assert restarts, "the case is meant to hit the restart test"
+    for rho, true, rs in pairs:
+        if not rs:
+            assert abs(rho - true) <= 0.25 * abs(rho)
+    for i in restarts:
+        r = tr[i]["vec"]["r"]
+        assert np.array_equal(tr[i + 1]["vec"]["r0"], r)
+        assert tr[i + 1]["rho"] == tr[i]["est"]
+        assert abs(tr[i]["est"] - math.fsum(r * r)) <= 1e-6 * tr[i]["est"]
+    assert res.status == CONVERGED
+    assert np.linalg.norm(b - S @ res.x) <= 1.1e-8 * np.linalg.norm(b)
+    x_ref = sp.linalg.spsolve(S.tocsc(), b)
+    assert np.linalg.norm(res.x - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
+
+
+def test_reordered_restart_test_bounds_the_drift(monkeypatch):
+    """The bound E of the restart test covers the drift it is built for: on
+    the passes before the first restart, |rho_{j+1} - (r_{j+1}, r_0)| stays
+    below 4 u E_{j+1}."""
+    _, _, tr, _ = _reordered_trace(ob.RESTART_KAPPA, monkeypatch)
+    for i, (rho, true, rs) in enumerate(_true_rho_next(tr)):
+        if rs:
+            break
+        assert abs(rho - true) <= 4 * ob.U64 * tr[i]["err"]
+
+
 def test_pipelined_auxiliary_vectors():
     """Alg. 4 keeps s = A p, z = A s, y = A q, v = A z, w = A r, t = A w;
     Alg. 7 keeps the same with hat vectors on the right (s = A p-hat, ...) and
