@@ -6,7 +6,13 @@
  * in Krasnopolsky, "Revisiting Performance of BiCGStab Methods for Solving
  * Systems with Multiple Right-Hand Sides" (arXiv:1907.12874):
  *   - classical BiCGStab            (Appendix B, Alg. 1 basic; Alg. 2 / Alg. 5 merged)
- *   - Reordered BiCGStab            (Appendix B, Alg. 6)
+ *   - Reordered BiCGStab            (Appendix B, Alg. 6; its recurrence
+ *                                    rho_{j+1} = -omega_j psi_j is checked
+ *                                    against a running bound of the rounding
+ *                                    it has absorbed, and a column whose rho
+ *                                    has fallen to that bound restarts with
+ *                                    r_{j+1} as its shadow vector: the paper
+ *                                    leaves such convergence issues aside)
  *   - Pipelined BiCGStab            (Appendix B, Alg. 4 / Alg. 7)
  *   - Improved BiCGStab             (Appendix B, Alg. 3)
  * each in the "basic" form (one memory pass per vector operation, the Basic

@@ -955,7 +955,7 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
   for (const Step& s : P.iter) {
     if (s.kind == K_GROUP) {
       r += s.nin;
-      w += s.nout;
+      w += s.nout - op_info(s.op).ncond;
       if (op_info(s.op).ndot > 0 || s.fin != F_NONE) ++fin_kernels;  // its finalize kernel
     } else if (s.kind == K_PREC) {
       ++pa;

@@ -167,9 +167,12 @@ void group(Ctx& h, const Step& st, double* const* vp) {
   if (Op::EARLY && h.glob.nrun == 0) return;
   const int k = h.k;
   bool on[kMaxK];
+  unsigned wmask[kMaxK];
   Coef cf[kMaxK];
   for (int c = 0; c < k; ++c) {
     on[c] = true;
+    // outputs in COUT are written only where the column restarts
+    wmask[c] = Op::COUT == 0u || ISh(h, I_RESTART, c) != 0 ? ~0u : ~Op::COUT;
     if (Op::PART == PART_RUN) on[c] = ISh(h, I_STATUS, c) == ST_RUNNING;
     if (Op::PART == PART_ZEROB) on[c] = ISh(h, I_ZEROB, c) != 0;
     cf[c].alpha = SCh(h, S_ALPHA, c);
@@ -200,7 +203,8 @@ void group(Ctx& h, const Step& st, double* const* vp) {
         for (int q = 0; q < Op::NIN; ++q) v[q] = in[q][e];
         if (Op::USE_D) v[Op::NIN] = h.diag[i];
         Op::template f<double>(v, cf[c], o, acc[c]);
-        for (int j = 0; j < Op::NOUT; ++j) out[j][e] = o[j];
+        for (int j = 0; j < Op::NOUT; ++j)
+          if ((wmask[c] >> j) & 1) out[j][e] = o[j];
       }
     }
     if (Op::NDOT > 0)
@@ -250,6 +254,7 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_IB_X, KIbX)
     G(OP_F_PP_G2H, KPPG2H)
     G(OP_F_PP_G4H, KPPG4H)
+    G(OP_RE_R, KReR)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }

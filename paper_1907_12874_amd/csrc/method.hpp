@@ -31,12 +31,15 @@ struct Coef {
 // running columns, every column, or the columns whose right-hand side is zero.
 enum Part { PART_RUN = 0, PART_ALL = 1, PART_ZEROB = 2 };
 
-#define OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, USED)   \
-  static constexpr int NIN = NI, NOUT = NO, NDOT = ND;   \
-  static constexpr unsigned XIN = XI, XOUT = XO;         \
-  static constexpr int PART = PT;                        \
-  static constexpr bool EARLY = EARLY_;                  \
+// COUT: bitmask of outputs written only for a column that restarts in this
+// pass (I_RESTART set by the scalar step before it).
+#define OP_HEAD_C(NI, NO, ND, XI, XO, PT, EARLY_, USED, CO) \
+  static constexpr int NIN = NI, NOUT = NO, NDOT = ND;      \
+  static constexpr unsigned XIN = XI, XOUT = XO, COUT = CO; \
+  static constexpr int PART = PT;                           \
+  static constexpr bool EARLY = EARLY_;                     \
   static constexpr bool USE_D = USED;
+#define OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, USED) OP_HEAD_C(NI, NO, ND, XI, XO, PT, EARLY_, USED, 0u)
 #define OP_HEAD(NI, NO, ND, XI, XO, PT, EARLY_) OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, false)
 // USE_D: the op also reads the row's diagonal entry a_ii, passed as v[NIN].
 #define OP_HEAD_D(NI, NO, ND, XI, XO, PT, EARLY_) OP_HEAD_(NI, NO, ND, XI, XO, PT, EARLY_, true)
@@ -128,6 +131,14 @@ struct KCXrRho {  // in: x, p, s, t, r0 ; out: x, r
     double r = R(v[2] - c.omega * v[3]);
     o[1] = r;
     a[0] += r * v[4];
+  }
+};
+struct KReR {  // Alg. 6: in: rt, t ; out: r = rt - omega t, and r0 = r where the column restarts
+  OP_HEAD_C(2, 2, 0, 0, 0, PART_RUN, true, false, 2u)
+  OP_F {
+    const double r = R(v[0] - c.omega * v[1]);
+    o[0] = r;
+    o[1] = r;
   }
 };
 struct KCRRho {  // in: s, t, r0 ; out: r
@@ -378,6 +389,10 @@ struct KIbX {  // in: x, z, s ; out: x
 
 // ------------------------------------------------------- scalar recurrence ---
 
+// FP64 unit roundoff and the factor of the Reordered method's restart test.
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+constexpr double kRestartKappa = 16.0;
+
 BCG_HD BCG_INLINE double& SC(const Ctl& C, int slot, int c) { return C.sc[slot * kMaxK + c]; }
 BCG_HD BCG_INLINE int& IS(const Ctl& C, int slot, int c) { return C.ist[slot * kMaxK + c]; }
 
@@ -445,6 +460,9 @@ BCG_HD inline void finalize_column(int step, int c, const Ctl& C) {
     SC(C, S_OMEGA, c) = 1.0;
     SC(C, S_BETA, c) = 0.0;
     SC(C, S_EST, c) = rr;
+    SC(C, S_RE_ERR, c) = rr;
+    SC(C, S_RE_SH, c) = rr;
+    IS(C, I_RESTART, c) = 0;
     if (!isfinite(bb)) {
       st = ST_NONFINITE;
       return;
@@ -577,22 +595,45 @@ BCG_HD inline void finalize_column(int step, int c, const Ctl& C) {
         stop(ST_NONFINITE);
         return;
       }
+      const double est_prev = SC(C, S_EST, c);  // ||r_j||^2 as the previous pass estimated it
       SC(C, S_OMEGA, c) = omega;
       SC(C, S_EST, c) = est;
+      IS(C, I_RESTART, c) = 0;
       if (est < eps2) {
         pend = ST_CONVERGED;
         return;
       }
-      const double rho1 = -omega * psi;
-      if (omega == 0.0 || rho1 == 0.0) {
+      if (omega == 0.0) {
         pend = ST_BREAKDOWN;
         return;
       }
-      const double beta = (rho1 / SC(C, S_RHO, c)) * (SC(C, S_ALPHA, c) / omega);
-      if (!isfinite(beta)) {
-        stop(ST_NONFINITE);
-        return;
+      // rho_{j+1} = -omega psi rests on (rt, r0) = 0, which rounding meets
+      // only up to an error that adds up pass by pass; E bounds it. Once
+      // |rho_{j+1}| is down to u E the recurrence carries no information:
+      // restart with the shadow vector r0 = r_{j+1} and rho_{j+1} = the stop
+      // estimate of (r_{j+1}, r_{j+1}), beta = 0.
+      const double rn = est_prev > 0.0 ? sqrt(est_prev) : 0.0;
+      double err = SC(C, S_RE_ERR, c) + sqrt(SC(C, S_RE_SH, c)) * (rn + 2.0 * sqrt(eta) + 2.0 * fabs(omega) * sqrt(phi));
+      double rho1 = -omega * psi;
+      double beta;
+      if (fabs(rho1) <= kRestartKappa * kU64 * err) {
+        if (!(est > 0.0)) {
+          pend = ST_BREAKDOWN;
+          return;
+        }
+        rho1 = est;
+        beta = 0.0;
+        SC(C, S_RE_SH, c) = est;
+        err = eta;
+        IS(C, I_RESTART, c) = 1;
+      } else {
+        beta = (rho1 / SC(C, S_RHO, c)) * (SC(C, S_ALPHA, c) / omega);
+        if (!isfinite(beta)) {
+          stop(ST_NONFINITE);
+          return;
+        }
       }
+      SC(C, S_RE_ERR, c) = err;
       SC(C, S_BETA, c) = beta;
       SC(C, S_RHONEXT, c) = rho1;
       return;

@@ -33,13 +33,16 @@ enum ScalarSlot {
   S_SIGMA_PREV,  //   sigma_{j-1}
   S_C1,          //   beta_{j+1} alpha_{j+1} / alpha_j (z update)
   S_C2,          //   alpha_{j+1} delta_{j+1} (z update)
+  S_RE_ERR,      // Reordered BiCGStab (Alg. 6): running bound E of the rho recurrence's rounding
+  S_RE_SH,       //   (r0, r0) of the current shadow vector
   S_D0,  // dot results D0..D6 follow
   S_NSCAL = S_D0 + 7
 };
 // ---- per-column ints ist[slot * kMaxK + c] ------------------------------------
 // I_PEND_NEXT: a stop found while forming the next pass's scalars (Alg. 3),
-// taken when that pass would start.
-enum IntSlot { I_STATUS = 0, I_PEND, I_ITERS, I_ZEROB, I_PEND_NEXT, I_NINT };
+// taken when that pass would start. I_RESTART: the Reordered method restarts
+// this column in the current pass (its r pass also writes the new shadow r0).
+enum IntSlot { I_STATUS = 0, I_PEND, I_ITERS, I_ZEROB, I_PEND_NEXT, I_RESTART, I_NINT };
 // ---- globals -----------------------------------------------------------------
 struct Globals {
   int nrun;      // columns with status RUNNING; every iteration kernel exits at once when 0
@@ -68,7 +71,7 @@ enum FinStep {
   F_OMEGA_BASIC,    // D0=phi D1=psi: omega
   F_CONV_BASIC,     // D2=(r,r): explicit stop test
   F_BETA_END,       // D3=rho': beta, then close the iteration
-  F_RE_OMEGA,       // D0=theta D1=phi D2=psi D3=eta: omega, stop, rho'=-omega psi, beta
+  F_RE_OMEGA,       // D0=theta D1=phi D2=psi D3=eta: omega, stop, rho'=-omega psi, beta, restart test
   F_END,            // close the iteration
   F_PIPE_INIT,      // D0=(r0,w0): alpha_0
   F_PIPE_OMEGA,     // D0=theta D1=phi D2=pi: omega, pi-omega*theta stop test
@@ -134,6 +137,7 @@ enum OpId {
   OP_IB_X,           // Alg. 3 basic: x = x + z + omega s
   OP_F_PP_G2H,       // fused Jacobi, Alg. 7: OP_PP_G2 that also writes zh = z / a_ii
   OP_F_PP_G4H,       // fused Jacobi, Alg. 7: OP_PP_G4 that also writes wh = w / a_ii
+  OP_RE_R,           // Alg. 6: r = rt - omega t; r0 = r for a column that restarts
   OP_NUM
 };
 
@@ -185,9 +189,12 @@ struct Plan {
 bool build_plan(int variant, int formulation, int precond, Plan* plan, std::string* err);
 
 // Static description of every op (for traffic accounting and validation).
+// The last ncond outputs are written only for a column that restarts (a rare
+// event, left out of the per-iteration traffic).
 struct OpInfo {
   int nin, nout, ndot;
   const char* name;
+  int ncond;
 };
 const OpInfo& op_info(int op);
 

@@ -59,6 +59,7 @@ const OpInfo kOps[OP_NUM] = {
     {3, 1, 0, "ib_x"},           // OP_IB_X
     {6, 5, 3, "f_pp_g2h"},       // OP_F_PP_G2H
     {7, 3, 4, "f_pp_g4h"},       // OP_F_PP_G4H
+    {2, 2, 0, "re_r", 1},        // OP_RE_R (r0 written on a restart only)
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -218,7 +219,7 @@ void reordered_fused(int precond, Plan* P) {
   else
     it.push_back(SPMM(V_TH, V_T));
   it.push_back(G(OP_R_G3, {V_R, V_V, V_T, V_R0}, {V_RT}, 0, F_RE_OMEGA));
-  it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));             // r = rt - omega t
+  it.push_back(G(OP_RE_R, {V_RT, V_T}, {V_R, V_R0}));             // r = rt - omega t
   it.push_back(G(OP_R_XZV, {V_X, V_VH, V_TH, V_Q, V_S}, {V_X, V_Z, V_VH}, 0, F_END));
 }
 
@@ -242,7 +243,7 @@ void reordered(int formulation, int precond, Plan* P) {
   if (formulation == 0) {
     it.push_back(G(OP_R_G3, {V_R, V_V, V_T, V_R0}, {V_RT}, 0, F_RE_OMEGA));
     if (jac) it.push_back(PREC(V_T, V_Q));
-    it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));   // r = rt - omega t
+    it.push_back(G(OP_RE_R, {V_RT, V_T}, {V_R, V_R0}));   // r = rt - omega t
     it.push_back(G(OP_R_XZV, {V_X, V_VH, V_TH, V_Q, V_S}, {V_X, V_Z, V_VH}, 0, F_END));
   } else {
     it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));   // rt = r - alpha v
@@ -251,7 +252,7 @@ void reordered(int formulation, int precond, Plan* P) {
     it.push_back(G(OP_DOT, {V_T, V_R0}, {}, 2));         // psi
     it.push_back(G(OP_DOTSELF, {V_RT}, {}, 3, F_RE_OMEGA));  // eta
     if (jac) it.push_back(PREC(V_T, V_Q));
-    it.push_back(G(OP_SUB_OMEGA, {V_RT, V_T}, {V_R}));
+    it.push_back(G(OP_RE_R, {V_RT, V_T}, {V_R, V_R0}));
     it.push_back(G(OP_XUPD, {V_X, V_VH, V_TH}, {V_X}));
     it.push_back(G(OP_SUB_OMEGA, {V_TH, V_Q}, {V_Z}));   // z = th - omega q
     Step s = G(OP_PUPD, {V_Z, V_VH, V_S}, {V_VH}, 0, F_END);  // vh = z + beta (vh - omega s)

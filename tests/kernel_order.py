@@ -137,8 +137,17 @@ def spmm_epilogue_dot(row_ptr, k, block=256, runs_max=256, fin_lanes=16):
     G = max(1, min(nb, runs_max))
     mg = -(-G // fin_lanes)
 
-    def dot(u, w):
-        p = np.multiply(u, w)
+    sizes = np.diff(np.asarray(blk))
+    uniform = nb > 0 and bool(np.all(sizes == sizes[0])) and sizes[0] % rpp == 0
+
+    def block_partials(p):
+        if uniform:
+            # every block holds m whole passes of rpp rows: the same sums as
+            # the loop below, for all blocks at once
+            m = int(sizes[0]) // rpp
+            acc = np.add.accumulate(p.reshape(nb, m, rpp), axis=1)[:, -1, :]
+            wv = _wave_tree(acc.reshape(nb, waves, slots))
+            return np.add.accumulate(wv, axis=1)[:, -1]
         part = np.zeros(nb)
         for L in range(nb):
             r0, r1 = blk[L], blk[L + 1]
@@ -148,6 +157,10 @@ def spmm_epilogue_dot(row_ptr, k, block=256, runs_max=256, fin_lanes=16):
             acc = np.add.accumulate(q.reshape(m, rpp), axis=0)[-1]
             wv = _wave_tree(acc.reshape(waves, slots))
             part[L] = np.add.accumulate(wv)[-1]
+        return part
+
+    def dot(u, w):
+        part = block_partials(np.multiply(u, w))
         runs = np.zeros(mg * fin_lanes)
         for g in range(G):
             b0, b1 = nb * g // G, nb * (g + 1) // G

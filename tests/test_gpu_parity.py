@@ -553,6 +553,61 @@ def test_bitwise_fused_k64_multichunk(lib, variant):
         assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
 
 
+@pytest.mark.parametrize("formulation", ["merged", "basic", "fused"])
+def test_reordered_restart_bitwise(lib, formulation):
+    """Reordered BiCGStab with Jacobi at k = 32 on 24^3 rows, to tol 1e-8:
+    the restart test of the rho recurrence fires (the oracle's trace says
+    where), and the library takes the same restarts: pass counts, statuses,
+    solutions and every pass's alpha, omega, rho and stop estimate equal the
+    oracle's in the kernels' summation order."""
+    import torch
+
+    say(f"reordered restart bitwise {formulation}")
+    A = conv_diff(24, 3, (1.0, 0.7, 0.3))
+    k = 32
+    b, _ = manufactured_rhs(A, k, seed=0)
+    S = A.to_scipy()
+    s = gpu_solver(lib, A, k, "reordered", formulation, "jacobi")
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-8, maxit=500)
+    hist = s.history()
+    X = to_np(x)
+    restarts = 0
+    for c in range(k):
+        tr = []
+        with oracle_dot(fused_dot(A, k, "reordered") if formulation == "fused" else group_dot(A.n, k)):
+            ref = oracle.solve_column(S, b[:, c], None, "reordered", formulation, "jacobi", 1e-8, 500, trace=tr)
+        restarts += sum(bool(t["restart"]) for t in tr)
+        assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), (c, info.iters[c], ref.iters)
+        assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
+        for j, t in enumerate(tr):
+            assert tuple(hist[j, c, :]) == (t["alpha"], t["omega"], t["rho"], t["est"]), (c, j)
+    assert restarts > 0
+    assert np.all(info.status == 0)
+
+
+def test_reordered_restart_full_size(lib):
+    """The column that ran to the pass limit before the restart test existed
+    (128^3 7-point, Jacobi, k = 32, fused Reordered form, column 19): 36
+    passes, with the restart the oracle takes at pass 31, equal bit for bit
+    (iterate and per-pass scalars) to the oracle in the kernels' order."""
+    import torch
+
+    say("reordered restart full size 128^3 k=32 fused, 36 passes")
+    cfg = config_problem(1, seed=0, k=32)
+    A, b = cfg["A"], cfg["b"]
+    s = gpu_solver(lib, A, 32, "reordered", "fused", "jacobi")
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-8, maxit=36)
+    hist = s.history()
+    c = 19
+    tr = []
+    with oracle_dot(fused_dot(A, 32, "reordered")):
+        ref = oracle.solve_column(A.to_scipy(), b[:, c], None, "reordered", "fused", "jacobi", 1e-8, 36, trace=tr)
+    assert any(t["restart"] for t in tr)
+    assert np.array_equal(to_np(x)[:, c], ref.x)
+    for j, t in enumerate(tr):
+        assert tuple(hist[j, c, :]) == (t["alpha"], t["omega"], t["rho"], t["est"]), j
+
+
 # ---------------------------------------------------- full-size checks ---
 
 def test_full_size_cfg1_sampled(lib):

@@ -1,0 +1,52 @@
+"""CPU checks of the summation-order models in kernel_order.py: the
+vectorised path of the product-epilogue dot (row blocks of equal length)
+against a plain loop over blocks, row slots and waves."""
+import numpy as np
+
+from kernel_order import _pad_pow2, _wave_tree, spmm_epilogue_dot, spmm_row_blocks
+from workloads import conv_diff, random_sparse
+
+
+def _loop_epilogue_dot(row_ptr, k, u, w, block=256, runs_max=256, fin_lanes=16):
+    kp = _pad_pow2(k)
+    cpl = 2 if k % 2 == 0 else 1
+    rpp, slots, waves = block * cpl // kp, 64 * cpl // kp, block // 64
+    blk = spmm_row_blocks(row_ptr, k, block)
+    nb = len(blk) - 1
+    p = u * w
+    part = []
+    for L in range(nb):
+        r0, r1 = blk[L], blk[L + 1]
+        slot_sums = np.zeros(rpp)
+        for s in range(rpp):
+            acc = 0.0
+            for r in range(r0 + s, r1, rpp):
+                acc += p[r]
+            slot_sums[s] = acc
+        wave = _wave_tree(slot_sums.reshape(waves, slots))
+        tot = 0.0
+        for x in wave:
+            tot += x
+        part.append(tot)
+    G = max(1, min(nb, runs_max))
+    runs = []
+    for g in range(G):
+        acc = 0.0
+        for b in range(nb * g // G, nb * (g + 1) // G):
+            acc += part[b]
+        runs.append(acc)
+    lanes = [0.0] * fin_lanes
+    for i, v in enumerate(runs):
+        lanes[i % fin_lanes] += v
+    tot = 0.0
+    for v in lanes:
+        tot += v
+    return tot
+
+
+def test_epilogue_dot_uniform_and_ragged_blocks():
+    rng = np.random.default_rng(4)
+    for A, k in ((conv_diff(16, 3, (1.0, 0.7, 0.3)), 32), (conv_diff(16, 3, (1.0, 0.7, 0.3)), 5),
+                 (conv_diff(13, 3, (0.3, 0.2, 0.1)), 32), (random_sparse(3001, 9, seed=1), 8)):
+        u, w = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+        assert spmm_epilogue_dot(A.row_ptr, k)(u, w) == _loop_epilogue_dot(A.row_ptr, k, u, w)
