@@ -112,6 +112,20 @@ def jacobi_preconditioner(A):
     return lambda u: u / d
 
 
+def jacobi_folded_operator(A):
+    """A M^{-1} with M = diag(A), as a CSR matrix: entry (i, j) is
+    a_ij / a_jj (one division per stored entry)."""
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(A)
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    if np.any(d == 0.0):
+        raise ValueError("Jacobi preconditioner: zero diagonal entry")
+    Ah = A.copy()
+    Ah.data = A.data / d[A.indices]
+    return Ah
+
+
 class _Recorder:
     def __init__(self, trace, vectors: bool):
         self.trace = trace
@@ -242,11 +256,18 @@ def alg2_merged_bicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False):
     return ColumnResult(x, r, maxit, MAXIT, trace)
 
 
-def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
+def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False, A_prec=None):
     """Alg. 5: merged preconditioned BiCGStab (p-hat = M^{-1} p, s-hat =
     M^{-1} s). The solution update x += alpha p-hat + omega s-hat does not
     depend on beta; it is formed before the breakdown checks on rho_{j+1} so a
-    column that stops there keeps the pass's x and r updates."""
+    column that stops there keeps the pass's x and r updates.
+
+    A_prec, if given, is the operator A M^{-1} stored as a matrix (possible
+    for a diagonal M): the two products read v = A_prec p and t = A_prec s
+    instead of A (M^{-1} p) and A (M^{-1} s). Alg. 5 preconditions from the
+    right, so the iterates are the same in exact arithmetic; only the
+    rounding of the products differs. p-hat and s-hat are then formed for the
+    solution update alone."""
     rec = _Recorder(trace, trace_vectors)
     early, x, r, rho, eps2 = _begin(A, b, x0, tol)
     if early is not None:
@@ -255,7 +276,7 @@ def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     p = r.copy()
     for j in range(maxit):
         ph = Minv(p)
-        v = A @ ph
+        v = A @ ph if A_prec is None else A_prec @ p
         delta = dot(v, r0)
         if delta == 0.0:
             return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
@@ -264,7 +285,7 @@ def alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
             return ColumnResult(x, r, j + 1, NONFINITE, trace)
         s = r - alpha * v
         sh = Minv(s)
-        t = A @ sh
+        t = A @ sh if A_prec is None else A_prec @ s
         phi, psi, theta = dot(t, s), dot(t, t), dot(s, s)
         omega = phi / psi if psi != 0.0 else 0.0
         est = theta - omega * phi
@@ -566,7 +587,9 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     explicit residual-norm stop test. The fused form (a single-device
     regrouping of the merged statements: dots formed in the sparse products'
     epilogues, the Jacobi division done by the pass that produces the vector)
-    computes the merged listing's statements, so it maps to that listing."""
+    computes the merged listing's statements, so it maps to that listing;
+    for the classical method with Jacobi it folds M^{-1} into the products
+    (Alg. 5 with A M^{-1} stored as a matrix)."""
     import scipy.sparse as sp
 
     A = sp.csr_matrix(A)
@@ -574,7 +597,8 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     x0 = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64)
     if variant not in VARIANTS or formulation not in FORMULATIONS or precond not in PRECONDS:
         raise ValueError(f"unknown method {variant}/{formulation}/{precond}")
-    if formulation == "fused":
+    fused = formulation == "fused"
+    if fused:
         formulation = "merged"
     if variant == "improved":
         # Alg. 3; its basic form runs the same statements one per pass
@@ -591,6 +615,9 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
             return alg1_bicgstab(A, b, x0, tol, maxit, Minv if precond == "jacobi" else None, **kw)
         if precond == "none":
             return alg2_merged_bicgstab(A, b, x0, tol, maxit, **kw)
+        if fused:
+            # the fused form folds Jacobi into the products: A M^{-1} as a matrix
+            return alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, A_prec=jacobi_folded_operator(A), **kw)
         return alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, **kw)
     if variant == "reordered":
         return alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, **kw)

@@ -17,6 +17,10 @@ from workloads import conv_diff, manufactured_rhs, random_sparse
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
+# the fused classical form with Jacobi folds M^{-1} into the products (A M^{-1}
+# as a matrix), a rounding-level change of Alg. 5; the other fused forms run
+# the merged listing
+METHODS += [("classical", "fused", "jacobi")]
 
 
 def _tiny_systems():
@@ -178,6 +182,23 @@ def test_reordered_restart_test_bounds_the_drift(monkeypatch):
         if rs:
             break
         assert abs(rho - true) <= 4 * ob.U64 * tr[i]["err"]
+
+
+def test_jacobi_folded_operator():
+    """A M^{-1} with M = diag(A): entry (i, j) is a_ij / a_jj, and the
+    product with p equals A (M^{-1} p) up to one rounding per term."""
+    A = conv_diff(9, 3, (1.0, -0.7, 0.3)).to_scipy()
+    A.data = A.data * np.random.default_rng(3).uniform(0.5, 2.0, A.nnz)
+    Ah = ob.jacobi_folded_operator(A)
+    d = A.diagonal()
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    for e in np.random.default_rng(4).choice(A.nnz, 50, replace=False):
+        i, j = rows[e], A.indices[e]
+        assert Ah[i, j] == A[i, j] / d[j]
+    p = np.random.default_rng(5).uniform(-1, 1, A.shape[0])
+    ref = A @ (p / d)
+    bound = 4 * np.finfo(float).eps * (abs(A) @ abs(p / d))
+    assert np.all(np.abs(Ah @ p - ref) <= bound)
 
 
 def test_pipelined_auxiliary_vectors():
