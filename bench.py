@@ -60,7 +60,7 @@ OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
     "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g1", "pp_g2", "pp_g3", "pp_g4",
     "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h", "ib_init", "ib_g1", "ib_g2",
-    "ib_g3", "ib_z", "ib_v", "ib_x", "f_pp_g2h", "f_pp_g4h", "re_r",
+    "ib_g3", "ib_z", "ib_v", "ib_x", "f_pp_g2h", "f_pp_g4h", "re_r", "f_xr_rho_d",
 ]
 
 
@@ -134,33 +134,47 @@ def roofline_of(solver, b, n, nnz, k, iters=10):
     return roof, kernels, it_summary
 
 
-def kernel_source_sha():
-    """Hash of the kernel sources and of the files that fix their launch
-    shapes and plans; counter-derived traffic is reported only for the source
-    it was measured on."""
+# Sources that define each kernel family's code and launch shape: counter
+# traffic is reported for a kernel only while these are unchanged.
+KERNEL_SOURCES = {
+    "spmm": ("spmm.hip", "internal.hpp", "reduce.hpp", "plan.hpp"),
+    "vector": ("kernels.hip", "method.hpp", "reduce.hpp", "internal.hpp", "plan.hpp", "plans.cpp", "api.hip"),
+}
+
+
+def kernel_family(kernel):
+    return "spmm" if kernel.startswith(("spmm", "reduce_runs")) else "vector"
+
+
+def kernel_source_sha(family="spmm"):
+    """Hash of the sources of a kernel family (KERNEL_SOURCES)."""
     import hashlib
 
     h = hashlib.sha256()
-    for fn in ("spmm.hip", "kernels.hip", "method.hpp", "reduce.hpp", "api.hip", "plans.cpp", "plan.hpp",
-               "internal.hpp"):
+    for fn in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_1907_12874_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, k):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
-    copy of known size), or None if absent or taken on other kernel sources."""
+def traffic_key(grid, k, variant, formulation, precond):
+    return f"convdiff{grid}_k{k}_{variant}_{formulation}_{precond}"
+
+
+def measured_traffic(kernel, key):
+    """HBM bytes per launch of `kernel` on workload `key` from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain 1 GiB copy in the same run), or None if absent or
+    taken on other sources of that kernel."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_sha") != kernel_source_sha() or d.get("k") != k:
+    ent = d.get("workloads", {}).get(key, {}).get("kernels", {}).get(kernel)
+    if ent is None or ent.get("source_sha") != kernel_source_sha(kernel_family(kernel)):
         return None
-    ent = d.get("kernels", {}).get(kernel)
-    return None if ent is None else ent.get("hbm_bytes_per_launch")
+    return ent.get("hbm_bytes_per_launch")
 
 
 def copy_probe(reps=5):
@@ -734,6 +748,9 @@ def compose_line(rep):
                                             if any(f"{v}_k{kk}" in f for kk in ks)}))
         bad = [f"{r['variant']}/{r['formulation']}/k{r['k']}" for r in rep.get("sweep", []) if not r["equal_accuracy"]]
         opt.append(("sweep_unequal_accuracy", bad))
+        gap = {f"{r['variant'][:4]}/{r['formulation']}/k{r['k']}": r["solve_passes_vs_merged"]
+               for r in rep.get("sweep", []) if abs(r.get("solve_passes_vs_merged", 1.0) - 1.0) > 0.05}
+        opt.append(("sweep_solve_pass_gap", gap))
     if "small_2d" in rep:
         sm = rep["small_2d"]
         opt.append(("small_2d", {**{f"{r['variant'][:4]}_{r['formulation']}": [r["us_per_iter"], r["launches_per_iter"],
@@ -780,15 +797,29 @@ def compose_line(rep):
     return line
 
 
-def profile_run(pk, dev, what, maxit):
-    """One tier workload after a warm-up, for the tier kernel traces under
-    rocprofv3: the precision tier's matrix solved in FP64 or FP32 + FP64
-    refinement, or the batched tier's 64 systems (autotuned, then solved)."""
+def profile_run(pk, dev, what, maxit, k=32):
+    """One workload after a warm-up, for kernel traces and counter runs under
+    rocprofv3 (after the 1 GiB device copy that calibrates the byte
+    counters): the precision tier's matrix solved in FP64 or FP32 + FP64
+    refinement, the batched tier's 64 systems (autotuned, then solved), or
+    the random sparse matrix (n = 2^21, 15 random columns per row) at k
+    right-hand sides, classical merged with Jacobi, `maxit` fixed passes."""
     import torch
 
     from workloads import config_problem
 
-    if what in ("fp64", "fp32_refine"):
+    copy_probe(reps=1)
+    if what == "random":
+        from workloads import manufactured_rhs, random_sparse
+
+        A = random_sparse(2**21, 15, seed=0)
+        b = torch.from_numpy(np.ascontiguousarray(manufactured_rhs(A, k, seed=0)[0])).to(dev)
+        s = pk.Solver.from_csr(A, k, variant="classical", formulation="merged", precond="jacobi", device=dev)
+        s.solve(b, tol=0.0, maxit=2)
+        t, _ = timed(lambda: s.solve(b, tol=0.0, maxit=maxit))
+        print("random sparse k", k, "ms", round(t * 1e3, 2), "passes", maxit, flush=True)
+        s.close()
+    elif what in ("fp64", "fp32_refine"):
         cfg = config_problem(2, seed=0)
         b = torch.from_numpy(cfg["b"]).to(dev)
         s = pk.Solver.from_csr(cfg["A"], cfg["k"], precision=what, device=dev)
@@ -827,9 +858,9 @@ def main():
     ap.add_argument("--no-seeds", action="store_true", help="skip the headline solve on input seeds 1 and 2")
     ap.add_argument("--report", default=os.path.join(ROOT, "gpurun_out", "bench_report.json"),
                     help="where the full report goes (JSON); stdout gets one compact line")
-    ap.add_argument("--profile-run", choices=("fp64", "fp32_refine", "batched"),
-                    help="run one tier workload after a warm-up and exit without the JSON line (the command "
-                         "behind the tier kernel traces)")
+    ap.add_argument("--profile-run", choices=("fp64", "fp32_refine", "batched", "random"),
+                    help="run one workload after a warm-up and exit without the JSON line (the command behind "
+                         "the tier kernel traces and the counter runs; 'random' takes --k and --maxit passes)")
     ap.add_argument("--sweep-passes", type=int, default=20)
     ap.add_argument("--no-host", action="store_true", help="skip the host-CPU Table 4 section")
     ap.add_argument("--host-grid", type=int, default=160)
@@ -855,7 +886,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.profile_run:
-        profile_run(pk, dev, args.profile_run, min(args.maxit, 3000))
+        profile_run(pk, dev, args.profile_run, min(args.maxit, 3000), k=args.k)
         return
     copy_gbps = copy_probe()
     print(f"# plain 1 GiB device copy: {copy_gbps} GB/s (read + write)", file=sys.stderr, flush=True)
@@ -923,8 +954,9 @@ def main():
 
     if not args.no_roofline:
         roof, kernels, it_summary = roofline_of(s, b, n, nnz, k)
-        roof["traffic"] = measured_traffic(roof["kernel"], k)
-        roof["source_sha"] = kernel_source_sha()
+        roof["traffic"] = measured_traffic(roof["kernel"],
+                                           traffic_key(args.grid, k, args.variant, args.formulation, args.precond))
+        roof["source_sha"] = kernel_source_sha(kernel_family(roof["kernel"]))
         out["roofline"] = roof
         out["kernels"] = kernels
         out["iteration"] = it_summary
@@ -986,6 +1018,15 @@ def main():
                           f"{row['solve_iters_max']} it", file=sys.stderr, flush=True)
                     sv.close()
                     del sv
+        # A solve's time also depends on how many passes it took, and forms
+        # that differ only in rounding order stop at different pass counts
+        # (BiCGStab amplifies summation-order differences near the
+        # tolerance): flag each form's solve pass count against the merged
+        # form's, so solve times are not read as per-pass speed.
+        for r in sweep:
+            m = [q for q in sweep if q["k"] == r["k"] and q["variant"] == r["variant"] and q["formulation"] == "merged"]
+            if m and m[0]["solve_iters_max"] > 0:
+                r["solve_passes_vs_merged"] = round(r["solve_iters_max"] / m[0]["solve_iters_max"], 3)
         out["sweep"] = sweep
         gains, fusion = {}, {}
         for kk in ks:

@@ -30,7 +30,8 @@
  *     when the handle was created. The library borrows them: it never frees
  *     or retains them beyond the call, except the matrix arrays, which must
  *     stay valid and unchanged (except through bicgstab_update_values) for the
- *     lifetime of the handle.
+ *     lifetime of the handle (or, for the values, until bicgstab_update_values
+ *     hands the handle another array).
  *   - Work is enqueued on the handle's HIP stream. bicgstab_solve* return after
  *     the stream has finished the solve (they synchronise the stream).
  *   - Return value: BICGSTAB_OK (0) or a negative error code; a failed call
@@ -174,9 +175,16 @@ int bicgstab_solve_transpose(bicgstab_t h, const double* d_g, double* d_lambda, 
  * (the derivative of A^{-1} B restricted to the sparsity pattern). */
 int bicgstab_grad_values(bicgstab_t h, const double* d_lambda, const double* d_x, double* d_grad);
 
-/* Tell the handle that the values behind A->d_values changed (same pattern):
- * refreshes the diagonal, the FP32 copy and the transposed values. */
-int bicgstab_update_values(bicgstab_t h);
+/* New matrix values, same sparsity pattern (the differentiation tier's
+ * A(values)): d_values == NULL means the caller changed the values array the
+ * handle borrows in place; otherwise the handle borrows d_values (nnz FP64
+ * entries in the pattern's CSR order, device memory that must stay valid and
+ * unchanged until the next update or the handle's end) instead of the array
+ * given before. Refreshes what derives from the values on the handle's
+ * stream (Jacobi diagonal, FP32 copy, transposed values); returns after it has
+ * finished. A zero diagonal under Jacobi gives BICGSTAB_EINVAL (the handle
+ * keeps the new values; update again before solving). */
+int bicgstab_update_values(bicgstab_t h, const double* d_values);
 
 /* Y = A X (n x k, row-major) with the solver's sparse-product kernel, on the
  * handle's stream, asynchronous. For kernel-level checks and timing. */

@@ -64,7 +64,7 @@ def lib():
     L.bicgstab_solve_noalloc.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
     L.bicgstab_solve_transpose.argtypes = [H, vp, vp, dbl, i32, C.POINTER(Info)]
     L.bicgstab_grad_values.argtypes = [H, vp, vp, vp]
-    L.bicgstab_update_values.argtypes = [H]
+    L.bicgstab_update_values.argtypes = [H, C.c_void_p]
     L.bicgstab_spmm.argtypes = [H, vp, vp]
     L.bicgstab_history.argtypes = [H, C.POINTER(dbl), i32, C.POINTER(i32)]
     L.bicgstab_last_solve_stats.argtypes = [H, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]

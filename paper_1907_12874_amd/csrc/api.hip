@@ -90,6 +90,8 @@ struct bicgstab_ctx {
   double* diag = nullptr;
   float* diag32 = nullptr;
   float* val32 = nullptr;
+  double* val_fold = nullptr;   // A M^{-1} (Jacobi folded into the values) for plans that use it
+  float* val_fold32 = nullptr;  //   the same in FP32 (refinement tier)
   int32_t* blk = nullptr;
   double* partials = nullptr;
   double* bpart = nullptr;    // row-block partials of products with a dot epilogue
@@ -117,6 +119,7 @@ struct bicgstab_ctx {
   int32_t* perm_t = nullptr;
   double* val_t = nullptr;
   float* val32_t = nullptr;
+  double* val_fold_t = nullptr;  // A^T M^{-1} (folded Jacobi on the transposed matrix)
   int32_t* blk_t = nullptr;
   SpmmPartition part_t;  // row blocks of the product with A^T
   std::vector<GraphEntry> graphs;
@@ -135,6 +138,14 @@ bool has_spmm_t(const bicgstab_ctx* h) {
   for (const auto* list : {&h->plan.init, &h->plan.iter})
     for (const Step& st : *list)
       if (st.kind == K_SPMM_T) return true;
+  return false;
+}
+
+// The plan has products with the Jacobi-folded matrix A M^{-1}.
+bool has_fold(const bicgstab_ctx* h) {
+  for (const auto* list : {&h->plan.init, &h->plan.iter})
+    for (const Step& st : *list)
+      if (st.fold) return true;
   return false;
 }
 
@@ -169,6 +180,7 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_diag = take((size_t)h->n * 8);
   const size_t o_diag32 = take(fp32_inner(h) ? (size_t)h->n * 4 : 0);
   const size_t o_val32 = take(fp32_inner(h) ? (size_t)h->nnz * 4 : 0);
+  const size_t o_vfold = take(has_fold(h) ? (size_t)h->nnz * elem : 0);
   const size_t o_blk = take(h->part.blk.size() * 4);
   const size_t o_part = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
   const size_t o_bpart = take(has_spmm_dot(h) ? (h->part.blk.size() - 1) * 3 * (size_t)h->k * 8 : 0);
@@ -185,6 +197,8 @@ size_t layout(bicgstab_ctx* h, bool assign) {
     h->diag = (double*)(b + o_diag);
     h->diag32 = fp32_inner(h) ? (float*)(b + o_diag32) : nullptr;
     h->val32 = fp32_inner(h) ? (float*)(b + o_val32) : nullptr;
+    h->val_fold = has_fold(h) && !fp32_inner(h) ? (double*)(b + o_vfold) : nullptr;
+    h->val_fold32 = has_fold(h) && fp32_inner(h) ? (float*)(b + o_vfold) : nullptr;
     h->blk = (int32_t*)(b + o_blk);
     h->partials = (double*)(b + o_part);
     h->bpart = has_spmm_dot(h) ? (double*)(b + o_bpart) : nullptr;
@@ -236,6 +250,7 @@ int prepare(bicgstab_ctx* h) {
                                        " zero diagonal entries");
   }
   if (fp32_inner(h)) HIPCHK(launch_convert_f32(h->val, h->val32, h->nnz, h->ws));
+  if (has_fold(h)) HIPCHK(launch_fold_jacobi(h->col, h->val, h->diag, h->val_fold, h->val_fold32, h->nnz, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   if (has_spmm_t(h) && h->n > 0) {
     const int rc = build_transpose(h);
@@ -245,13 +260,17 @@ int prepare(bicgstab_ctx* h) {
   return BICGSTAB_OK;
 }
 
-SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
+// which: 0 = A, 1 = A^T; fold: the Jacobi-folded values (A M^{-1}, A^T M^{-1}).
+SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32, bool fold = false) {
   SpmmMat m;
   m.n = (int)h->n;
   if (which == 0) {
     m.row_ptr = h->row_ptr;
     m.col = h->col;
-    m.val = fp32 ? (const void*)h->val32 : (const void*)h->val;
+    if (fold)
+      m.val = fp32 ? (const void*)h->val_fold32 : (const void*)h->val_fold;
+    else
+      m.val = fp32 ? (const void*)h->val32 : (const void*)h->val;
     m.blk = h->blk;
     m.nblk = (int)h->part.blk.size() - 1;
     m.xcd_chunk = h->spmm_xcd_chunk;
@@ -261,7 +280,10 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
   } else {
     m.row_ptr = h->rp_t;
     m.col = h->col_t;
-    m.val = fp32 ? (const void*)h->val32_t : (const void*)h->val_t;
+    if (fold)
+      m.val = fp32 ? nullptr : (const void*)h->val_fold_t;
+    else
+      m.val = fp32 ? (const void*)h->val32_t : (const void*)h->val_t;
     m.blk = h->blk_t;
     m.nblk = (int)h->part_t.blk.size() - 1;
     m.xcd_chunk = h->spmm_xcd_chunk;
@@ -272,9 +294,12 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32) {
   return m;
 }
 
-hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M, void* const* vp, const Ctl& ctl,
+hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void* const* vp, const Ctl& ctl,
                        bool fp32, hipStream_t s, bool early_exit = true) {
   const Globals* g = early_exit ? h->glob : nullptr;
+  // a product of the Jacobi-folded form reads A M^{-1} (of the same matrix, A or A^T)
+  const SpmmMat M = st.fold ? mat_of(h, M0.blk == h->blk ? 0 : 1, fp32, true) : M0;
+  if (st.fold && !M.val) return hipErrorInvalidValue;
   switch (st.kind) {
     case K_SPMM:
       return launch_spmm(M, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
@@ -587,6 +612,11 @@ int build_transpose(bicgstab_ctx* h) {
   HIPCHK(launch_transpose_fill(h->row_ptr, h->col, n, h->rp_t, counts, h->col_t, h->perm_t, h->ws));
   HIPCHK(launch_transpose_sort_rows(h->rp_t, h->col_t, h->perm_t, n, h->ws));
   HIPCHK(launch_gather_values(h->val, h->perm_t, h->val_t, nnz, h->ws));
+  if (has_fold(h)) {
+    // A^T M^{-1}: M = diag(A) is also the diagonal of A^T
+    HIPCHK(alloc((void**)&h->val_fold_t, (size_t)nnz * 8));
+    HIPCHK(launch_fold_jacobi(h->col_t, h->val_t, h->diag, h->val_fold_t, nullptr, nnz, h->ws));
+  }
   std::vector<int32_t> rp((size_t)n + 1);
   HIPCHK(hipMemcpyAsync(rp.data(), h->rp_t, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
@@ -811,9 +841,17 @@ int bicgstab_grad_values(bicgstab_t h, const double* d_lambda, const double* d_x
   return BICGSTAB_OK;
 }
 
-int bicgstab_update_values(bicgstab_t h) {
+int bicgstab_update_values(bicgstab_t h, const double* d_values) {
   if (!h) return fail(BICGSTAB_EINVAL, "null handle");
+  if (d_values && h->nnz > 0 && ((uintptr_t)d_values % alignof(double)) != 0)
+    return fail(BICGSTAB_EINVAL, "values must be 8-byte aligned");
   HIPCHK(hipSetDevice(h->device));
+  if (d_values && d_values != h->val) {
+    // captured iteration graphs hold the old array's address
+    HIPCHK(hipStreamSynchronize(h->ws));
+    clear_graphs(h);
+    h->val = d_values;
+  }
   int rc = begin_on_internal_stream(h);
   if (rc) return rc;
   h->prepared = false;
@@ -821,6 +859,7 @@ int bicgstab_update_values(bicgstab_t h) {
   if (rc) return rc;
   if (h->have_t) {
     HIPCHK(launch_gather_values(h->val, h->perm_t, h->val_t, h->nnz, h->ws));
+    if (h->val_fold_t) HIPCHK(launch_fold_jacobi(h->col_t, h->val_t, h->diag, h->val_fold_t, nullptr, h->nnz, h->ws));
     HIPCHK(hipStreamSynchronize(h->ws));
   }
   return BICGSTAB_OK;
@@ -926,7 +965,7 @@ int bicgstab_destroy(bicgstab_t h) {
   clear_graphs(h);
   if (h->owned && h->base) hipFree(h->base);
   for (void* p : {(void*)h->rp_t, (void*)h->col_t, (void*)h->perm_t, (void*)h->val_t, (void*)h->val32_t,
-                  (void*)h->blk_t, (void*)h->bpart_t})
+                  (void*)h->val_fold_t, (void*)h->blk_t, (void*)h->bpart_t})
     if (p) hipFree(p);
   for (void* p : {(void*)h->h_blk, (void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
     if (p) hipHostFree(p);

@@ -62,10 +62,15 @@ struct BGlob {
 // barrier with ordinal e completes when the counter reaches (e + 1) * nw.
 // Every wave first waits for its own stores to complete, then one thread
 // releases at agent scope, arrives, waits and acquires. Returns false on abort.
-__device__ bool sys_barrier(unsigned* bar, unsigned target, int* abort_flag, long long wait_ticks) {
+// A system on a single workgroup needs only the workgroup barrier: its waves
+// share one compute unit and its L1, so a workgroup-scope release / acquire
+// (__syncthreads) orders their global stores and loads, and no agent-scope
+// fence (which writes back the L2) or counter is needed.
+__device__ bool sys_barrier(unsigned* bar, unsigned target, int* abort_flag, long long wait_ticks, int nw) {
   __shared__ int s_ok;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (nw == 1) return true;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   __shared__ int st[kMaxK], pend[kMaxK], iters[kMaxK], zerob[kMaxK];
   __shared__ int nrun;
   unsigned epoch = 0;
-  auto barrier = [&]() { return sys_barrier(S.bar, (++epoch) * (unsigned)S.nw, G.abort_flag, G.wait_ticks); };
+  auto barrier = [&]() { return sys_barrier(S.bar, (++epoch) * (unsigned)S.nw, G.abort_flag, G.wait_ticks, S.nw); };
   // element offsets fit in 32 bits (checked at create): uniform base + 32-bit offset addressing
   auto eidx = [&](int row) { return (unsigned)(row * k + c); };
   if (w == 0 && threadIdx.x == 0) S.clk[0] = wall_clock64();

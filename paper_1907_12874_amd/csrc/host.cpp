@@ -43,6 +43,7 @@ struct bicgstab_host_ctx {
   int threads = 1;
   std::vector<int32_t> rp, col;
   std::vector<double> val;
+  std::vector<double> val_fold;  // A M^{-1} (Jacobi folded into the values), when a plan step needs it
   std::vector<int32_t> rpt, colt;  // A^T (Improved BiCGStab's f0 = A^T r0)
   std::vector<double> valt;
   std::vector<double> diag;
@@ -115,8 +116,10 @@ void spmm(const Ctx& h, const std::vector<int32_t>& rp, const std::vector<int32_
 
 // The product with an epilogue: the dots (y, w), or (y, w), (y, y), (w, w),
 // and / or the Jacobi-scaled copy yh = y / a_ii.
-void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, int epi, int slot, int fin) {
+void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, int epi, int slot, int fin,
+              bool fold) {
   const int k = h.k;
+  const std::vector<double>& val = fold ? h.val_fold : h.val;
   const int nd = epilogue_dots(epi);
   const bool scaled = epilogue_prec(epi);
   for_ranges(h, [&](int t, int64_t r0, int64_t r1) {
@@ -126,7 +129,7 @@ void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, i
     for (int64_t i = r0; i < r1; ++i) {
       for (int c = 0; c < k; ++c) acc[c] = 0.0;
       for (int32_t e = h.rp[i]; e < h.rp[i + 1]; ++e) {
-        const double a = h.val[e];
+        const double a = val[e];
         const double* xr = X + (size_t)h.col[e] * k;
         for (int c = 0; c < k; ++c) acc[c] += a * xr[c];
       }
@@ -255,6 +258,7 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_F_PP_G2H, KPPG2H)
     G(OP_F_PP_G4H, KPPG4H)
     G(OP_RE_R, KReR)
+    G(OP_F_XR_RHO_D, KFXrRhoD)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }
@@ -263,11 +267,11 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
 int run_step(Ctx& h, const Step& st, double* const* vp, bool early_exit = true) {
   if (early_exit && h.glob.nrun == 0 && st.kind != K_GROUP) return BICGSTAB_OK;
   switch (st.kind) {
-    case K_SPMM: spmm(h, h.rp, h.col, h.val, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
+    case K_SPMM: spmm(h, h.rp, h.col, st.fold ? h.val_fold : h.val, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
     case K_SPMM_T: spmm(h, h.rpt, h.colt, h.valt, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
     case K_SPMM_DOT:
       spmm_dot(h, vp[st.in[0]], vp[st.out[0]], epilogue_dots(st.op) > 0 ? vp[st.in[1]] : nullptr,
-               epilogue_prec(st.op) ? vp[st.out[1]] : nullptr, st.op, st.slot, st.fin);
+               epilogue_prec(st.op) ? vp[st.out[1]] : nullptr, st.op, st.slot, st.fin, st.fold != 0);
       return BICGSTAB_OK;
     case K_PREC: prec(h, vp[st.in[0]], vp[st.out[0]]); return BICGSTAB_OK;
     case K_GROUP: return run_group(h, st, vp);
@@ -344,9 +348,17 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
     if (precond == BICGSTAB_PRECOND_JACOBI && zero > 0)
       return fail(BICGSTAB_EINVAL, "Jacobi preconditioner: " + std::to_string(zero) + " zero diagonal entries");
   }
-  bool need_t = false;
+  bool need_t = false, need_fold = false;
   for (const auto* list : {&h->plan.init, &h->plan.iter})
-    for (const Step& s : *list) need_t |= s.kind == K_SPMM_T;
+    for (const Step& s : *list) {
+      need_t |= s.kind == K_SPMM_T;
+      need_fold |= s.fold != 0;
+    }
+  if (need_fold) {
+    // A M^{-1}: entry (i, j) is a_ij / a_jj
+    h->val_fold.resize(h->val.size());
+    for (size_t e = 0; e < h->val.size(); ++e) h->val_fold[e] = h->val[e] / h->diag[h->col[e]];
+  }
   if (need_t) build_transpose(*h);
   const size_t nk = (size_t)n * k;
   for (int v : h->plan.vecs) {

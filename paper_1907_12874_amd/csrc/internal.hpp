@@ -64,6 +64,10 @@ hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
 hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,
                                float* diag32, int n, Globals* glob, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t s);
+// a_ij / a_jj for every stored entry (Jacobi folded into the matrix), into
+// out64 and / or out32
+hipError_t launch_fold_jacobi(const int32_t* col, const double* val, const double* diag, double* out64, float* out32,
+                              int64_t nnz, hipStream_t s);
 // The three runs of Table 1's vector updates (1: three passes, 2: two updates
 // merged, 3: three updates merged).
 hipError_t launch_axpby(int run, const double* x, double* y, double* z, long n, double a, double b, double c,

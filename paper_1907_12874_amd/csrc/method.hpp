@@ -133,6 +133,17 @@ struct KCXrRho {  // in: x, p, s, t, r0 ; out: x, r
     a[0] += r * v[4];
   }
 };
+struct KFXrRhoD {  // folded Jacobi: in: x, p, s, t, r0 (+ a_ii) ; out: x, r ; dot (r, r0)
+  OP_HEAD_D(5, 2, 1, 1, 1, PART_RUN, true)
+  OP_F {
+    const double ph = R(v[1] / v[5]);
+    const double sh = R(v[2] / v[5]);
+    o[0] = v[0] + c.alpha * ph + c.omega * sh;
+    const double r = R(v[2] - c.omega * v[3]);
+    o[1] = r;
+    a[0] += r * v[4];
+  }
+};
 struct KReR {  // Alg. 6: in: rt, t ; out: r = rt - omega t, and r0 = r where the column restarts
   OP_HEAD_C(2, 2, 0, 0, 0, PART_RUN, true, false, 2u)
   OP_F {

@@ -138,6 +138,7 @@ enum OpId {
   OP_F_PP_G2H,       // fused Jacobi, Alg. 7: OP_PP_G2 that also writes zh = z / a_ii
   OP_F_PP_G4H,       // fused Jacobi, Alg. 7: OP_PP_G4 that also writes wh = w / a_ii
   OP_RE_R,           // Alg. 6: r = rt - omega t; r0 = r for a column that restarts
+  OP_F_XR_RHO_D,     // folded Jacobi, Alg. 5: x += alpha p / a_ii + omega s / a_ii; r = s - omega t; dot (r, r0)
   OP_NUM
 };
 
@@ -175,6 +176,7 @@ struct Step {
   int slot;      // first dot slot written
   int fin;       // FinStep
   int nin, nout; // vector reads / writes of the pass (traffic accounting)
+  int fold;      // products: 1 = with A M^{-1} (Jacobi folded into the values), 0 = with A
 };
 
 struct Plan {

@@ -60,6 +60,7 @@ const OpInfo kOps[OP_NUM] = {
     {6, 5, 3, "f_pp_g2h"},       // OP_F_PP_G2H
     {7, 3, 4, "f_pp_g4h"},       // OP_F_PP_G4H
     {2, 2, 0, "re_r", 1},        // OP_RE_R (r0 written on a restart only)
+    {5, 2, 1, "f_xr_rho_d"},     // OP_F_XR_RHO_D (+ the diagonal)
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -96,6 +97,13 @@ Step SPMM_DOT(int x, int y, int epi, int w, int slot, int fin) {
   return s;
 }
 
+// The same with the Jacobi-folded matrix: y = (A M^{-1}) x.
+Step SPMM_DOT_FOLD(int x, int y, int epi, int w, int slot, int fin) {
+  Step s = SPMM_DOT(x, y, epi, w, slot, fin);
+  s.fold = 1;
+  return s;
+}
+
 // Sparse product y = A x that also writes yh = y / a_ii, with the dot
 // (y, w) in its epilogue when w is given.
 Step SPMM_PREC(int x, int y, int yh, int w = V_NONE, int slot = 0, int fin = F_NONE) {
@@ -124,37 +132,34 @@ Step PREC(int in, int out) {
 // Fused form (one device, beyond the paper's grouping): the same statements as
 // Alg. 2 / Alg. 5 in five launches and their finalize kernels:
 //   v = A ph with delta = (v, r0) in the product's epilogue;
-//   s = r - alpha v (and sh = s / a_ii);
+//   s = r - alpha v;
 //   t = A sh with phi = (t, s), psi = (t, t), theta = (s, s) in the epilogue;
 //   x += alpha ph + omega sh, r = s - omega t, rho' = (r, r0);
-//   p = r + beta (p - omega v) (and ph = p / a_ii).
-// With Jacobi the pass that makes p or s also writes its preconditioned copy,
-// so no separate preconditioner pass reads it back.
+//   p = r + beta (p - omega v).
+// With Jacobi the preconditioner is folded into the products: Alg. 5
+// preconditions from the right, so v = A (M^{-1} p) = (A M^{-1}) p, and with a
+// diagonal M the matrix A M^{-1} (entries a_ij / a_jj) is formed once. The
+// products then read p and s themselves, ph = p / a_ii and sh = s / a_ii are
+// formed inside the solution-update pass, and no ph or sh block is written
+// or read back.
 void classical_fused(int precond, Plan* P) {
   const bool jac = precond == 1;
-  const int ph = jac ? V_PH : V_P;
-  const int sh = jac ? V_SH : V_S;
   P->init = {SPMM(V_X, V_V), G(OP_INIT_P, {V_B, V_V}, {V_R, V_R0, V_P}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
-  if (jac) P->init.push_back(PREC(V_P, V_PH));
   auto& it = P->iter;
-  it.push_back(SPMM_DOT(ph, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
   if (jac)
-    it.push_back(G(OP_F_SUB_ALPHA_H, {V_R, V_V}, {V_S, V_SH}));
+    it.push_back(SPMM_DOT_FOLD(V_P, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
   else
-    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_S}));
-  it.push_back(SPMM_DOT(sh, V_T, E_PPT, V_S, 0, F_OMEGA_MERGED));
+    it.push_back(SPMM_DOT(V_P, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
+  it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_S}));
   if (jac) {
-    it.push_back(G(OP_F_XR_RHO_H, {V_X, V_PH, V_SH, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
-    it.push_back(G(OP_F_PUPD_H, {V_R, V_P, V_V}, {V_P, V_PH}));
+    it.push_back(SPMM_DOT_FOLD(V_S, V_T, E_PPT, V_S, 0, F_OMEGA_MERGED));
+    it.push_back(G(OP_F_XR_RHO_D, {V_X, V_P, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
   } else {
+    it.push_back(SPMM_DOT(V_S, V_T, E_PPT, V_S, 0, F_OMEGA_MERGED));
     it.push_back(G(OP_C_XR_RHO, {V_X, V_P, V_S, V_T, V_R0}, {V_X, V_R}, 3, F_BETA_END));
-    it.push_back(G(OP_PUPD, {V_R, V_P, V_V}, {V_P}));
   }
+  it.push_back(G(OP_PUPD, {V_R, V_P, V_V}, {V_P}));
   P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T};
-  if (jac) {
-    P->vecs.push_back(V_PH);
-    P->vecs.push_back(V_SH);
-  }
 }
 
 void classical(int formulation, int precond, Plan* P) {

@@ -136,11 +136,14 @@ struct DotEpilogue {
       store_y<T, CPL>(Yh, row, k, c, yh);
     }
     if constexpr (epilogue_dots(EPI) > 0) {
+      // the epilogue's operand block is read once: nontemporal, as in the
+      // vector passes
       T w[CPL];
       if constexpr (CPL == 1) {
-        w[0] = W[(size_t)row * k + c];
+        w[0] = __builtin_nontemporal_load(W + (size_t)row * k + c);
       } else {
-        const typename VecOf<T, CPL>::type t = *(const typename VecOf<T, CPL>::type*)(W + (size_t)row * k + c);
+        const typename VecOf<T, CPL>::type t =
+            __builtin_nontemporal_load((const typename VecOf<T, CPL>::type*)(W + (size_t)row * k + c));
 #pragma unroll
         for (int h = 0; h < CPL; ++h) w[h] = t[h];
       }

@@ -168,7 +168,8 @@ class Solver:
         self.values.copy_(v)
         with torch.cuda.device(self.device):
             self._set_stream()
-            check(lib().bicgstab_update_values(self._h), "bicgstab_update_values")
+            check(lib().bicgstab_update_values(self._h, C.c_void_p(self.values.data_ptr())),
+                  "bicgstab_update_values")
         self.values_version += 1
 
     def spmm(self, X, out=None):

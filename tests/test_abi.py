@@ -117,18 +117,19 @@ def test_merging_reduces_launches(L):
 
 def test_fused_plan_traffic(L):
     """Fused classical form: the dots of the products' epilogues read one more
-    block each, the Jacobi division rides on the passes that produce p and s,
-    and the solution update joins {r, rho'}: 12 reads / 4 writes without a
-    preconditioner (merged: 14 / 4) and 13 / 6 with Jacobi and no separate
-    preconditioner pass (merged: 15 / 4 plus two passes of 1 / 1). Fused
-    Reordered form below."""
+    block each and the solution update joins {r, rho'}: 12 reads / 4 writes
+    without a preconditioner (merged: 14 / 4). With Jacobi the products read
+    the folded matrix A M^{-1} and the solution update divides p and s by
+    a_ii itself, so the plan is the same 12 / 4 with no preconditioner pass
+    and no p-hat or s-hat block (merged: 15 / 4 plus two passes of 1 / 1).
+    Fused Reordered form below."""
     from paper_1907_12874_amd import plan_traffic
 
     a = plan_traffic("classical", "fused", "none")
     b = plan_traffic("classical", "fused", "jacobi")
     # launches: five passes, the two products' partial-sum and finalize kernels, one more finalize
     assert (a["reads"], a["writes"], a["spmms"], a["precond_apps"], a["launches"]) == (12, 4, 2, 0, 10)
-    assert (b["reads"], b["writes"], b["spmms"], b["precond_apps"], b["launches"]) == (13, 6, 2, 0, 10)
+    assert (b["reads"], b["writes"], b["spmms"], b["precond_apps"], b["launches"]) == (12, 4, 2, 0, 10)
     m = plan_traffic("classical", "merged", "jacobi")
     assert b["reads"] + b["writes"] < m["reads"] + m["writes"] + 2 * m["precond_apps"]
     assert b["launches"] < m["launches"]

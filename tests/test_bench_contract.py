@@ -64,7 +64,8 @@ def _full_size_report():
                               "fixed_GBps": 5370.1, "fixed_ms_per_iter": 2.7812, "model_ms_per_iter": 2.6543,
                               "measured_over_model": 1.012, "solve_ms": 612.33, "solve_iters_max": 216,
                               "solve_rhs_it_per_s": 10400.2, "equal_accuracy": not (v == "reordered" and f == "fused"),
-                              "relres_true_max": 9.87654321e-09})
+                              "relres_true_max": 9.87654321e-09,
+                              "solve_passes_vs_merged": 1.0 if f == "merged" else 1.176})
     gains = {f"{v}_k{kk}": 0.0712 for v in ("classical", "reordered", "pipelined") for kk in ks}
     tab4 = [{"method": m, "m": mm, "basic_ms": 1.2345, "merged_ms": 1.1111, "improvement": 0.1, "model_improvement": 0.12,
              "paper_improvement": 0.1, "basic_GBps": 5000.0, "merged_GBps": 5100.0, "basic_bytes": 1.0e9,

@@ -157,6 +157,23 @@ def test_batched_tuner_config_and_determinism(lib):
     bs.close()
 
 
+def test_batched_single_workgroup_systems(lib):
+    """Every system on one workgroup (its passes synchronised by the
+    workgroup barrier alone, no device-wide counter), up to 20,000 rows, to
+    tol 1e-8: bit for bit the oracle in that configuration's summation order,
+    for a 256- and a 512-lane variant."""
+    systems, rhs = _batch(8, seed=11, nmin=300, nmax=20000)
+    say(f"batched single workgroup: {[(A.n, k) for A, k in systems]}")
+    bs = lib.BatchedSolver(systems)
+    for v in (1, 3):
+        bs.set_config(v, [1] * len(systems))
+        _, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-8, maxit=3000, solver=bs)
+        for info in infos:
+            assert np.all(info.status == oracle.CONVERGED)
+        _check_bitwise(bs, systems, rhs, X, infos, 1e-8, 3000)
+    bs.close()
+
+
 def test_batched_variants_agree_bitwise(lib):
     """The kernel variants of one block size sum in the same order: with the
     same shares they return identical results, and each matches the oracle in

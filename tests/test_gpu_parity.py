@@ -224,7 +224,8 @@ def _check_solve(lib, A, b, variant, formulation, precond, tol, maxit=3000, x0=N
         pooled over the columns);
       * the stop test: the GPU stopped at the first pass where its own
         estimate fell below (tol ||b||)^2, and its per-pass estimates track the
-        oracle's (within a factor 10) while those are above 1e-6 of the first.
+        oracle's (within a factor 10) while those are above 1e-6 of the first
+        and before the oracle's first tenfold jump.
         (The stopping pass itself is not compared: BiCGStab's estimate
         plateaus near the threshold, so two oracle runs that differ only in
         dot-product order stop up to 13 passes apart on the 64 x 64 case.)
@@ -264,7 +265,15 @@ def _check_solve(lib, A, b, variant, formulation, precond, tol, maxit=3000, x0=N
             eg = hist[:j, c, 3]
             eo = np.array([t["est"] for t in ref.traces[0]])
             assert eg[j - 1] < eps2 * (1 + 1e-12) and np.all(eg[: j - 1] >= eps2 * (1 - 1e-12)), (c, j)
+            # while the oracle's estimate is above 1e-6 of the first, and
+            # before its first jump by more than 10x: BiCGStab's residual is
+            # not monotone, and where a spike appears depends on rounding (a
+            # rounding-level change such as the fused form's folded Jacobi
+            # products moves it), after which two runs no longer follow one path
+            jump = np.nonzero(eo[1:] > 10 * eo[:-1])[0]
             live = eo > 1e-6 * eo[0]
+            if jump.size:
+                live[jump[0] + 1:] = False
             ratio = eg[live] / eo[live]
             assert np.all((ratio > 0.1) & (ratio < 10)), (c, ratio)
     # the library's own true residual agrees with one recomputed on the host
@@ -408,11 +417,10 @@ def test_deterministic_and_graph_equals_direct(lib, monkeypatch, variant, formul
 
 
 def test_fused_equals_merged_up_to_dot_order(lib):
-    """The fused classical form computes the merged form's statements: with
-    the dot products of a pass replaced by the same values, the updates are the
-    same. Checked here as: the sparse products of both forms are bitwise the
-    plain product, and 20 fixed passes agree within the summation-order
-    envelope of the oracle."""
+    """The fused classical form computes the merged form's statements (with
+    Jacobi, its products read A M^{-1} instead of applying M^{-1} first, a
+    rounding-level change): 20 fixed passes of both forms agree within the
+    summation-order envelope of the oracle."""
     import torch
 
     say("fused vs merged")

@@ -2,6 +2,7 @@
 the differentiation tier (adjoint solve with A^T, pattern-restricted
 gradient, torch.autograd chaining), against the CPU oracle, dense autograd
 and finite differences."""
+import os
 import sys
 
 import numpy as np
@@ -278,3 +279,122 @@ def test_autograd_solver_reused_before_backward(lib):
         loss.backward()
         ref = vc.grad.numpy()
         assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < 1e-9, (sc, np.linalg.norm(g - ref) / np.linalg.norm(ref))
+
+
+def test_update_values_with_a_new_array(lib):
+    """bicgstab_update_values through the C ABI: handing the handle another
+    values array (same pattern) gives the solve of a handle created on that
+    array, bit for bit, Jacobi diagonal included; a NULL pointer after an
+    in-place change of the borrowed array does the same."""
+    import ctypes as C
+
+    import torch
+
+    from paper_1907_12874_amd import _lib
+
+    say("update_values with a new array / NULL after an in-place change")
+    A = conv_diff(12, 3, (0.5, -0.3, 0.2))
+    k = 3
+    b = torch.from_numpy(manufactured_rhs(A, k, seed=4)[0]).cuda()
+    vals2 = A.values * 1.25
+    vals2[A.col_idx == A.row_of_entry()] *= 1.1  # a different diagonal
+    A2 = wg.CSR(A.n, A.row_ptr, A.col_idx, vals2)
+    s = lib.Solver.from_csr(A, k, precond="jacobi")
+    x1, _ = s.solve(b, tol=1e-10, maxit=1000)
+    v2 = torch.from_numpy(vals2).cuda()
+    L = _lib.lib()
+    assert L.bicgstab_update_values(s._h, C.c_void_p(v2.data_ptr())) == 0
+    x2, info2 = s.solve(b, tol=1e-10, maxit=1000)
+    ref = lib.Solver.from_csr(A2, k, precond="jacobi")
+    xr, infor = ref.solve(b, tol=1e-10, maxit=1000)
+    assert np.array_equal(info2.iters, infor.iters)
+    assert torch.equal(x2, xr)
+    assert not torch.equal(x1, x2)
+    # in place on the array the handle now borrows, then NULL
+    v2.mul_(0.8)
+    assert L.bicgstab_update_values(s._h, None) == 0
+    x3, _ = s.solve(b, tol=1e-10, maxit=1000)
+    ref3 = lib.Solver.from_csr(wg.CSR(A.n, A.row_ptr, A.col_idx, vals2 * 0.8), k, precond="jacobi")
+    xr3, _ = ref3.solve(b, tol=1e-10, maxit=1000)
+    assert torch.equal(x3, xr3)
+    s.close()
+    ref.close()
+    ref3.close()
+    del v2
+
+
+def test_precision_tier_inner_trajectory_full_size(lib):
+    """The precision tier's first FP32 inner solve at full size (27-point
+    random 100^3, k = 32), stopped after 15 inner passes (the inner solve to
+    1e-5 takes 17), on columns 0 and 31: x = ||b_c|| d_15 equals, bit for
+    bit, the refinement oracle's FP32
+    inner solve (oracle.refine.inner_merged_fp32) run with the kernels'
+    dot-product summation order. FP32 storage, FP32-accumulated products,
+    FP64 dots and scalars and the FP64 inner solution d all round the same
+    way on both sides."""
+    import math
+
+    import torch
+
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__)))
+    from kernel_order import group_dot
+
+    say("precision tier: 15 inner FP32 passes at 100^3, k = 32 (bitwise)")
+    from workloads import config_problem
+
+    cfg = config_problem(2, seed=0)
+    A, b, k = cfg["A"], cfg["b"], cfg["k"]
+    s = lib.Solver.from_csr(A, k, precision="fp32_refine")
+    x, info = s.solve(torch.from_numpy(b).cuda(), tol=1e-10, maxit=15)
+    X = x.cpu().numpy()
+    S = A.to_scipy()
+    A32 = S.astype(np.float32)
+    g = group_dot(A.n, k)
+    saved = orf._dot
+    # the inner solve's dots accumulate FP64 products of FP32 operands
+    orf._dot = lambda u, w: g(np.asarray(u, np.float64), np.asarray(w, np.float64))
+    try:
+        for c in (0, k - 1):
+            r = b[:, c] - S @ np.zeros(A.n)  # r = b - A x0 with x0 = 0
+            scale = math.sqrt(g(r, r))
+            d, passes, _ = orf.inner_merged_fp32(A32, None, (r / scale).astype(np.float32), 1e-5, 15)
+            assert passes == int(info.iters[c]) == 15
+            assert np.array_equal(X[:, c], 0.0 + scale * d), (c, np.abs(X[:, c] - scale * d).max())
+    finally:
+        orf._dot = saved
+    s.close()
+
+
+def test_precision_tier_error_vs_fp64_oracle_full_size(lib):
+    """The precision tier's workload at full size (27-point random 100^3,
+    k = 32, tol 1e-10): FP32 inner solves with FP64 refinement and the plain
+    FP64 solve on the same GPU, each against the CPU FP64 oracle run to
+    1e-12 on columns 0 and 31. The refined solution's error is stated and
+    stays within 5x that of the FP64 solve to the same tolerance."""
+    import torch
+
+    from workloads import config_problem
+
+    say("precision tier: error against the FP64 oracle at 100^3, k = 32")
+    cfg = config_problem(2, seed=0)
+    A, b, k = cfg["A"], cfg["b"], cfg["k"]
+    S = A.to_scipy()
+    bt = torch.from_numpy(b).cuda()
+    out = {}
+    for prec in ("fp32_refine", "fp64"):
+        s = lib.Solver.from_csr(A, k, precision=prec)
+        x, info = s.solve(bt, tol=1e-10, maxit=5000)
+        assert np.all(info.status == 0)
+        out[prec] = x.cpu().numpy()
+        s.close()
+    errs = {p: [] for p in out}
+    for c in (0, k - 1):
+        ref = oracle.solve_column(S, b[:, c], None, "classical", "merged", "none", 1e-12, 5000)
+        assert ref.status == oracle.CONVERGED
+        nr = np.linalg.norm(ref.x)
+        for p in out:
+            errs[p].append(float(np.linalg.norm(out[p][:, c] - ref.x) / nr))
+    say(f"  relative error vs the FP64 oracle (tol 1e-12), columns 0 and {k - 1}: FP32+refinement "
+        f"{errs['fp32_refine']}, FP64 {errs['fp64']}")
+    for e32, e64 in zip(errs["fp32_refine"], errs["fp64"]):
+        assert e32 <= 5 * e64 + 1e-10
