@@ -57,8 +57,24 @@ struct GridCaps {
   int blocks;
   int dot_blocks;
 };
+// A scalar step handed from a pass to the next one: the pass leaves its dot
+// partials (pair-major, P pairs x nb) in `part` and launches no finalize
+// kernel; every workgroup of the next pass sums them in the finalize
+// kernel's order and runs the step itself, and its workgroup 0 stores the new
+// state. Only steps whose inputs they do not overwrite qualify (F_ALPHA,
+// F_OMEGA_MERGED, F_OMEGA_BASIC), so workgroups that read the state before or
+// after workgroup 0 stores it take the same decisions.
+struct Pending {
+  const double* part;
+  int fin, slot, P, nb;
+};
+bool op_takes_pending(int op);
+// defer: leave the dot partials for the next pass (no finalize kernel)
 hipError_t launch_group(int op, const void* const* in, void* const* out, const void* diag, int n, int k, int slot,
-                        int fin, const Ctl& ctl, bool fp32, const GridCaps& caps, hipStream_t s);
+                        int fin, const Ctl& ctl, bool fp32, const GridCaps& caps, hipStream_t s,
+                        const Pending* pending = nullptr, bool defer = false);
+// Workgroups of a vector pass (its dot partials per pair).
+int group_blocks(int op, int n, int k, const GridCaps& caps);
 hipError_t launch_setup_state(const Ctl& ctl, double tol, int maxit, int hist_cap, hipStream_t s);
 hipError_t launch_mark_maxit(const Ctl& ctl, hipStream_t s);
 hipError_t launch_extract_diag(const int32_t* row_ptr, const int32_t* col, const double* val, double* diag,

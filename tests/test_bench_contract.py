@@ -113,8 +113,10 @@ def _full_size_report():
         "small_2d": small,
         "gpu_tab4": {"rows": tab4},
         "random_sparse": {"rows": rs},
-        "tiers": {"precision": {"fp64": {"ms": 80.03, "err_vs_oracle": 1.2e-10},
-                                "fp32_refine": {"ms": 40.49, "err_vs_oracle": 2.3e-10}, "speedup_fp32_refine": 1.977},
+        "tiers": {"precision": {"fp64": {"ms": 80.03, "err_vs_xstar_max": 2.158362225818514e-09},
+                                "fp32_refine": {"ms": 40.49, "err_vs_xstar_max": 1.879629673763007e-09},
+                                "speedup_fp32_refine": 1.977,
+                                "fp32_refine_tol1e-12": {"ms": 61.23, "err_vs_xstar_max": 2.345678901234e-12}},
                   "batched": {"ms": 387.89, "rhs_it_per_s": 142570.3, "algorithmic_GBps": 2666.6,
                               "speedup_vs_loop": 1.761},
                   "autograd": {"forward_ms": 46.13, "forward_backward_ms": 93.44}},
