@@ -645,6 +645,7 @@ def small_2d_section(pk, dev, passes=100, reps=5, maxit=3000):
         tr = pk.plan_traffic(variant, form, "none")
         sv.solve(b, x0, tol=0.0, maxit=2, out=x)
         tt = {2: float("inf"), 2 + passes: float("inf")}
+        st = {}
         for _ in range(reps):
             for p in tt:
                 torch.cuda.synchronize()
@@ -652,7 +653,12 @@ def small_2d_section(pk, dev, passes=100, reps=5, maxit=3000):
                 sv.solve(b, x0, tol=0.0, maxit=p, out=x)
                 torch.cuda.synchronize()
                 tt[p] = min(tt[p], time.perf_counter() - ta)
+                st[p] = sv.stats()
         per_it = (tt[2 + passes] - tt[2]) / passes
+        # kernels per iteration as launched (at this size the alpha / omega
+        # steps ride on the next pass, so fewer than the plan's count)
+        d_it = st[2 + passes]["iterations_enqueued"] - st[2]["iterations_enqueued"]
+        launched = (st[2 + passes]["launches"] - st[2]["launches"]) / max(1, d_it)
         ts = float("inf")
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -660,12 +666,13 @@ def small_2d_section(pk, dev, passes=100, reps=5, maxit=3000):
             _, inf = sv.solve(b, x0, tol=tol, maxit=maxit, out=x)
             torch.cuda.synchronize()
             ts = min(ts, time.perf_counter() - ta)
-        rows.append({"variant": variant, "formulation": form, "launches_per_iter": tr["launches"],
-                     "us_per_iter": round(per_it * 1e6, 2), "us_per_launch": round(per_it * 1e6 / tr["launches"], 2),
+        rows.append({"variant": variant, "formulation": form, "launches_per_iter": round(launched, 2),
+                     "plan_launches_per_iter": tr["launches"],
+                     "us_per_iter": round(per_it * 1e6, 2), "us_per_launch": round(per_it * 1e6 / launched, 2),
                      "fixed_rhs_it_per_s": round(1.0 / per_it, 1), "solve_ms": round(ts * 1e3, 3),
                      "solve_iters": int(inf.iters[0]), "solve_rhs_it_per_s": round(float(inf.iters[0]) / ts, 1),
                      "converged": bool(inf.status[0] == 0), "relres_true": float(inf.relres_true[0])})
-        print(f"# small 2d {variant:9s} {form:6s}: {rows[-1]['us_per_iter']:.1f} us/it, {tr['launches']} launches/it, "
+        print(f"# small 2d {variant:9s} {form:6s}: {rows[-1]['us_per_iter']:.1f} us/it, {launched:.0f} launches/it, "
               f"solve {rows[-1]['solve_ms']:.2f} ms, {rows[-1]['solve_iters']} it", file=sys.stderr, flush=True)
         sv.close()
     # the persistent batched kernel on this one system
@@ -1002,20 +1009,24 @@ def main():
                     # (t(2 + P) - t(2)) / P, so start-up passes and the exit
                     # check cancel; a warm-up solve prepares the handle first
                     sv.solve(bk, x0k, tol=0.0, maxit=2, out=xk)
-                    tp = {}
+                    tp, stp = {}, {}
                     for p in (2, 2 + args.sweep_passes):
                         torch.cuda.synchronize()
                         ta = time.perf_counter()
                         sv.solve(bk, x0k, tol=0.0, maxit=p, out=xk)
                         torch.cuda.synchronize()
                         tp[p] = time.perf_counter() - ta
+                        stp[p] = sv.stats()
                     tt = tp[2 + args.sweep_passes] - tp[2]
+                    d_it = stp[2 + args.sweep_passes]["iterations_enqueued"] - stp[2]["iterations_enqueued"]
+                    launched = (stp[2 + args.sweep_passes]["launches"] - stp[2]["launches"]) / max(1, d_it)
                     # solve to the tolerance: equal accuracy
                     ta = time.perf_counter()
                     _, inf = sv.solve(bk, x0k, tol=args.tol, maxit=min(args.maxit, 2000), out=xk)
                     torch.cuda.synchronize()
                     ts = time.perf_counter() - ta
-                    row = {"k": kk, "variant": variant, "formulation": form, "launches_per_iter": tr["launches"],
+                    row = {"k": kk, "variant": variant, "formulation": form, "launches_per_iter": round(launched, 2),
+                           "plan_launches_per_iter": tr["launches"],
                            "bytes_per_iter": ib,
                            "fixed_rhs_it_per_s": round(kk * args.sweep_passes / tt, 1),
                            "fixed_GBps": round(args.sweep_passes * ib / tt / 1e9, 1),

@@ -200,7 +200,9 @@ int bicgstab_history(bicgstab_t h, double* hist, int32_t cap, int32_t* count);
  * of length k. */
 int bicgstab_refine_outer(bicgstab_t h, int32_t* outer);
 
-/* Number of kernel launches and device-to-host polls of the last solve. */
+/* Iterations enqueued (whole captured chunks), kernel launches (passes, the
+ * products' run-partial sums and finalize kernels; a replayed graph counts
+ * the kernels it holds) and device-to-host polls of the last solve. */
 int bicgstab_last_solve_stats(bicgstab_t h, int32_t* iterations_enqueued, int32_t* launches, int32_t* polls);
 
 /* Kernel-level timing: runs the start-up passes on (d_b, d_x) and then

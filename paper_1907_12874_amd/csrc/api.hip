@@ -94,6 +94,7 @@ struct bicgstab_ctx {
   float* val_fold32 = nullptr;  //   the same in FP32 (refinement tier)
   int32_t* blk = nullptr;
   double* partials = nullptr;
+  double* partials_alt = nullptr;  // partials a pass leaves for the next one (Pending)
   double* bpart = nullptr;    // row-block partials of products with a dot epilogue
   double* bpart_t = nullptr;  // the same for the transposed matrix (own allocation)
   double* sc = nullptr;
@@ -105,6 +106,7 @@ struct bicgstab_ctx {
   int chunk = 8;
   int spmm_opl = 0;          // SpMM rows per lane per row block (0: default for the width)
   int spmm_xcd_chunk = 1;    // SpMM row blocks per XCD run (1: round-robin order)
+  int fold_max = 8192;       // hand an alpha / omega step to the next pass when its partials are at most this many
   bool use_graph = true;
   // pinned host mirrors
   int32_t* h_blk = nullptr;  // the row-block list, the source of its uploads
@@ -183,6 +185,7 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_vfold = take(has_fold(h) ? (size_t)h->nnz * elem : 0);
   const size_t o_blk = take(h->part.blk.size() * 4);
   const size_t o_part = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
+  const size_t o_part_alt = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
   const size_t o_bpart = take(has_spmm_dot(h) ? (h->part.blk.size() - 1) * 3 * (size_t)h->k * 8 : 0);
   const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
   const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
@@ -201,6 +204,7 @@ size_t layout(bicgstab_ctx* h, bool assign) {
     h->val_fold32 = has_fold(h) && fp32_inner(h) ? (float*)(b + o_vfold) : nullptr;
     h->blk = (int32_t*)(b + o_blk);
     h->partials = (double*)(b + o_part);
+    h->partials_alt = (double*)(b + o_part_alt);
     h->bpart = has_spmm_dot(h) ? (double*)(b + o_bpart) : nullptr;
     h->sc = (double*)(b + o_sc);
     h->ist = (int*)(b + o_ist);
@@ -294,9 +298,66 @@ SpmmMat mat_of(bicgstab_ctx* h, int which, bool fp32, bool fold = false) {
   return m;
 }
 
-hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void* const* vp, const Ctl& ctl,
-                       bool fp32, hipStream_t s, bool early_exit = true) {
+// How a step of an iteration links to its neighbours: it leaves its scalar
+// step to the next pass (defer), and / or takes the previous pass's (pend).
+struct StepLink {
+  bool defer = false;
+  Pending pend{nullptr, F_NONE, 0, 0, 0};
+};
+
+// A reduction whose scalar step only forms alpha or omega (F_ALPHA,
+// F_OMEGA_*), followed by a pass that can take it over, skips its
+// one-workgroup finalize kernel when its partials are few (small k): the
+// next pass's workgroups sum them and run the step themselves.
+std::vector<StepLink> link_steps(const bicgstab_ctx* h, const std::vector<Step>& steps, const SpmmMat& M) {
+  std::vector<StepLink> L(steps.size());
+  for (size_t i = 0; i + 1 < steps.size(); ++i) {
+    const Step& a = steps[i];
+    const Step& b = steps[i + 1];
+    if (a.fin != F_ALPHA && a.fin != F_OMEGA_MERGED && a.fin != F_OMEGA_BASIC) continue;
+    if (b.kind != K_GROUP || !op_takes_pending(b.op) || L[i].pend.fin != F_NONE) continue;
+    int P = 0, nb = 0;
+    if (a.kind == K_GROUP) {
+      P = op_info(a.op).ndot * h->k;
+      nb = group_blocks(a.op, (int)h->n, h->k, h->caps);
+    } else if (a.kind == K_SPMM_DOT) {
+      P = epilogue_dots(a.op) * h->k;
+      nb = spmm_dot_runs(M.nblk);
+    } else {
+      continue;
+    }
+    if (P <= 0 || M.nblk <= 0 || (long)P * nb > h->fold_max) continue;
+    L[i].defer = true;
+    L[i + 1].pend = Pending{h->partials_alt, a.fin, a.slot, P, nb};
+  }
+  return L;
+}
+
+// Kernels one step launches: the pass itself, a product's run-partial sums,
+// and the finalize kernel unless the step hands its scalar step on.
+int step_kernels(const Step& st, const StepLink& lk, int k) {
+  if (st.kind == K_GROUP) return 1 + ((op_info(st.op).ndot > 0 || st.fin != F_NONE) && !lk.defer ? 1 : 0);
+  if (st.kind == K_SPMM_DOT) {
+    const int P = epilogue_dots(st.op) * k;
+    return 1 + (P > 0 ? 1 : 0) + ((P > 0 || st.fin != F_NONE) && !lk.defer ? 1 : 0);
+  }
+  return 1;
+}
+
+int iteration_kernels(const bicgstab_ctx* h, const std::vector<Step>& steps, const std::vector<StepLink>& links) {
+  int n = 0;
+  for (size_t i = 0; i < steps.size(); ++i) n += step_kernels(steps[i], links[i], h->k);
+  return n;
+}
+
+hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void* const* vp, const Ctl& ctl0,
+                       bool fp32, hipStream_t s, bool early_exit = true, const StepLink* lk = nullptr) {
   const Globals* g = early_exit ? h->glob : nullptr;
+  // a pass that leaves its partials for the next one writes them apart
+  Ctl ctl = ctl0;
+  const bool defer = lk && lk->defer;
+  if (defer) ctl.partials = h->partials_alt;
+  const Pending* pend = lk && lk->pend.fin != F_NONE ? &lk->pend : nullptr;
   // a product of the Jacobi-folded form reads A M^{-1} (of the same matrix, A or A^T)
   const SpmmMat M = st.fold ? mat_of(h, M0.blk == h->blk ? 0 : 1, fp32, true) : M0;
   if (st.fold && !M.val) return hipErrorInvalidValue;
@@ -313,7 +374,7 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
       void* yh = epilogue_prec(st.op) ? vp[st.out[1]] : nullptr;
       const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
       return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], w, yh, diag, st.op, h->k, fp32, ctl, st.slot, st.fin,
-                             M.bpart, g, s);
+                             M.bpart, g, s, defer);
     }
     case K_PREC:
       return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
@@ -324,7 +385,8 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
       for (int i = 0; i < st.nin; ++i) in[i] = vp[st.in[i]];
       for (int i = 0; i < st.nout; ++i) out[i] = vp[st.out[i]];
       const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
-      return launch_group(st.op, in, out, diag, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->caps, s);
+      return launch_group(st.op, in, out, diag, (int)h->n, h->k, st.slot, st.fin, ctl, fp32, h->caps, s, pend,
+                          defer);
     }
   }
   return hipErrorInvalidValue;
@@ -332,9 +394,10 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
 
 int enqueue_steps(bicgstab_ctx* h, const std::vector<Step>& steps, const SpmmMat& M, void* const* vp, const Ctl& ctl,
                   bool fp32, int* launches) {
-  for (const Step& st : steps) {
-    HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
-    ++*launches;
+  const std::vector<StepLink> links = link_steps(h, steps, M);
+  for (size_t i = 0; i < steps.size(); ++i) {
+    HIPCHK(launch_step(h, steps[i], M, vp, ctl, fp32, h->ws, true, &links[i]));
+    *launches += step_kernels(steps[i], links[i], h->k);
   }
   return BICGSTAB_OK;
 }
@@ -353,16 +416,19 @@ int enqueue_chunk(bicgstab_ctx* h, int which, const SpmmMat& M, void* const* vp,
   for (auto& g : h->graphs) {
     if (g.x == vp[V_X] && g.b == vp[V_B] && g.mat == which && g.chunk == h->chunk) {
       HIPCHK(hipGraphLaunch(g.exec, h->ws));
-      *launches += h->chunk * (int)h->plan.iter.size();
+      *launches += h->chunk * iteration_kernels(h, h->plan.iter, link_steps(h, h->plan.iter, M));
       return BICGSTAB_OK;
     }
   }
   hipGraph_t graph = nullptr;
+  const std::vector<StepLink> links = link_steps(h, h->plan.iter, M);
   HIPCHK(hipStreamBeginCapture(h->ws, hipStreamCaptureModeThreadLocal));
   int dummy = 0;
   for (int c = 0; c < h->chunk; ++c) {
-    for (const Step& st : h->plan.iter) {
-      hipError_t e = launch_step(h, st, M, vp, ctl, fp32, h->ws);
+    for (size_t i = 0; i < h->plan.iter.size(); ++i) {
+      const Step& st = h->plan.iter[i];
+      hipError_t e = launch_step(h, st, M, vp, ctl, fp32, h->ws, true, &links[i]);
+      dummy += step_kernels(st, links[i], h->k) - 1;
       if (e != hipSuccess) {
         hipStreamEndCapture(h->ws, &graph);
         if (graph) hipGraphDestroy(graph);
@@ -700,6 +766,7 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   h->hist_cap = std::max(0, env_int("BICGSTAB_HIST_CAP", 1024));
   h->caps.blocks = std::max(8, env_int("BICGSTAB_GRID_CAP", 512));
   h->caps.dot_blocks = std::max(1, std::min(4096, env_int("BICGSTAB_DOT_GRID", 512)));
+  h->fold_max = std::max(0, env_int("BICGSTAB_FOLD_MAX", 8192));
   h->spmm_xcd_chunk = std::max(1, env_int("BICGSTAB_SPMM_XCD_CHUNK", 1));
   h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
   h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;

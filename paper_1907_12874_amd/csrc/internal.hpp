@@ -42,7 +42,7 @@ hipError_t launch_spmm(const SpmmMat& A, const void* X, void* Y, int k, bool fp3
 // column runs.
 hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, void* Yh, const void* diag,
                            int epi, int k, bool fp32, const Ctl& ctl, int slot, int fin, double* bpart,
-                           const Globals* glob, hipStream_t s);
+                           const Globals* glob, hipStream_t s, bool defer = false);
 // Runs of row blocks the epilogue partials are first summed over (<= 256).
 int spmm_dot_runs(int nblk);
 // The one-workgroup finalize kernel after a reduction pass of nb workgroups

@@ -69,6 +69,7 @@ struct GArgs {
   long n;
   int k, kpl, slot, fin;
   Ctl ctl;
+  Pending pend;  // a scalar step left by the previous pass (pend.fin = F_NONE: none)
 };
 
 // Dot products leave the streaming pass as one partial sum per workgroup and
@@ -156,9 +157,109 @@ __global__ __launch_bounds__(kFinBlock) void finalize_kernel(Ctl ctl, int P, int
 
 // ---------------------------------------------------------- group kernel ---
 
-template <class Op, class T, int U, int BS>
+// The scalar step a pass took over from the pass before (Pending): every
+// workgroup stages the k columns' state in LDS, sums the pending partials in
+// the finalize kernel's order (kFinLanes lanes per pair, lane g over
+// workgroups g, g + kFinLanes, ..., then the lanes in order), and runs the
+// step on its LDS copy, whose scalars the pass then uses. Workgroup 0 stores
+// the new state. The step must not overwrite its own inputs (it reads the
+// state another workgroup may be storing at the same time): F_ALPHA,
+// F_OMEGA_MERGED and F_OMEGA_BASIC write only alpha, omega, the estimate, a
+// pending stop and (for a column that stops) its status, which every
+// workgroup computes alike.
+struct PendState {
+  double sc[S_NSCAL * kMaxK];
+  int ist[I_NINT * kMaxK];
+  Globals glob;
+  double red[kBlock];
+};
+
+template <int BS>
+__device__ void take_pending(const GArgs& a, PendState& ps, Ctl& L) {
+  const int k = a.k, t = threadIdx.x;
+  for (int i = t; i < S_NSCAL * kMaxK; i += BS)
+    if ((i & (kMaxK - 1)) < k) ps.sc[i] = a.ctl.sc[i];
+  for (int i = t; i < I_NINT * kMaxK; i += BS)
+    if ((i & (kMaxK - 1)) < k) ps.ist[i] = a.ctl.ist[i];
+  if (t == 0) ps.glob = *a.ctl.glob;
+  __syncthreads();
+  L = a.ctl;
+  L.sc = ps.sc;
+  L.ist = ps.ist;
+  L.glob = &ps.glob;
+  constexpr int G = kFinLanes;
+  constexpr int PP = BS / G;
+  const int P = a.pend.P, nb = a.pend.nb;
+  for (int p0 = 0; p0 < P; p0 += PP) {
+    const int p = p0 + t / G, g = t % G;
+    double v = 0.0;
+    if (p < P) {
+      const double* q = a.pend.part + (size_t)p * nb;
+#pragma unroll 8
+      for (int b = g; b < nb; b += G) v += q[b];
+    }
+    ps.red[t] = v;
+    __syncthreads();
+    if (t < PP && p0 + t < P) {
+      double sum = 0.0;
+      for (int j = 0; j < G; ++j) sum += ps.red[t * G + j];
+      const int pp = p0 + t, d = pp / k, c = pp - d * k;
+      SC(L, S_D0 + a.pend.slot + d, c) = sum;
+    }
+    __syncthreads();
+  }
+  if (t < k) finalize_column(a.pend.fin, t, L);
+  __syncthreads();
+  if (t == 0) finalize_global(a.pend.fin, L);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int i = t; i < S_NSCAL * kMaxK; i += BS)
+      if ((i & (kMaxK - 1)) < k) a.ctl.sc[i] = ps.sc[i];
+    for (int i = t; i < I_NINT * kMaxK; i += BS)
+      if ((i & (kMaxK - 1)) < k) a.ctl.ist[i] = ps.ist[i];
+    if (t == 0) *a.ctl.glob = ps.glob;
+  }
+}
+
+// The passes that take over a pending scalar step (those that follow an
+// alpha or omega reduction in the plans).
+template <class Op>
+struct TakesPending {
+  static constexpr bool value = false;
+};
+template <>
+struct TakesPending<KSubAlpha> {
+  static constexpr bool value = true;
+};
+template <>
+struct TakesPending<KXUpd> {
+  static constexpr bool value = true;
+};
+template <>
+struct TakesPending<KCXrRho> {
+  static constexpr bool value = true;
+};
+template <>
+struct TakesPending<KFXrRhoD> {
+  static constexpr bool value = true;
+};
+
+bool op_takes_pending(int op) {
+  return op == OP_SUB_ALPHA || op == OP_XUPD || op == OP_C_XR_RHO || op == OP_F_XR_RHO_D;
+}
+
+template <class Op, class T, int U, int BS, bool PEND>
 __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
-  if (Op::EARLY && a.ctl.glob->nrun == 0) return;
+  // A pass that takes a pending step has no early exit: its workgroup 0 may
+  // store the running-column count while other workgroups start, so their
+  // waves could read different counts; with no column running the step and
+  // the pass do nothing anyway.
+  if (!PEND && Op::EARLY && a.ctl.glob->nrun == 0) return;
+  // the scalars this pass uses: the device state, or the LDS copy after a
+  // pending scalar step
+  __shared__ PendState ps;  // unused (and not allocated) without PEND
+  Ctl cs = a.ctl;
+  if constexpr (PEND) take_pending<BS>(a, ps, cs);
   const int kpl = a.kpl;
   const int kp = 1 << kpl;
   const int k = a.k;
@@ -166,9 +267,9 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
   bool on = c < k;
   if (on) {
     if (Op::PART == PART_RUN)
-      on = IS(a.ctl, I_STATUS, c) == ST_RUNNING;
+      on = IS(cs, I_STATUS, c) == ST_RUNNING;
     else if (Op::PART == PART_ZEROB)
-      on = IS(a.ctl, I_ZEROB, c) != 0;
+      on = IS(cs, I_ZEROB, c) != 0;
   }
   constexpr int NI = Op::NIN + (Op::USE_D ? 1 : 0) > 0 ? Op::NIN + (Op::USE_D ? 1 : 0) : 1;
   constexpr int NO = Op::NOUT > 0 ? Op::NOUT : 1;
@@ -178,15 +279,15 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
   for (int d = 0; d < ND; ++d) acc[d] = 0.0;
   if (on) {
     Coef cf;
-    cf.alpha = SC(a.ctl, S_ALPHA, c);
-    cf.omega = SC(a.ctl, S_OMEGA, c);
-    cf.beta = SC(a.ctl, S_BETA, c);
-    cf.scale = SC(a.ctl, S_SCALE, c);
-    cf.delta = SC(a.ctl, S_DELTA, c);
-    cf.c1 = SC(a.ctl, S_C1, c);
-    cf.c2 = SC(a.ctl, S_C2, c);
+    cf.alpha = SC(cs, S_ALPHA, c);
+    cf.omega = SC(cs, S_OMEGA, c);
+    cf.beta = SC(cs, S_BETA, c);
+    cf.scale = SC(cs, S_SCALE, c);
+    cf.delta = SC(cs, S_DELTA, c);
+    cf.c1 = SC(cs, S_C1, c);
+    cf.c2 = SC(cs, S_C2, c);
     // outputs in COUT are written only where the column restarts
-    const unsigned wmask = Op::COUT == 0u || IS(a.ctl, I_RESTART, c) != 0 ? ~0u : ~Op::COUT;
+    const unsigned wmask = Op::COUT == 0u || IS(cs, I_RESTART, c) != 0 ? ~0u : ~Op::COUT;
     const int rpb = BS >> kpl;
     const long n = a.n;
     const long stride = (long)gridDim.x * rpb;
@@ -241,19 +342,33 @@ __global__ __launch_bounds__(BS) void group_kernel(GArgs a) {
   if constexpr (Op::NDOT > 0) block_reduce_store<Op::NDOT, BS>(acc, a);
 }
 
-template <class Op, class T>
-hipError_t launch_op(const GArgs& a0, const GridCaps& caps, hipStream_t s) {
-  GArgs a = a0;
-  constexpr int BS = kBlock;
+template <class Op>
+int op_blocks(long n, int kpl, const GridCaps& caps) {
   const int cap = Op::NDOT > 0 ? caps.dot_blocks : caps.blocks;
-  const int rpb = BS >> a.kpl;
-  long blocks = (a.n + rpb - 1) / rpb;
+  const int rpb = kBlock >> kpl;
+  long blocks = (n + rpb - 1) / rpb;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+template <class Op, class T>
+hipError_t launch_op(const GArgs& a0, const GridCaps& caps, hipStream_t s, bool defer) {
+  GArgs a = a0;
+  constexpr int BS = kBlock;
+  const int blocks = op_blocks<Op>(a.n, a.kpl, caps);
   constexpr int U = Op::NIN <= 4 ? 4 : 2;
-  hipLaunchKernelGGL((group_kernel<Op, T, U, BS>), dim3((unsigned)blocks), dim3(BS), 0, s, a);
+  if (a.pend.fin != F_NONE) {
+    if constexpr (TakesPending<Op>::value)
+      hipLaunchKernelGGL((group_kernel<Op, T, U, BS, true>), dim3((unsigned)blocks), dim3(BS), 0, s, a);
+    else
+      return hipErrorInvalidValue;  // the host hands pending steps only to the passes above
+  } else {
+    hipLaunchKernelGGL((group_kernel<Op, T, U, BS, false>), dim3((unsigned)blocks), dim3(BS), 0, s, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (defer) return hipSuccess;  // the partials stay for the next pass
   if (Op::NDOT > 0 || a.fin != F_NONE) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, a.ctl, Op::NDOT * a.k, (int)blocks, a.slot,
                        a.fin, Op::EARLY ? 1 : 0);
@@ -263,49 +378,49 @@ hipError_t launch_op(const GArgs& a0, const GridCaps& caps, hipStream_t s) {
 }
 
 template <class T>
-hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStream_t s) {
+hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStream_t s, bool defer) {
   switch (op) {
-    case OP_INIT: return launch_op<KInit, T>(a, grid_cap, s);
-    case OP_INIT_P: return launch_op<KInitP, T>(a, grid_cap, s);
-    case OP_ZEROB: return launch_op<KZeroB, T>(a, grid_cap, s);
-    case OP_COPY: return launch_op<KCopy, T>(a, grid_cap, s);
-    case OP_FILL0: return launch_op<KFill0, T>(a, grid_cap, s);
-    case OP_EXIT: return launch_op<KExit, T>(a, grid_cap, s);
-    case OP_DOT: return launch_op<KDot, T>(a, grid_cap, s);
-    case OP_DOTSELF: return launch_op<KDotSelf, T>(a, grid_cap, s);
-    case OP_SUB_ALPHA: return launch_op<KSubAlpha, T>(a, grid_cap, s);
-    case OP_SUB_OMEGA: return launch_op<KSubOmega, T>(a, grid_cap, s);
-    case OP_XUPD: return launch_op<KXUpd, T>(a, grid_cap, s);
-    case OP_PUPD: return launch_op<KPUpd, T>(a, grid_cap, s);
-    case OP_C_PPT: return launch_op<KCPpt, T>(a, grid_cap, s);
-    case OP_C_XR_RHO: return launch_op<KCXrRho, T>(a, grid_cap, s);
-    case OP_C_R_RHO: return launch_op<KCRRho, T>(a, grid_cap, s);
-    case OP_R_G3: return launch_op<KRG3, T>(a, grid_cap, s);
-    case OP_R_XZV: return launch_op<KRXzv, T>(a, grid_cap, s);
-    case OP_P_G1: return launch_op<KPG1, T>(a, grid_cap, s);
-    case OP_P_G2: return launch_op<KPG2, T>(a, grid_cap, s);
-    case OP_P_G3: return launch_op<KPG3, T>(a, grid_cap, s);
-    case OP_PP_G1: return launch_op<KPPG1, T>(a, grid_cap, s);
-    case OP_PP_G2: return launch_op<KPPG2, T>(a, grid_cap, s);
-    case OP_PP_G3: return launch_op<KPPG3, T>(a, grid_cap, s);
-    case OP_PP_G4: return launch_op<KPPG4, T>(a, grid_cap, s);
-    case OP_REF_RESID: return launch_op<KRefResid, T>(a, grid_cap, s);
-    case OP_REF_SCALE: return launch_op<KRefScale, T>(a, grid_cap, s);
-    case OP_REF_UPDATE: return launch_op<KRefUpdate, T>(a, grid_cap, s);
-    case OP_F_SUB_ALPHA_H: return launch_op<KFSubAlphaH, T>(a, grid_cap, s);
-    case OP_F_PUPD_H: return launch_op<KFPUpdH, T>(a, grid_cap, s);
-    case OP_F_XR_RHO_H: return launch_op<KFXrRhoH, T>(a, grid_cap, s);
-    case OP_IB_INIT: return launch_op<KIbInit, T>(a, grid_cap, s);
-    case OP_IB_G1: return launch_op<KIbG1, T>(a, grid_cap, s);
-    case OP_IB_G2: return launch_op<KIbG2, T>(a, grid_cap, s);
-    case OP_IB_G3: return launch_op<KIbG3, T>(a, grid_cap, s);
-    case OP_IB_Z: return launch_op<KIbZ, T>(a, grid_cap, s);
-    case OP_IB_V: return launch_op<KIbV, T>(a, grid_cap, s);
-    case OP_IB_X: return launch_op<KIbX, T>(a, grid_cap, s);
-    case OP_F_PP_G2H: return launch_op<KPPG2H, T>(a, grid_cap, s);
-    case OP_F_PP_G4H: return launch_op<KPPG4H, T>(a, grid_cap, s);
-    case OP_RE_R: return launch_op<KReR, T>(a, grid_cap, s);
-    case OP_F_XR_RHO_D: return launch_op<KFXrRhoD, T>(a, grid_cap, s);
+    case OP_INIT: return launch_op<KInit, T>(a, grid_cap, s, defer);
+    case OP_INIT_P: return launch_op<KInitP, T>(a, grid_cap, s, defer);
+    case OP_ZEROB: return launch_op<KZeroB, T>(a, grid_cap, s, defer);
+    case OP_COPY: return launch_op<KCopy, T>(a, grid_cap, s, defer);
+    case OP_FILL0: return launch_op<KFill0, T>(a, grid_cap, s, defer);
+    case OP_EXIT: return launch_op<KExit, T>(a, grid_cap, s, defer);
+    case OP_DOT: return launch_op<KDot, T>(a, grid_cap, s, defer);
+    case OP_DOTSELF: return launch_op<KDotSelf, T>(a, grid_cap, s, defer);
+    case OP_SUB_ALPHA: return launch_op<KSubAlpha, T>(a, grid_cap, s, defer);
+    case OP_SUB_OMEGA: return launch_op<KSubOmega, T>(a, grid_cap, s, defer);
+    case OP_XUPD: return launch_op<KXUpd, T>(a, grid_cap, s, defer);
+    case OP_PUPD: return launch_op<KPUpd, T>(a, grid_cap, s, defer);
+    case OP_C_PPT: return launch_op<KCPpt, T>(a, grid_cap, s, defer);
+    case OP_C_XR_RHO: return launch_op<KCXrRho, T>(a, grid_cap, s, defer);
+    case OP_C_R_RHO: return launch_op<KCRRho, T>(a, grid_cap, s, defer);
+    case OP_R_G3: return launch_op<KRG3, T>(a, grid_cap, s, defer);
+    case OP_R_XZV: return launch_op<KRXzv, T>(a, grid_cap, s, defer);
+    case OP_P_G1: return launch_op<KPG1, T>(a, grid_cap, s, defer);
+    case OP_P_G2: return launch_op<KPG2, T>(a, grid_cap, s, defer);
+    case OP_P_G3: return launch_op<KPG3, T>(a, grid_cap, s, defer);
+    case OP_PP_G1: return launch_op<KPPG1, T>(a, grid_cap, s, defer);
+    case OP_PP_G2: return launch_op<KPPG2, T>(a, grid_cap, s, defer);
+    case OP_PP_G3: return launch_op<KPPG3, T>(a, grid_cap, s, defer);
+    case OP_PP_G4: return launch_op<KPPG4, T>(a, grid_cap, s, defer);
+    case OP_REF_RESID: return launch_op<KRefResid, T>(a, grid_cap, s, defer);
+    case OP_REF_SCALE: return launch_op<KRefScale, T>(a, grid_cap, s, defer);
+    case OP_REF_UPDATE: return launch_op<KRefUpdate, T>(a, grid_cap, s, defer);
+    case OP_F_SUB_ALPHA_H: return launch_op<KFSubAlphaH, T>(a, grid_cap, s, defer);
+    case OP_F_PUPD_H: return launch_op<KFPUpdH, T>(a, grid_cap, s, defer);
+    case OP_F_XR_RHO_H: return launch_op<KFXrRhoH, T>(a, grid_cap, s, defer);
+    case OP_IB_INIT: return launch_op<KIbInit, T>(a, grid_cap, s, defer);
+    case OP_IB_G1: return launch_op<KIbG1, T>(a, grid_cap, s, defer);
+    case OP_IB_G2: return launch_op<KIbG2, T>(a, grid_cap, s, defer);
+    case OP_IB_G3: return launch_op<KIbG3, T>(a, grid_cap, s, defer);
+    case OP_IB_Z: return launch_op<KIbZ, T>(a, grid_cap, s, defer);
+    case OP_IB_V: return launch_op<KIbV, T>(a, grid_cap, s, defer);
+    case OP_IB_X: return launch_op<KIbX, T>(a, grid_cap, s, defer);
+    case OP_F_PP_G2H: return launch_op<KPPG2H, T>(a, grid_cap, s, defer);
+    case OP_F_PP_G4H: return launch_op<KPPG4H, T>(a, grid_cap, s, defer);
+    case OP_RE_R: return launch_op<KReR, T>(a, grid_cap, s, defer);
+    case OP_F_XR_RHO_D: return launch_op<KFXrRhoD, T>(a, grid_cap, s, defer);
     default: return hipErrorInvalidValue;
   }
 }
@@ -316,7 +431,8 @@ hipError_t launch_finalize(const Ctl& ctl, int P, int nb, int slot, int fin, boo
 }
 
 hipError_t launch_group(int op, const void* const* in, void* const* out, const void* diag, int n, int k, int slot,
-                        int fin, const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s) {
+                        int fin, const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s,
+                        const Pending* pending, bool defer) {
   GArgs a;
   for (int i = 0; i < 7; ++i) a.in[i] = in[i];
   for (int i = 0; i < 5; ++i) a.out[i] = out[i];
@@ -330,7 +446,17 @@ hipError_t launch_group(int op, const void* const* in, void* const* out, const v
   a.slot = slot;
   a.fin = fin;
   a.ctl = ctl;
-  return fp32 ? dispatch_op<float>(op, a, grid_cap, s) : dispatch_op<double>(op, a, grid_cap, s);
+  a.pend = pending ? *pending : Pending{nullptr, F_NONE, 0, 0, 0};
+  if (pending && (pending->P > kMaxK * 7 || !op_takes_pending(op))) return hipErrorInvalidValue;
+  return fp32 ? dispatch_op<float>(op, a, grid_cap, s, defer) : dispatch_op<double>(op, a, grid_cap, s, defer);
+}
+
+// Workgroups of a vector pass (for the pair-major partial layout).
+int group_blocks(int op, int n, int k, const GridCaps& caps) {
+  int kpl = 0;
+  while ((1 << kpl) < pad_k(k)) ++kpl;
+  const GridCaps c = caps;
+  return op_info(op).ndot > 0 ? op_blocks<KDot>(n, kpl, c) : op_blocks<KCopy>(n, kpl, c);
 }
 
 // ------------------------------------------------------- preconditioner ---

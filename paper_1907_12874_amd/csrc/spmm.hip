@@ -580,7 +580,7 @@ int spmm_dot_runs(int nblk) { return std::max(1, std::min(nblk, 256)); }
 
 hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void* W, void* Yh, const void* diag,
                            int epi, int k, bool fp32, const Ctl& ctl, int slot, int fin, double* bpart,
-                           const Globals* glob, hipStream_t s) {
+                           const Globals* glob, hipStream_t s, bool defer) {
   if (epi < 0 || epi >= E_NUM || (epilogue_dots(epi) > 0 && !W) || (epilogue_prec(epi) && (!Yh || !diag)))
     return hipErrorInvalidValue;
   const int P = epilogue_dots(epi) * k;
@@ -597,6 +597,7 @@ hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void*
     }
   }
   if (P == 0 && fin == F_NONE) return hipSuccess;
+  if (defer) return hipSuccess;  // the run partials stay for the next pass
   // with no rows the partials are not written: the finalize then sums nothing
   return launch_finalize(ctl, A.nblk > 0 ? P : 0, G, slot, fin, glob != nullptr, s);
 }

@@ -616,6 +616,37 @@ def test_reordered_restart_full_size(lib):
         assert tuple(hist[j, c, :]) == (t["alpha"], t["omega"], t["rho"], t["est"]), j
 
 
+@pytest.mark.parametrize("variant,formulation,precond", [("classical", "merged", "jacobi"), ("classical", "merged", "none"),
+                                                         ("classical", "basic", "jacobi"), ("classical", "fused", "jacobi"),
+                                                         ("reordered", "merged", "none"), ("reordered", "fused", "none")])
+def test_pending_scalar_step_changes_nothing(lib, monkeypatch, variant, formulation, precond):
+    """At small k an alpha or omega reduction hands its scalar step to the
+    next pass (no one-workgroup finalize kernel): solutions, pass counts,
+    statuses and per-pass scalars equal those of the same solve with every
+    step in its own finalize kernel (BICGSTAB_FOLD_MAX=0), bit for bit, with
+    fewer kernel launches per iteration."""
+    import torch
+
+    say(f"pending scalar step {variant}/{formulation}/{precond}")
+    A = conv_diff(19, 3, (1.0, 0.7, 0.3))
+    b, _ = manufactured_rhs(A, 3, seed=41)
+    bt = torch.from_numpy(b).cuda()
+    res = {}
+    for fold in ("8192", "0"):
+        monkeypatch.setenv("BICGSTAB_FOLD_MAX", fold)
+        s = gpu_solver(lib, A, 3, variant, formulation, precond)
+        x, info = s.solve(bt, tol=1e-9, maxit=2000)
+        res[fold] = (to_np(x), info.iters.copy(), info.status.copy(), s.history(), s.stats())
+        s.close()
+    (x1, i1, s1, h1, st1), (x0, i0, s0, h0, st0) = res["8192"], res["0"]
+    assert np.array_equal(i1, i0) and np.array_equal(s1, s0) and np.all(s1 == 0)
+    assert np.array_equal(x1, x0)
+    for c in range(3):  # the passes each column ran (the rest of the history is not written)
+        assert np.array_equal(h1[: i1[c], c], h0[: i0[c], c]), c
+    assert st1["iterations_enqueued"] == st0["iterations_enqueued"]
+    assert st1["launches"] < st0["launches"], (st1, st0)
+
+
 # ---------------------------------------------------- full-size checks ---
 
 def test_full_size_cfg1_sampled(lib):
