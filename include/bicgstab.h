@@ -269,8 +269,9 @@ int bicgstab_batched_solve(bicgstab_batched_t h, const double* const* d_b, doubl
  * shares are first proportional to measured work (bytes per pass x passes)
  * and then twice re-derived from a per-system time model fitted to the run
  * before (passes x (latency + bytes / (share x per-workgroup bandwidth)),
- * least squares; the smallest makespan whose shares fit the budget). Keeps
- * the fastest configuration. d_x holds the initial guesses on input (restored
+ * least squares; the smallest makespan whose shares fit the budget). Last,
+ * the best allocation thinned: every share divided by 2, 4, 8 and 16 (at
+ * least one workgroup each). Keeps the fastest configuration. d_x holds the initial guesses on input (restored
  * before every trial) and the solution of the chosen configuration on output.
  * best_ms: that configuration's kernel time (may be NULL). */
 int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double* const* d_x, double tol,
@@ -285,8 +286,8 @@ int bicgstab_batched_get_config(bicgstab_batched_t h, int32_t* variant, int32_t*
 int bicgstab_batched_set_config(bicgstab_batched_t h, int32_t variant, const int32_t* workgroups);
 /* Host-only: parameters of kernel variant `variant` (0-based; an error past
  * the last one): threads per workgroup, rows a thread takes per step of a
- * vector phase, entries per step of a row product, rows per step of a sparse
- * product. Any pointer may be NULL. */
+ * vector phase, entries per pipelined step of a row product, rows per stage
+ * of a sparse product's pipeline. Any pointer may be NULL. */
 int bicgstab_batched_variant_info(int32_t variant, int32_t* block, int32_t* rows_per_step,
                                   int32_t* entries_per_step, int32_t* product_rows_per_step);
 int bicgstab_batched_destroy(bicgstab_batched_t h);

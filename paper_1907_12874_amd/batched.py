@@ -25,7 +25,8 @@ class BatchedConfig:
 
 def variant_info(variant: int):
     """(threads per workgroup, rows per vector-phase step, entries per
-    row-product step, rows per sparse-product step)."""
+    pipelined row-product step, rows per stage of the sparse products'
+    pipeline)."""
     b, r, e, pr = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
     check(lib().bicgstab_batched_variant_info(int(variant), C.byref(b), C.byref(r), C.byref(e), C.byref(pr)),
           "bicgstab_batched_variant_info")

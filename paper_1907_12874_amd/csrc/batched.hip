@@ -62,6 +62,14 @@ struct BGlob {
 // barrier with ordinal e completes when the counter reaches (e + 1) * nw.
 // Every wave first waits for its own stores to complete, then one thread
 // releases at agent scope, arrives, waits and acquires. Returns false on abort.
+// On this multi-XCD part the agent-scope release writes back the L2 of the
+// workgroup's XCD and the acquire invalidates its L1 and L2; both complete
+// asynchronously, so the thread waits for each (s_waitcnt) before it arrives
+// and before the workgroup barrier lets the other waves load: without the
+// first wait the arrival could be seen before the written-back data, without
+// the second another wave's load could be served from a line the
+// invalidation has not reached yet (both seen as rare stale reads of other
+// workgroups' blocks and partials when the waits were left to the compiler).
 // A system on a single workgroup needs only the workgroup barrier: its waves
 // share one compute unit and its L1, so a workgroup-scope release / acquire
 // (__syncthreads) orders their global stores and loads, and no agent-scope
@@ -73,6 +81,7 @@ __device__ bool sys_barrier(unsigned* bar, unsigned target, int* abort_flag, lon
   if (nw == 1) return true;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     const unsigned long long t0 = wall_clock64();
@@ -86,6 +95,7 @@ __device__ bool sys_barrier(unsigned* bar, unsigned target, int* abort_flag, lon
       __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     s_ok = ok;
   }
   __syncthreads();
@@ -123,7 +133,15 @@ __device__ void reduce_partials(const BSys& S, int slot, double (*out)[kMaxK]) {
   for (int t = threadIdx.x; t < ND * kp; t += BS) {
     const int d = t / kp, c = t - d * kp;
     double v = 0.0;
-    for (int q = 0; q < S.nw; ++q) v += S.part[((size_t)(slot * S.nw + q) * 4 + d) * kp + c];
+    // 16 partials loaded at once (not one dependent load per workgroup),
+    // then added in workgroup order
+    for (int q0 = 0; q0 < S.nw; q0 += 16) {
+      double pv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) pv[j] = S.part[((size_t)(slot * S.nw + min(q0 + j, S.nw - 1)) * 4 + d) * kp + c];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v = q0 + j < S.nw ? v + pv[j] : v;
+    }
     out[d][c] = v;
   }
   __syncthreads();
@@ -144,99 +162,117 @@ __device__ __forceinline__ T& at(T* base, unsigned e) {
   return *(T*)((gchar*)base + e * (unsigned)sizeof(T));
 }
 
-// (A X)[row, c], the row's entries in stored order, no contraction (bitwise
-// the CSR product of the single-system path). CH entries per step, branch
-// free: a slot past the row's end repeats the row's last entry and its product
-// is not added (a select), so the column indices and values of a step load
-// together, then all its gathers are in flight before the first is used.
-template <int CH>
-__device__ __forceinline__ double row_product(const BSys& S, const gdouble* __restrict__ X, int row, int c) {
+// Sparse products: (A X)[row, c] for the rows row, row + rpp, ... below row1
+// of a thread, each row's entries added in stored order with no contraction
+// (bitwise the CSR product of the single-system path), handed to
+// emit(row, e, y, q) in increasing row order, where q holds NP operands of
+// element e = (row, c) that pre(e, q) loads (the other block the phase reads
+// at that element).
+//
+// A row's product is a chain of three dependent loads: its row offsets, then
+// its column indices and values, then the gathered X entries. The rows of a
+// thread are software-pipelined so that the chain of one row overlaps those
+// of the next two: while the gathers of a stage (RU rows) are in flight, the
+// column indices of the next stage and the row offsets of the stage after
+// are loaded, and every load of the loop body is unconditional (rows past
+// row1 load a valid row's entries and are not emitted), so a stage costs
+// about one memory round trip instead of three. The first CH entries of a row
+// go through the pipeline; a longer row adds the rest afterwards, CH at a
+// time, still in entry order. A slot past the row's end repeats its last
+// entry and its product is not added (a select); an empty row's slots load
+// entry 0 (a system without entries points at a zero dummy entry) and add
+// nothing.
+template <int CH, int RU, int NP, class Pre, class Emit>
+__device__ __forceinline__ void product_rows(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
+                                             int row1, int c, Pre pre, Emit emit) {
+  if (row >= row1) return;
   gcint* __restrict__ rp = (gcint*)S.row_ptr;
   gcint* __restrict__ col = (gcint*)S.col;
   gcdouble* __restrict__ val = (gcdouble*)S.val;
-  const int eb = rp[row], ee = rp[row + 1];
-  double sum = 0.0;
-  for (int e0 = eb; e0 < ee; e0 += CH) {
-    int cj[CH];
-    double av[CH], xv[CH];
+  const int k = S.k;
+  const int last = row1 - 1;
+  // stage being computed: rows row + u * rpp, their offsets and column indices
+  int eb[RU], ne[RU], cj[RU][CH];
+  // row offsets of the next stage (raw, so no wait is forced before they are used)
+  int pa[RU], pb[RU];
+  auto load_cols = [&](const int (&a)[RU], const int (&b)[RU]) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int e = min(e0 + j, ee - 1);
-      cj[j] = col[e];
-      av[j] = val[e];
+    for (int u = 0; u < RU; ++u) {
+      eb[u] = a[u];
+      ne[u] = b[u] - a[u];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) cj[u][j] = col[ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0];
     }
+  };
+  auto load_offsets = [&](int r) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) xv[j] = at(X, (unsigned)(cj[j] * S.k + c));
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const double t = sum + av[j] * xv[j];
-      sum = e0 + j < ee ? t : sum;
+    for (int u = 0; u < RU; ++u) {
+      const int rr = min(r + u * rpp, last);
+      pa[u] = rp[rr];
+      pb[u] = rp[rr + 1];
     }
-  }
-  return sum;
-}
-
-// The products of RU rows at once (rows row + u * rpp below row1; the others
-// give 0): each row's entries in stored order as in row_product, with the
-// loads of all RU rows of a step issued together.
-template <int CH, int RU>
-__device__ __forceinline__ void rows_product(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
-                                             int row1, int c, double (&z)[RU]) {
-  if constexpr (RU == 1) {
-    z[0] = row < row1 ? row_product<CH>(S, X, row, c) : 0.0;
-  } else {
-    gcint* __restrict__ rp = (gcint*)S.row_ptr;
-    gcint* __restrict__ col = (gcint*)S.col;
-    gcdouble* __restrict__ val = (gcdouble*)S.val;
-    int eb[RU], ne[RU];
-    int len = 0;
+  };
+  load_offsets(row);
+  load_cols(pa, pb);
+  load_offsets(row + RU * rpp);
+  for (;;) {
+    double xv[RU][CH], av[RU][CH], q[RU][NP > 0 ? NP : 1];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) xv[u][j] = at(X, (unsigned)(cj[u][j] * k + c));
+#pragma unroll
+      for (int j = 0; j < CH; ++j) av[u][j] = val[ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0];
+      if constexpr (NP > 0) pre((unsigned)(min(row + u * rpp, last) * k + c), q[u]);
+    }
+    // the stage's offsets and entry ranges, kept for the sums below
+    int ebc[RU], nec[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) ebc[u] = eb[u], nec[u] = ne[u];
+    const int nrow = row + RU * rpp;
+    load_cols(pa, pb);
+    load_offsets(nrow + RU * rpp);
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int rr = row + u * rpp;
-      eb[u] = 0;
-      ne[u] = 0;
-      if (rr < row1) {
-        eb[u] = rp[rr];
-        ne[u] = rp[rr + 1] - eb[u];
+      if (rr >= row1) break;
+      double z = 0.0;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const double t = z + av[u][j] * xv[u][j];
+        z = j < nec[u] ? t : z;
       }
-      z[u] = 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) len = max(len, ne[u]);
-    for (int o = 0; o < len; o += CH) {
-      int cj[RU][CH];
-      double av[RU][CH], xv[RU][CH];
-#pragma unroll
-      for (int u = 0; u < RU; ++u)
+      // entries past the first CH (rows longer than a step)
+      for (int o = CH; o < nec[u]; o += CH) {
+        int cl[CH];
+        double al[CH], xl[CH];
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-          // a slot past the row's end repeats its last entry; an empty row's
-          // slots gather row 0 and load no entry
-          const int e = ne[u] > 0 ? eb[u] + min(o + j, ne[u] - 1) : -1;
-          cj[u][j] = e >= 0 ? col[e] : 0;
-          av[u][j] = e >= 0 ? val[e] : 0.0;
+          const int e = ebc[u] + min(o + j, nec[u] - 1);
+          cl[j] = col[e];
+          al[j] = val[e];
         }
 #pragma unroll
-      for (int u = 0; u < RU; ++u)
-#pragma unroll
-        for (int j = 0; j < CH; ++j) xv[u][j] = at(X, (unsigned)(cj[u][j] * S.k + c));
-#pragma unroll
-      for (int u = 0; u < RU; ++u)
+        for (int j = 0; j < CH; ++j) xl[j] = at(X, (unsigned)(cl[j] * k + c));
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-          const double t = z[u] + av[u][j] * xv[u][j];
-          z[u] = o + j < ne[u] ? t : z[u];
+          const double t = z + al[j] * xl[j];
+          z = o + j < nec[u] ? t : z;
         }
+      }
+      emit(rr, (unsigned)(rr * k + c), z, q[u]);
     }
+    if (nrow >= row1) break;
+    row = nrow;
   }
 }
 
 enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_EPS2, B_BB, B_NS };
 
-// VU: rows per step of a thread in the vector phases and RU in the sparse
-// products (all their loads issued before any is used); a thread still
-// visits its rows in increasing order, so its partial sums keep their order.
-// CH: entries per step of a row product.
+// VU: rows per step of a thread in the vector phases (all their loads issued
+// before any is used); RU: rows per stage of the sparse products' pipeline;
+// CH: entries per pipelined step of a row product. A thread still visits its
+// rows in increasing order, so its partial sums keep their order.
 template <int BS, int VU, int CH, int RU>
 __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ Gp, const BSys* __restrict__ sys,
                                                      const int32_t* __restrict__ wg_sys) {
@@ -275,23 +311,17 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   // ---- start: r = b - A x0, r0 = r, p = r; partial (r, r), (b, b)
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < k)
-    for (int row = row0 + rsub; row < row1; row += RU * rpp) {
-      double z[RU];
-      rows_product<CH, RU>(S, x, row, rpp, row1, c, z);
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int rr = row + u * rpp;
-        if (rr >= row1) break;
-        const unsigned e = eidx(rr);
-        const double bv = at(b, e);
-        const double res = bv - z[u];
-        at(r, e) = res;
-        at(r0, e) = res;
-        at(p, e) = res;
-        acc[0] += res * res;
-        acc[1] += bv * bv;
-      }
-    }
+    product_rows<CH, RU, 1>(
+        S, x, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(b, e); },
+        [&](int, unsigned e, double z, const double(&q)[1]) {
+          const double bv = q[0];
+          const double res = bv - z;
+          at(r, e) = res;
+          at(r0, e) = res;
+          at(p, e) = res;
+          acc[0] += res * res;
+          acc[1] += bv * bv;
+        });
   store_partials<BS, 2>(S, 0, w, acc, s_w);
   if (!barrier()) return;
   reduce_partials<BS, 2>(S, 0, dsum);
@@ -336,18 +366,12 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     const bool run1 = c < k && st[c] == ST_RUNNING;
     acc[0] = 0.0;
     if (run1)
-      for (int row = row0 + rsub; row < row1; row += RU * rpp) {
-        double z[RU];
-        rows_product<CH, RU>(S, p, row, rpp, row1, c, z);
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int rr = row + u * rpp;
-          if (rr >= row1) break;
-          const unsigned e = eidx(rr);
-          at(v, e) = z[u];
-          acc[0] += z[u] * at(r0, e);
-        }
-      }
+      product_rows<CH, RU, 1>(
+          S, p, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(r0, e); },
+          [&](int, unsigned e, double z, const double(&q)[1]) {
+            at(v, e) = z;
+            acc[0] += z * q[0];
+          });
     store_partials<BS, 1>(S, 1, w, acc, s_w);
     if (!barrier()) return;
     reduce_partials<BS, 1>(S, 1, dsum);
@@ -393,22 +417,15 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     // ---- C: t = A s; phi = (t, s), psi = (t, t), theta = (s, s)
     acc[0] = acc[1] = acc[2] = 0.0;
     if (run2)
-      for (int row = row0 + rsub; row < row1; row += RU * rpp) {
-        double z[RU];
-        rows_product<CH, RU>(S, s, row, rpp, row1, c, z);
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int rr = row + u * rpp;
-          if (rr >= row1) break;
-          const unsigned e = eidx(rr);
-          const double tt = z[u];
-          const double ss = at(s, e);
-          at(t, e) = tt;
-          acc[0] += tt * ss;
-          acc[1] += tt * tt;
-          acc[2] += ss * ss;
-        }
-      }
+      product_rows<CH, RU, 1>(
+          S, s, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(s, e); },
+          [&](int, unsigned e, double tt, const double(&q)[1]) {
+            const double ss = q[0];
+            at(t, e) = tt;
+            acc[0] += tt * ss;
+            acc[1] += tt * tt;
+            acc[2] += ss * ss;
+          });
     store_partials<BS, 3>(S, 2, w, acc, s_w);
     if (!barrier()) return;
     reduce_partials<BS, 3>(S, 2, dsum);
@@ -523,19 +540,17 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   // ---- exit: partial (b - A x, b - A x) and (r, r) per column
   acc[0] = acc[1] = 0.0;
   if (c < k)
-    for (int row = row0 + rsub; row < row1; row += RU * rpp) {
-      double z[RU];
-      rows_product<CH, RU>(S, x, row, rpp, row1, c, z);
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int rr = row + u * rpp;
-        if (rr >= row1) break;
-        const unsigned e = eidx(rr);
-        const double d = at(b, e) - z[u];
-        acc[0] += d * d;
-        acc[1] += at(r, e) * at(r, e);
-      }
-    }
+    product_rows<CH, RU, 2>(
+        S, x, row0 + rsub, rpp, row1, c,
+        [&](unsigned e, double(&q)[2]) {
+          q[0] = at(b, e);
+          q[1] = at(r, e);
+        },
+        [&](int, unsigned e, double z, const double(&q)[2]) {
+          const double d = q[0] - z;
+          acc[0] += d * d;
+          acc[1] += q[1] * q[1];
+        });
   store_partials<BS, 2>(S, 0, w, acc, s_w);
   if (!barrier()) return;
   if (w != 0) return;
@@ -560,13 +575,13 @@ __global__ void batched_reset_kernel(unsigned* bars, int nsys, int* abort_flag) 
 constexpr double kBarrierWaitSeconds = 2.0;
 
 // Kernel variants the tuner chooses from: threads per workgroup, rows per
-// step in the vector phases, entries per step of a row product, rows per
-// step in the sparse products.
+// step in the vector phases, entries per pipelined step of a row product,
+// rows per stage of the sparse products' pipeline.
 struct Variant {
   int block, rows, entries, product_rows;
 };
-constexpr Variant kVariants[] = {{256, 2, 8, 1}, {256, 4, 8, 2}, {512, 2, 8, 1},
-                                 {512, 4, 8, 2}, {512, 4, 4, 4}, {256, 4, 4, 4}};
+constexpr Variant kVariants[] = {{256, 2, 8, 1}, {1024, 2, 8, 1}, {512, 2, 8, 1},
+                                 {512, 4, 8, 1}, {512, 2, 8, 2}, {512, 8, 8, 1}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <int V>
@@ -640,7 +655,7 @@ struct bicgstab_batched_ctx {
   int variant = 1;
   std::vector<int> nw;
   // fixed workspace layout (offsets from base)
-  size_t o_glob = 0, o_sys = 0, o_wg = 0, o_bar = 0, o_res = 0, o_part = 0, bytes_needed = 0;
+  size_t o_glob = 0, o_sys = 0, o_wg = 0, o_dummy = 0, o_bar = 0, o_res = 0, o_part = 0, bytes_needed = 0;
   size_t res_bytes = 0, stage_bytes = 0;
   std::vector<size_t> o_vec;
   char* base = nullptr;
@@ -754,7 +769,8 @@ void compute_layout(bicgstab_batched_ctx* h) {
   h->o_glob = take(sizeof(BGlob));
   h->o_sys = take(sizeof(BSys) * h->nsys);
   h->o_wg = take(4 * (size_t)h->pool_wgs);
-  h->stage_bytes = off;  // [glob][sys][wg map] uploaded at each solve
+  h->o_dummy = take(16);  // a zero entry (column 0, value 0) for systems without entries
+  h->stage_bytes = off;  // [glob][sys][wg map][dummy] uploaded at each solve
   h->o_bar = take(4 * (size_t)h->nsys);
   // results, read back in one copy: iters, status, relres, relres_rec, clocks, abort flag
   h->res_bytes = 4 * h->total_cols * 2 + 8 * h->total_cols * 2 + 16 * (size_t)h->nsys + 8;
@@ -830,8 +846,8 @@ int run(bicgstab_batched_ctx* h, const double* const* b, double* const* x, doubl
     const int kp = next_pow2(h->k[s]);
     BSys& d = S[s];
     d.row_ptr = h->rp[s];
-    d.col = h->col[s];
-    d.val = h->val[s];
+    d.col = h->nnz[s] > 0 ? h->col[s] : (const int32_t*)(h->base + h->o_dummy);
+    d.val = h->nnz[s] > 0 ? h->val[s] : (const double*)(h->base + h->o_dummy + 8);
     d.b = b[s];
     d.x = x[s];
     d.vec = (double*)(h->base + h->o_vec[s]);

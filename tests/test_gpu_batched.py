@@ -138,7 +138,7 @@ def test_batched_tuner_config_and_determinism(lib):
     cfg = bs.config()
     say(f"  best {best:.3f} ms, variant {cfg.variant} {lib.batched.variant_info(cfg.variant)}, "
         f"workgroups {cfg.workgroups.tolist()}")
-    assert cfg.block in (256, 512) and np.all(cfg.workgroups >= 1) and best > 0
+    assert cfg.block == lib.batched.variant_info(cfg.variant)[0] and np.all(cfg.workgroups >= 1) and best > 0
     x1, i1 = bs.solve(btens, tol=1e-8, maxit=3000)
     x2, i2 = bs.solve(btens, tol=1e-8, maxit=3000)
     for s in range(len(systems)):
@@ -161,7 +161,7 @@ def test_batched_single_workgroup_systems(lib):
     """Every system on one workgroup (its passes synchronised by the
     workgroup barrier alone, no device-wide counter), up to 20,000 rows, to
     tol 1e-8: bit for bit the oracle in that configuration's summation order,
-    for a 256- and a 512-lane variant."""
+    for a 1024- and a 512-lane variant."""
     systems, rhs = _batch(8, seed=11, nmin=300, nmax=20000)
     say(f"batched single workgroup: {[(A.n, k) for A, k in systems]}")
     bs = lib.BatchedSolver(systems)
@@ -201,7 +201,7 @@ def test_batched_variants_agree_bitwise(lib):
             by_block[block] = (X, infos)
             _check_bitwise(bs, systems, rhs, X, infos, 1e-9, 2000)
         v += 1
-    assert v >= 2 and len(by_block) == 2
+    assert v >= 2 and len(by_block) >= 2
     bs.close()
 
 
@@ -224,7 +224,10 @@ def test_batched_full_size_64_systems(lib):
     """The batched workload at full size: 64 systems, n log-uniform in
     [1e3, 2e5], k in 1..8, tol 1e-8, tuned. Every column converges with a
     true residual <= 1.1 tol (recomputed on the host); the six smallest
-    systems are checked bit for bit against the oracle."""
+    systems are checked bit for bit against the oracle; four more solves in
+    the same configuration repeat the first bit for bit (a stale read of
+    another workgroup's rows or partials through a barrier, which once showed
+    in about one full-size solve in three, changes the iterates)."""
     import torch
 
     cfg = config_problem(3, seed=0)
@@ -243,4 +246,8 @@ def test_batched_full_size_64_systems(lib):
         assert np.allclose(infos[s].relres_true, rt, rtol=1e-6), s
     small = sorted(range(len(systems)), key=lambda s: systems[s][0].n)[:6]
     _check_bitwise(bs, systems, rhs, X, infos, 1e-8, 5000, which=small)
+    for rep in range(4):
+        xr, ir = bs.solve(btens, tol=1e-8, maxit=5000)
+        for s in range(len(systems)):
+            assert torch.equal(xr[s], xs[s]) and np.array_equal(ir[s].iters, infos[s].iters), (rep, s)
     bs.close()
