@@ -271,7 +271,8 @@ int bicgstab_batched_solve(bicgstab_batched_t h, const double* const* d_b, doubl
  * before (passes x (latency + bytes / (share x per-workgroup bandwidth)),
  * least squares; the smallest makespan whose shares fit the budget). Last,
  * the best allocation thinned: every share divided by 2, 4, 8 and 16 (at
- * least one workgroup each). Keeps the fastest configuration. d_x holds the initial guesses on input (restored
+ * least one workgroup each), stopping at the first thinning that is not
+ * faster. Keeps the fastest configuration. d_x holds the initial guesses on input (restored
  * before every trial) and the solution of the chosen configuration on output.
  * best_ms: that configuration's kernel time (may be NULL). */
 int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double* const* d_x, double tol,

@@ -1130,10 +1130,12 @@ int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double
     rc = tune_allocation(bv, h->cap[bv] / div);
   }
   // the best allocation thinned: every system on 1/2 .. 1/16 of its
-  // workgroups (at least one). A pass's barriers cost more the more
-  // workgroups they join, so a system whose passes are short can finish
-  // sooner on fewer (a 4,096-row system alone: 18.5 us per pass on 8
-  // workgroups, 41.5 on the 64 its row count allows)
+  // workgroups (at least one), until a thinning is not faster. A pass's
+  // barriers cost more the more workgroups they join, so a system whose
+  // passes are short can finish sooner on fewer (a 4,096-row system alone:
+  // 18.5 us per pass on 8 workgroups, 41.5 on the 64 its row count allows);
+  // a batch of large systems only slows down (and 1/16 of its workgroups
+  // would take seconds)
   const std::vector<int> base = best_nw;
   const int base_variant = best_variant;
   for (int div : {2, 4, 8, 16}) {
@@ -1144,7 +1146,10 @@ int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double
       h->nw[s] = std::max(1, base[s] / div);
       changed |= h->nw[s] != base[s];
     }
-    if (changed) rc = trial();
+    if (!changed) break;
+    const double before = best;
+    rc = trial();
+    if (!(best < before)) break;
   }
   h->variant = best_variant;
   h->nw = best_nw;
