@@ -265,7 +265,8 @@ int bicgstab_batched_set_stream(bicgstab_batched_t h, void* stream);
 int bicgstab_batched_solve(bicgstab_batched_t h, const double* const* d_b, double* const* d_x, double tol,
                            int32_t maxit, bicgstab_info* info);
 /* Autotuner: times the batch under every kernel variant at its full resident
- * capacity, then the best variant at half and a quarter of it; for each, the
+ * capacity, then the best variant at half and (if half was faster) a quarter
+ * of it; for each, the
  * shares are first proportional to measured work (bytes per pass x passes)
  * and then twice re-derived from a per-system time model fitted to the run
  * before (passes x (latency + bytes / (share x per-workgroup bandwidth)),

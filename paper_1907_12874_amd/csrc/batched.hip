@@ -1123,11 +1123,13 @@ int bicgstab_batched_tune(bicgstab_batched_t h, const double* const* d_b, double
   if (!rc) rc = trial();
   // every variant at its full resident capacity
   for (int v = 0; v < kNumVariants && !rc; ++v) rc = tune_allocation(v, h->cap[v]);
-  // the best variant at smaller budgets
+  // the best variant at smaller budgets, until one is not faster
   const int bv = best_variant;
   for (int div : {2, 4}) {
     if (rc) break;
+    const double before = best;
     rc = tune_allocation(bv, h->cap[bv] / div);
+    if (!(best < before)) break;
   }
   // the best allocation thinned: every system on 1/2 .. 1/16 of its
   // workgroups (at least one), until a thinning is not faster. A pass's
