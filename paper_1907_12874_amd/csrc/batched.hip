@@ -47,7 +47,7 @@ struct BSys {
   double* out_relres_rec;
   unsigned* bar;
   unsigned long long* clk;  // [2]: wall clock at start / end of the system
-  int n, k, kpl, nw, w0, pad;
+  int n, k, kpl, nw, w0, maxlen;  // maxlen: entries of the system's longest row
 };
 
 struct BGlob {
@@ -183,8 +183,8 @@ __device__ __forceinline__ T& at(T* base, unsigned e) {
 // entry 0 (a system without entries points at a zero dummy entry) and add
 // nothing.
 template <int CH, int RU, int NP, class Pre, class Emit>
-__device__ __forceinline__ void product_rows(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
-                                             int row1, int c, Pre pre, Emit emit) {
+__device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
+                                                int row1, int c, Pre pre, Emit emit) {
   if (row >= row1) return;
   gcint* __restrict__ rp = (gcint*)S.row_ptr;
   gcint* __restrict__ col = (gcint*)S.col;
@@ -265,6 +265,22 @@ __device__ __forceinline__ void product_rows(const BSys& S, const gdouble* __res
     if (nrow >= row1) break;
     row = nrow;
   }
+}
+
+// The product with CH pipelined slots at most: fewer when no row of the
+// system has more entries (5 for a 5-point, 7 for a 7-point stencil), so no
+// slot is spent on padding every row shares. The sums are the same (a slot
+// past a row's end is never added).
+template <int CH, int RU, int NP, class Pre, class Emit>
+__device__ __forceinline__ void product_rows(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
+                                             int row1, int c, Pre pre, Emit emit) {
+  if constexpr (CH > 5) {
+    if (S.maxlen <= 5) return product_rows_ch<5, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
+  }
+  if constexpr (CH > 7) {
+    if (S.maxlen <= 7) return product_rows_ch<7, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
+  }
+  product_rows_ch<CH, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
 }
 
 enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_EPS2, B_BB, B_NS };
@@ -640,6 +656,7 @@ int log2i(int p) {
 struct bicgstab_batched_ctx {
   int nsys = 0;
   std::vector<int64_t> n, nnz;
+  std::vector<int> maxlen;  // entries of each system's longest row
   std::vector<int> k;
   std::vector<const int32_t*> rp, col;
   std::vector<const double*> val;
@@ -863,7 +880,7 @@ int run(bicgstab_batched_ctx* h, const double* const* b, double* const* x, doubl
     d.kpl = log2i(kp);
     d.nw = h->nw[s];
     d.w0 = w0;
-    d.pad = 0;
+    d.maxlen = h->maxlen[s];
     for (int q = 0; q < d.nw; ++q) wg[w0 + q] = s;
     w0 += d.nw;
     col0 += h->k[s];
@@ -976,6 +993,9 @@ int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t n
     }
     h->n.push_back(A.n);
     h->nnz.push_back(A.nnz);
+    int ml = 0;
+    for (int64_t i = 0; i < A.n; ++i) ml = std::max(ml, rp[i + 1] - rp[i]);
+    h->maxlen.push_back(ml);
     h->k.push_back(ks[s]);
     h->rp.push_back(A.d_row_ptr);
     h->col.push_back(A.d_col_idx);
