@@ -247,8 +247,9 @@ int bicgstab_destroy(bicgstab_t h);
  * shares, not on the other variant parameters, and repeat bit for bit. */
 typedef struct bicgstab_batched_ctx* bicgstab_batched_t;
 
-/* As[s]: the matrix of system s (n >= 1; pattern validated on the host, the
- * arrays must outlive the handle); ks[s] in [1, BICGSTAB_MAX_K]. nsys >= 1. */
+/* As[s]: the matrix of system s (1 <= n < 2^24, nnz < 2^29, n * k * 8 < 2^31;
+ * pattern validated on the host, the arrays must outlive the handle); ks[s]
+ * in [1, BICGSTAB_MAX_K]. nsys >= 1. Anything else: BICGSTAB_EINVAL. */
 int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, void* stream,
                             bicgstab_batched_t* out);
 /* Device workspace in bytes: six n_s x k_s Krylov blocks per system, the

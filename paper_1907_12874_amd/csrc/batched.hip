@@ -58,6 +58,29 @@ struct BGlob {
   int* abort_flag;
 };
 
+// Global-memory views of the arrays: pointers read from the descriptors are
+// generic; as global pointers the loads take a uniform base and a 32-bit
+// offset.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) const int32_t gcint;
+typedef __attribute__((address_space(1))) char gchar;
+
+// Element e of a global array through a 32-bit byte offset (every array of a
+// system fits in 32 bits: n * k * 8 < 2^31 and nnz < 2^29, checked at create;
+// the partials take a few MB), so the load or store takes a uniform base and
+// no 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ T& at(T* base, unsigned e) {
+  return *(T*)((gchar*)base + e * (unsigned)sizeof(T));
+}
+
+// Element (j, c) of a row-major n x k block: j * k + c with a 24-bit multiply
+// (a full-rate instruction; n < 2^24 and k <= 64 are checked at create).
+__device__ __forceinline__ unsigned xoff(int j, int k, int c) {
+  return __umul24((unsigned)j, (unsigned)k) + (unsigned)c;
+}
+
 // Barrier over the nw workgroups of one system: a monotonic counter; the
 // barrier with ordinal e completes when the counter reaches (e + 1) * nw.
 // Every wave first waits for its own stores to complete, then one thread
@@ -122,7 +145,7 @@ __device__ void store_partials(const BSys& S, int slot, int w, const double (&ac
     double v = s_w[0][d][c];
 #pragma unroll
     for (int q = 1; q < BS / 64; ++q) v += s_w[q][d][c];
-    S.part[((size_t)(slot * S.nw + w) * 4 + d) * kp + c] = v;
+    at((gdouble*)S.part, (unsigned)(((slot * S.nw + w) * 4 + d) * kp + c)) = v;
   }
 }
 
@@ -138,28 +161,14 @@ __device__ void reduce_partials(const BSys& S, int slot, double (*out)[kMaxK]) {
     for (int q0 = 0; q0 < S.nw; q0 += 16) {
       double pv[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) pv[j] = S.part[((size_t)(slot * S.nw + min(q0 + j, S.nw - 1)) * 4 + d) * kp + c];
+      for (int j = 0; j < 16; ++j)
+        pv[j] = at((gcdouble*)S.part, (unsigned)(((slot * S.nw + min(q0 + j, S.nw - 1)) * 4 + d) * kp + c));
 #pragma unroll
       for (int j = 0; j < 16; ++j) v = q0 + j < S.nw ? v + pv[j] : v;
     }
     out[d][c] = v;
   }
   __syncthreads();
-}
-
-// Global-memory views of the arrays: pointers read from the descriptors are
-// generic; as global pointers the loads take a uniform base and a 32-bit
-// offset.
-typedef __attribute__((address_space(1))) double gdouble;
-typedef __attribute__((address_space(1))) const double gcdouble;
-typedef __attribute__((address_space(1))) const int32_t gcint;
-typedef __attribute__((address_space(1))) char gchar;
-
-// Element e of a global array through a 32-bit byte offset (array bytes fit in
-// 31 bits, checked at create), so the load or store takes a uniform base.
-template <class T>
-__device__ __forceinline__ T& at(T* base, unsigned e) {
-  return *(T*)((gchar*)base + e * (unsigned)sizeof(T));
 }
 
 // Sparse products: (A X)[row, c] for the rows row, row + rpp, ... below row1
@@ -201,15 +210,15 @@ __device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __
       eb[u] = a[u];
       ne[u] = b[u] - a[u];
 #pragma unroll
-      for (int j = 0; j < CH; ++j) cj[u][j] = col[ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0];
+      for (int j = 0; j < CH; ++j) cj[u][j] = at(col, (unsigned)(ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0));
     }
   };
   auto load_offsets = [&](int r) {
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int rr = min(r + u * rpp, last);
-      pa[u] = rp[rr];
-      pb[u] = rp[rr + 1];
+      pa[u] = at(rp, (unsigned)rr);
+      pb[u] = at(rp, (unsigned)rr + 1u);
     }
   };
   load_offsets(row);
@@ -220,10 +229,10 @@ __device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
 #pragma unroll
-      for (int j = 0; j < CH; ++j) xv[u][j] = at(X, (unsigned)(cj[u][j] * k + c));
+      for (int j = 0; j < CH; ++j) xv[u][j] = at(X, xoff(cj[u][j], k, c));
 #pragma unroll
-      for (int j = 0; j < CH; ++j) av[u][j] = val[ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0];
-      if constexpr (NP > 0) pre((unsigned)(min(row + u * rpp, last) * k + c), q[u]);
+      for (int j = 0; j < CH; ++j) av[u][j] = at(val, (unsigned)(ne[u] > 0 ? eb[u] + min(j, ne[u] - 1) : 0));
+      if constexpr (NP > 0) pre(xoff(min(row + u * rpp, last), k, c), q[u]);
     }
     // the stage's offsets and entry ranges, kept for the sums below
     int ebc[RU], nec[RU];
@@ -249,18 +258,18 @@ __device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           const int e = ebc[u] + min(o + j, nec[u] - 1);
-          cl[j] = col[e];
-          al[j] = val[e];
+          cl[j] = at(col, (unsigned)e);
+          al[j] = at(val, (unsigned)e);
         }
 #pragma unroll
-        for (int j = 0; j < CH; ++j) xl[j] = at(X, (unsigned)(cl[j] * k + c));
+        for (int j = 0; j < CH; ++j) xl[j] = at(X, xoff(cl[j], k, c));
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           const double t = z + al[j] * xl[j];
           z = o + j < nec[u] ? t : z;
         }
       }
-      emit(rr, (unsigned)(rr * k + c), z, q[u]);
+      emit(rr, xoff(rr, k, c), z, q[u]);
     }
     if (nrow >= row1) break;
     row = nrow;
@@ -321,7 +330,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   unsigned epoch = 0;
   auto barrier = [&]() { return sys_barrier(S.bar, (++epoch) * (unsigned)S.nw, G.abort_flag, G.wait_ticks, S.nw); };
   // element offsets fit in 32 bits (checked at create): uniform base + 32-bit offset addressing
-  auto eidx = [&](int row) { return (unsigned)(row * k + c); };
+  auto eidx = [&](int row) { return xoff(row, k, c); };
   if (w == 0 && threadIdx.x == 0) S.clk[0] = wall_clock64();
 
   // ---- start: r = b - A x0, r0 = r, p = r; partial (r, r), (b, b)
@@ -970,12 +979,14 @@ int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t n
   h->user_stream = (hipStream_t)stream;
   for (int s = 0; s < nsys; ++s) {
     const bicgstab_csr& A = As[s];
-    // element offsets of the n x k blocks are 32-bit byte offsets in the kernel
-    if (A.n < 1 || A.nnz < 0 || A.nnz >= ((int64_t)1 << 31) || ks[s] < 1 || ks[s] > BICGSTAB_MAX_K ||
-        A.n * (int64_t)ks[s] * 8 >= ((int64_t)1 << 31) || !A.d_row_ptr ||
+    // element offsets of the n x k blocks and of the CSR arrays are 32-bit
+    // byte offsets in the kernel, and row indices go through 24-bit multiplies
+    if (A.n < 1 || A.n >= ((int64_t)1 << 24) || A.nnz < 0 || A.nnz >= ((int64_t)1 << 29) || ks[s] < 1 ||
+        ks[s] > BICGSTAB_MAX_K || A.n * (int64_t)ks[s] * 8 >= ((int64_t)1 << 31) || !A.d_row_ptr ||
         (A.nnz > 0 && (!A.d_col_idx || !A.d_values))) {
       destroy_ctx(h);
-      return bfail(BICGSTAB_EINVAL, "system " + std::to_string(s) + ": invalid matrix or k (or n*k*8 >= 2^31)");
+      return bfail(BICGSTAB_EINVAL, "system " + std::to_string(s) +
+                                        ": invalid matrix or k (n >= 2^24, nnz >= 2^29 or n*k*8 >= 2^31)");
     }
     // validate the pattern on the host: no kernel may index out of bounds
     std::vector<int32_t> rp((size_t)A.n + 1), cols((size_t)A.nnz);
