@@ -239,12 +239,14 @@ int bicgstab_destroy(bicgstab_t h);
  * BICGSTAB_EUNSUPPORTED. A barrier that waits longer than 2 s aborts the whole
  * launch (every workgroup exits) and the solve returns BICGSTAB_EHIP.
  *
- * Per system, each dot product is summed in a fixed order: per thread over its
- * rows (a stride of block / kp rows through the workgroup's contiguous chunk of
- * ceil(n / share) rows, kp = k rounded up to a power of two), a pairwise tree
- * over the row slots of a 64-wide wavefront, the wavefronts in index order,
- * then the workgroups in index order. Results depend on the block size and the
- * shares, not on the other variant parameters, and repeat bit for bit. */
+ * Per system, each dot product is summed in a fixed order: a 64-wide
+ * wavefront holds floor(64 / k) rows of k lanes; per thread over its rows (a
+ * stride of (block / 64) * floor(64 / k) rows through the workgroup's
+ * contiguous chunk of ceil(n / share) rows), a pairwise tree over the row
+ * slots of a wavefront (adjacent slots first, an odd last slot passed up
+ * unpaired), the wavefronts in index order, then the workgroups in index
+ * order. Results depend on the block size and the shares, not on the other
+ * variant parameters, and repeat bit for bit. */
 typedef struct bicgstab_batched_ctx* bicgstab_batched_t;
 
 /* As[s]: the matrix of system s (1 <= n < 2^24, nnz < 2^29, n * k * 8 < 2^31;

@@ -126,22 +126,36 @@ __device__ bool sys_barrier(unsigned* bar, unsigned target, int* abort_flag, lon
 }
 
 // Per-column partial sums of ND dots over this workgroup's rows, in a fixed
-// order (lanes of a column by xor shuffles, then the waves in index order),
-// stored to the system's partial slot.
+// order, stored to the system's partial slot. A wavefront holds rpw = 64 / k
+// rows of k lanes (lane = row slot * k + column); its slots are added by a
+// pairwise tree, adjacent slots first (slot s takes slot s + off when s is a
+// multiple of 2 off and s + off < rpw: an odd last slot passes up unpaired),
+// then the wavefronts in index order.
 template <int BS, int ND>
 __device__ void store_partials(const BSys& S, int slot, int w, const double (&acc)[4],
                                double (*s_w)[4][kMaxK]) {
   const int kp = 1 << S.kpl;
+  const int k = S.k, rpw = 64 / k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rs = lane / k;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double v = acc[d];
-    for (int off = kp; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if (lane < kp) s_w[wave][d][lane] = v;
+    if ((k & (k - 1)) == 0) {
+      // k a power of two: the same tree by xor shuffles (every slot ends
+      // with the sum its leader gets)
+      for (int off = k; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    } else {
+      for (int off = 1; off < rpw; off <<= 1) {
+        const double o = __shfl(v, min(lane + off * k, 63), 64);
+        if ((rs & (2 * off - 1)) == 0 && rs + off < rpw) v += o;
+      }
+    }
+    if (lane < k) s_w[wave][d][lane] = v;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < ND * kp; t += BS) {
-    const int d = t / kp, c = t - d * kp;
+  for (int t = threadIdx.x; t < ND * k; t += BS) {
+    const int d = t / k, c = t - d * k;
     double v = s_w[0][d][c];
 #pragma unroll
     for (int q = 1; q < BS / 64; ++q) v += s_w[q][d][c];
@@ -153,8 +167,8 @@ __device__ void store_partials(const BSys& S, int slot, int w, const double (&ac
 template <int BS, int ND>
 __device__ void reduce_partials(const BSys& S, int slot, double (*out)[kMaxK]) {
   const int kp = 1 << S.kpl;
-  for (int t = threadIdx.x; t < ND * kp; t += BS) {
-    const int d = t / kp, c = t - d * kp;
+  for (int t = threadIdx.x; t < ND * S.k; t += BS) {
+    const int d = t / S.k, c = t - d * S.k;
     double v = 0.0;
     // 16 partials loaded at once (not one dependent load per workgroup),
     // then added in workgroup order
@@ -306,9 +320,14 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   const BSys S = sys[sidx];
   const int w = blockIdx.x - S.w0;
   const int kp = 1 << S.kpl;
-  const int c = threadIdx.x & (kp - 1);
-  const int rsub = threadIdx.x >> S.kpl;
-  const int rpp = BS >> S.kpl;
+  // a wavefront holds 64 / k rows of k lanes (lane = row slot * k + column);
+  // the lanes past the last whole row take no row (c = k)
+  const int rpw = 64 / S.k;
+  const int lane = threadIdx.x & 63;
+  const int rslot = min(lane / S.k, rpw - 1);
+  const int c = lane / S.k < rpw ? lane - rslot * S.k : S.k;
+  const int rsub = (threadIdx.x >> 6) * rpw + rslot;
+  const int rpp = (BS / 64) * rpw;
   const int n = S.n, k = S.k;
   const size_t nk = (size_t)n * k;
   const int chunk = (n + S.nw - 1) / S.nw;

@@ -24,9 +24,12 @@ def _pad_pow2(k):
 
 
 def _wave_tree(t):
-    """Pairwise tree over the last axis (the row slots of a wave, xor shuffles)."""
+    """Pairwise tree over the last axis (the row slots of a wave): adjacent
+    slots first; with an odd count the last slot passes up unpaired."""
     while t.shape[-1] > 1:
-        t = t[..., 0::2] + t[..., 1::2]
+        odd = t.shape[-1] % 2
+        pairs = t[..., 0:t.shape[-1] - odd:2] + t[..., 1::2]
+        t = np.concatenate([pairs, t[..., -1:]], axis=-1) if odd else pairs
     return t[..., 0]
 
 
@@ -62,12 +65,14 @@ def group_dot(n, k, grid_cap=512, block=256, fin_lanes=16):
 
 def batched_dot(n, k, nw, block):
     """Dot of two length-n columns as the batched kernel computes it for a
-    system of n rows and k columns on nw workgroups of `block` threads: per
-    thread over its rows (a stride of block / kp rows through the workgroup's
-    contiguous chunk of ceil(n / nw) rows), a pairwise tree over the row slots
-    of a wave, the waves in order, then the workgroups in order."""
-    kp = _pad_pow2(k)
-    rpp, slots, waves = block // kp, 64 // kp, block // 64
+    system of n rows and k columns on nw workgroups of `block` threads: a
+    wave holds 64 // k rows of k lanes; per thread over its rows (a stride of
+    (block / 64) * (64 // k) rows through the workgroup's contiguous chunk of
+    ceil(n / nw) rows), a pairwise tree over the row slots of a wave (adjacent
+    first, an odd last slot unpaired), the waves in order, then the
+    workgroups in order."""
+    slots, waves = 64 // k, block // 64
+    rpp = waves * slots
     chunk = (n + nw - 1) // nw
     m = (chunk + rpp - 1) // rpp
 

@@ -50,3 +50,48 @@ def test_epilogue_dot_uniform_and_ragged_blocks():
                  (conv_diff(13, 3, (0.3, 0.2, 0.1)), 32), (random_sparse(3001, 9, seed=1), 8)):
         u, w = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
         assert spmm_epilogue_dot(A.row_ptr, k)(u, w) == _loop_epilogue_dot(A.row_ptr, k, u, w)
+
+
+def _loop_batched_dot(n, k, nw, block, u, w):
+    """The batched kernel's dot order written out lane by lane: lane l of
+    wave q holds row slot l // k, column l % k (lanes past 64 // k whole rows
+    idle); each thread adds its rows in order; the shuffle tree adds slot
+    s + off into slot s when s is a multiple of 2 off and s + off < 64 // k;
+    the waves and then the workgroups are added in order."""
+    rpw = 64 // k
+    waves = block // 64
+    rpp = waves * rpw
+    chunk = -(-n // nw)
+    p = u * w
+    tot = 0.0
+    for g in range(nw):
+        r0, r1 = min(n, g * chunk), min(n, (g + 1) * chunk)
+        wave_sums = []
+        for q in range(waves):
+            lanes = [0.0] * rpw
+            for s in range(rpw):
+                for r in range(r0 + q * rpw + s, r1, rpp):
+                    lanes[s] += p[r]
+            off = 1
+            while off < rpw:
+                for s in range(0, rpw, 2 * off):
+                    if s + off < rpw:
+                        lanes[s] = lanes[s] + lanes[s + off]
+                off *= 2
+            wave_sums.append(lanes[0])
+        v = wave_sums[0]
+        for x in wave_sums[1:]:
+            v += x
+        tot += v
+    return tot
+
+
+def test_batched_dot_model_matches_lane_loop():
+    from kernel_order import batched_dot
+
+    rng = np.random.default_rng(3)
+    for k in range(1, 9):
+        for n, nw, block in ((1000, 3, 256), (4093, 5, 512), (777, 1, 1024)):
+            u = rng.standard_normal(n)
+            w = rng.standard_normal(n)
+            assert batched_dot(n, k, nw, block)(u, w) == _loop_batched_dot(n, k, nw, block, u, w), (k, n, nw, block)
