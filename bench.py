@@ -12,7 +12,7 @@ form at k = 32, in RHS-iterations per second (sum over columns of the passes
 each column ran, divided by the step time).
 
 Output: the full report (every section below) is written as JSON to
---report (default gpurun_out/bench_report.json); stdout gets ONE compact JSON
+--report (default reports/bench_report.json); stdout gets ONE compact JSON
 line (under 4 KB) with the contract's keys and a summary of each section.
 Progress lines go to stderr.
 
@@ -878,7 +878,7 @@ def main():
     ap.add_argument("--no-tab4", action="store_true", help="skip Table 4 on the GPU (200^3 Poisson)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 2D system (k = 1, launch-bound)")
     ap.add_argument("--no-seeds", action="store_true", help="skip the headline solve on input seeds 1 and 2")
-    ap.add_argument("--report", default=os.path.join(ROOT, "gpurun_out", "bench_report.json"),
+    ap.add_argument("--report", default=os.path.join(ROOT, "reports", "bench_report.json"),
                     help="where the full report goes (JSON); stdout gets one compact line")
     ap.add_argument("--profile-run", choices=("fp64", "fp32_refine", "batched", "random"),
                     help="run one workload after a warm-up and exit without the JSON line (the command behind "

@@ -125,7 +125,7 @@ def _full_size_report():
         "cpu_baseline": {"value": 33.357, "unit": "RHS-iterations/s", "cores": 1, "kind": "oracle",
                          "sample": "classical/merged/jacobi, column 0 of the same workload, 200 fixed passes (stop test "
                                    "off), 15.0 s; NumPy/SciPy FP64 limited to 1 thread (host has 256 logical CPUs)"},
-        "report": "gpurun_out/bench_report.json",
+        "report": "reports/bench_report.json",
     }
 
 
