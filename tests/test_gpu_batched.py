@@ -123,6 +123,35 @@ def test_batched_edges_bitwise(lib):
     _check_bitwise(bs0, systems, rhs, X0, inf0, 1e-10, 0, x0s=x0s)
 
 
+def test_batched_empty_rows_and_empty_matrix(lib):
+    """Rows without entries and a matrix without any (no column index or
+    value array at all: the kernel reads a zero dummy entry): a scaled
+    identity with two empty rows whose right-hand side is zero there
+    converges in one pass; the zero matrix gives the zero solution for a zero
+    right-hand side and BREAKDOWN after one pass (delta = 0) for another one;
+    all bit for bit the oracle in the kernel's order."""
+    n4 = 40
+    keep = np.array([i not in (5, 17) for i in range(n4)])
+    rp4 = np.concatenate([[0], np.cumsum(keep)]).astype(np.int32)
+    cols4 = np.nonzero(keep)[0].astype(np.int32)
+    A4 = CSR(n4, rp4, cols4, np.full(cols4.size, 3.0))
+    b4 = np.random.default_rng(6).uniform(-1, 1, (n4, 2))
+    b4[~keep] = 0.0
+    n5 = 64
+    A5 = CSR(n5, np.zeros(n5 + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    b5 = np.zeros((n5, 2))
+    b5[:, 1] = np.random.default_rng(7).uniform(-1, 1, n5)
+    systems = [(A4, 2), (A5, 2)]
+    rhs = [b4, b5]
+    say("batched empty rows / empty matrix")
+    bs, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-10, maxit=50)
+    _check_bitwise(bs, systems, rhs, X, infos, 1e-10, 50)
+    assert np.all(infos[0].status == oracle.CONVERGED) and list(infos[0].iters) == [1, 1]
+    assert list(infos[1].status) == [oracle.CONVERGED, oracle.BREAKDOWN] and list(infos[1].iters) == [0, 1]
+    assert np.all(X[1][:, 0] == 0)
+    bs.close()
+
+
 def test_batched_tuner_config_and_determinism(lib):
     """The tuner returns a valid configuration whose solves are bitwise
     reproducible and bitwise the oracle's in that configuration's summation
