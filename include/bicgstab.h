@@ -190,6 +190,20 @@ int bicgstab_update_values(bicgstab_t h, const double* d_values);
  * handle's stream, asynchronous. For kernel-level checks and timing. */
 int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y);
 
+/* How the plain FP64 product (Section 3.1's SpMM; the product of the merged
+ * and basic forms and of bicgstab_spmm) stores A. When the pattern is a 3D
+ * grid in natural order (x fastest) whose entries couple each row only to rows
+ * one step away in x, y and z (7- and 27-point stencils), k = 32 (row blocks
+ * of 32 rows) and the grid divides into 2 x 4 x 4 tiles, create keeps a
+ * library-owned copy of A with its rows tile by tile (one tile per row block)
+ * and the product writes each row of Y at its own index: the same sums,
+ * bitwise, with fewer row blocks sharing a row's neighbours. tile = {tz, ty,
+ * tx}, grid = {nz, ny, nx}, all zero when A is stored row by row (other
+ * patterns, other k, the FP32 tier, products with dot epilogues, the
+ * environment variable BICGSTAB_SPMM_TILE=0 at create). Either pointer may be
+ * NULL. */
+int bicgstab_product_layout(bicgstab_t h, int32_t* tile, int32_t* grid);
+
 /* Per-iteration history of the last solve: for iteration j < count and column
  * c, hist[(j*k + c)*4 + {0,1,2,3}] = alpha_j, omega_j, rho_j, stop estimate_j.
  * Call with hist = NULL to get the count; cap = entries of 4 doubles. */

@@ -66,6 +66,7 @@ def lib():
     L.bicgstab_grad_values.argtypes = [H, vp, vp, vp]
     L.bicgstab_update_values.argtypes = [H, C.c_void_p]
     L.bicgstab_spmm.argtypes = [H, vp, vp]
+    L.bicgstab_product_layout.argtypes = [H, C.POINTER(i32), C.POINTER(i32)]
     L.bicgstab_history.argtypes = [H, C.POINTER(dbl), i32, C.POINTER(i32)]
     L.bicgstab_last_solve_stats.argtypes = [H, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.bicgstab_refine_outer.argtypes = [H, C.POINTER(i32)]
@@ -109,5 +110,5 @@ def exported_symbols():
         "bicgstab_batched_set_workspace", "bicgstab_batched_set_stream", "bicgstab_batched_solve",
         "bicgstab_batched_tune", "bicgstab_batched_get_config", "bicgstab_batched_set_config",
         "bicgstab_batched_variant_info", "bicgstab_batched_destroy", "bicgstab_axpby_tab1",
-        "bicgstab_solve_noalloc",
+        "bicgstab_solve_noalloc", "bicgstab_product_layout",
     ]

@@ -24,6 +24,7 @@ struct SpmmMat {
   int rows_cap;  // rows of the largest row block
   int xcd_chunk; // consecutive row blocks given to one XCD (1: plain round-robin order)
   double* bpart; // per-row-block partial sums of a product with a dot epilogue (nblk x 3k)
+  const int32_t* rowmap = nullptr;  // stored row i is row rowmap[i] of Y (nullptr: the same row)
 };
 
 struct SpmmPartition {

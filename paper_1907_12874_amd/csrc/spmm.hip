@@ -172,6 +172,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
   T* s_red = s_val + A.nnz_cap;
   int* s_col = reinterpret_cast<int*>(s_red + CPL * BS);
   int* s_rp = s_col + A.nnz_cap;
+  int* s_map = s_rp + A.rows_cap + 1;  // rows of Y when the stored rows are permuted
   const int r0 = A.blk[L], r1 = A.blk[L + 1];
   const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
   const int ne = e1 - e0;
@@ -187,9 +188,12 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
       s_val[i] = val[e0 + i];
     }
     for (int i = threadIdx.x; i <= r1 - r0; i += BS) s_rp[i] = A.row_ptr[r0 + i] - e0;
+    if (A.rowmap)
+      for (int i = threadIdx.x; i < r1 - r0; i += BS) s_map[i] = A.rowmap[r0 + i];
     __syncthreads();
     if (c >= k) return;
     const int nr = r1 - r0;
+    auto yrow = [&](int r) { return A.rowmap ? s_map[r] : r0 + r; };
     if constexpr (CPL > 1) {
       typedef typename VecOf<T, CPL>::type V;
       for (int r = rsub; r < nr; r += rpp) {
@@ -233,7 +237,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
             }
           }
         }
-        store_y<T, CPL>(Y, r0 + r, k, c, sv);
+        store_y<T, CPL>(Y, yrow(r), k, c, sv);
         epi(r0 + r, sv);
       }
     } else {
@@ -299,11 +303,11 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
           }
         }
         const T outA[1] = {sumA};
-        store_y<T, 1>(Y, r0 + r, k, c, outA);
+        store_y<T, 1>(Y, yrow(r), k, c, outA);
         epi(r0 + r, outA);
         if (has_b) {
           const T outB[1] = {sumB};
-          store_y<T, 1>(Y, r0 + rb, k, c, outB);
+          store_y<T, 1>(Y, yrow(rb), k, c, outB);
           epi(r0 + rb, outB);
         }
       }
@@ -344,7 +348,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
         for (int g = 0; g < rpp; ++g) v += s_red[h * BS + g * lpr + threadIdx.x];
         out[h] = v;
       }
-      store_y<T, CPL>(Y, r0, k, c, out);
+      store_y<T, CPL>(Y, A.rowmap ? A.rowmap[r0] : r0, k, c, out);
       epi(r0, out);
     }
   }
@@ -424,7 +428,7 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
-                     (size_t)(A.rows_cap + 1) * 4 + 16;
+                     (size_t)(A.rows_cap + 1) * 4 + (A.rowmap ? (size_t)A.rows_cap * 4 : 0) + 16;
   if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
 #define SPMM_CASE(KP, KPL)                                                                                         \
@@ -451,7 +455,7 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, T* yh
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
-                     (size_t)(A.rows_cap + 1) * 4 + 16;
+                     (size_t)(A.rows_cap + 1) * 4 + (A.rowmap ? (size_t)A.rows_cap * 4 : 0) + 16;
   if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
 #define SPMM_DOT_CASE(KP, KPL)                                                                                    \
@@ -583,6 +587,9 @@ hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void*
                            const Globals* glob, hipStream_t s, bool defer) {
   if (epi < 0 || epi >= E_NUM || (epilogue_dots(epi) > 0 && !W) || (epilogue_prec(epi) && (!Yh || !diag)))
     return hipErrorInvalidValue;
+  // the epilogue's partials follow the stored row order, which its fixed
+  // summation order assumes to be the rows' own
+  if (A.rowmap) return hipErrorInvalidValue;
   const int P = epilogue_dots(epi) * k;
   if (P > 256) return hipErrorInvalidValue;  // one thread per pair in reduce_runs_kernel
   const int G = spmm_dot_runs(A.nblk);

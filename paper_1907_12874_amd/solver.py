@@ -180,6 +180,14 @@ class Solver:
             check(lib().bicgstab_spmm(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr())), "bicgstab_spmm")
         return Y
 
+    def product_layout(self):
+        """(tile (tz, ty, tx), grid (nz, ny, nx)) of the tile-ordered storage the
+        plain product uses, or zeros when A is stored row by row."""
+        t = (C.c_int32 * 3)()
+        g = (C.c_int32 * 3)()
+        check(lib().bicgstab_product_layout(self._h, t, g), "bicgstab_product_layout")
+        return tuple(t), tuple(g)
+
     def history(self):
         """(iterations, k, 4) array of alpha, omega, rho, stop estimate."""
         cnt = C.c_int32()

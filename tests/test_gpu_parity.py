@@ -74,6 +74,55 @@ def test_spmm_bitwise(lib, k):
     assert np.array_equal(Y, S @ X)
 
 
+@pytest.mark.parametrize("k", [32])
+def test_tiled_product_matches_row_order(lib, k):
+    """A 3D grid matrix (7-point 24^3, 27-point 16^3 with random values) at
+    k = 32 is stored tile by tile for the plain product (its layout
+    reported), and that product equals SciPy's CSR product and the row-ordered
+    one (BICGSTAB_SPMM_TILE=0 at create) bit for bit; so do a classical merged
+    Jacobi solve's pass counts and iterates; after update_values the tiled
+    copy carries the new values; a random matrix, and the grid at k = 16, are
+    not tiled."""
+    import os
+    import torch
+
+    from workloads.generators import random_27pt
+
+    say(f"tiled product k={k}")
+    rng = np.random.default_rng(40 + k)
+    for A, grid in ((conv_diff(24, 3, (1.0, 0.7, 0.3)), (24, 24, 24)), (random_27pt(16, seed=3), (16, 16, 16))):
+        X = torch.from_numpy(rng.uniform(-1, 1, (A.n, k))).cuda()
+        st = gpu_solver(lib, A, k, precond="jacobi")
+        tile, g = st.product_layout()
+        assert g == grid and tile == (2, 4, 4), (tile, g)
+        os.environ["BICGSTAB_SPMM_TILE"] = "0"
+        try:
+            sr = gpu_solver(lib, A, k, precond="jacobi")
+        finally:
+            del os.environ["BICGSTAB_SPMM_TILE"]
+        assert sr.product_layout() == ((0, 0, 0), (0, 0, 0))
+        Yt = to_np(st.spmm(X))
+        Yr = to_np(sr.spmm(X))
+        assert np.array_equal(Yt, Yr) and np.array_equal(Yt, A.to_scipy() @ to_np(X))
+        b = torch.from_numpy(manufactured_rhs(A, k, seed=7)[0]).cuda()
+        xt, it = st.solve(b, tol=1e-8, maxit=500)
+        xr, ir = sr.solve(b, tol=1e-8, maxit=500)
+        assert np.array_equal(it.iters, ir.iters) and np.array_equal(to_np(xt), to_np(xr))
+        # new values through the same array: the tiled copy follows
+        A2 = CSR(A.n, A.row_ptr, A.col_idx, A.values * 1.5)
+        st.update_values(torch.from_numpy(A2.values).cuda())
+        assert np.array_equal(to_np(st.spmm(X)), A2.to_scipy() @ to_np(X))
+        st.close()
+        sr.close()
+    A = random_sparse(4096, 7, seed=1)
+    s = gpu_solver(lib, A, k)
+    assert s.product_layout() == ((0, 0, 0), (0, 0, 0))
+    s.close()
+    s = gpu_solver(lib, conv_diff(24, 3, (1.0, 0.7, 0.3)), 16)
+    assert s.product_layout() == ((0, 0, 0), (0, 0, 0))
+    s.close()
+
+
 def test_spmm_and_solve_unaligned_operands(lib):
     """Blocks that start one element past an aligned address (views into a
     larger buffer) take the one-column-per-lane product: the same sums, so
