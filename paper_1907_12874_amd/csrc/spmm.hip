@@ -188,12 +188,14 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
       s_val[i] = val[e0 + i];
     }
     for (int i = threadIdx.x; i <= r1 - r0; i += BS) s_rp[i] = A.row_ptr[r0 + i] - e0;
-    if (A.rowmap)
-      for (int i = threadIdx.x; i < r1 - r0; i += BS) s_map[i] = A.rowmap[r0 + i];
+    // the Y row of each staged row (its own index unless the rows are stored
+    // permuted): staged always, so the row loop carries no branch on it
+    const int32_t* __restrict__ rmap = A.rowmap;
+    for (int i = threadIdx.x; i < r1 - r0; i += BS) s_map[i] = rmap ? rmap[r0 + i] : r0 + i;
     __syncthreads();
     if (c >= k) return;
     const int nr = r1 - r0;
-    auto yrow = [&](int r) { return A.rowmap ? s_map[r] : r0 + r; };
+    auto yrow = [&](int r) { return s_map[r]; };
     if constexpr (CPL > 1) {
       typedef typename VecOf<T, CPL>::type V;
       for (int r = rsub; r < nr; r += rpp) {
@@ -314,7 +316,9 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
     }
   } else {
     // one long row (r1 == r0 + 1): lanes of the same columns split its entries
-    // and their sums are added in lane order
+    // and their sums are added in lane order (its Y row staged like the rows of
+    // a block; the barriers below order the store before its use)
+    if (threadIdx.x == 0) s_map[0] = A.rowmap ? A.rowmap[r0] : r0;
     T sum[CPL];
 #pragma unroll
     for (int h = 0; h < CPL; ++h) sum[h] = (T)0;
@@ -348,7 +352,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
         for (int g = 0; g < rpp; ++g) v += s_red[h * BS + g * lpr + threadIdx.x];
         out[h] = v;
       }
-      store_y<T, CPL>(Y, A.rowmap ? A.rowmap[r0] : r0, k, c, out);
+      store_y<T, CPL>(Y, s_map[0], k, c, out);
       epi(r0, out);
     }
   }
@@ -428,7 +432,7 @@ hipError_t spmm_launch_bs(const SpmmMat& A, const T* x, T* y, int k, const Globa
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
-                     (size_t)(A.rows_cap + 1) * 4 + (A.rowmap ? (size_t)A.rows_cap * 4 : 0) + 16;
+                     (size_t)(A.rows_cap + 1) * 4 + (size_t)A.rows_cap * 4 + 16;
   if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
 #define SPMM_CASE(KP, KPL)                                                                                         \
@@ -455,7 +459,7 @@ hipError_t spmm_dot_launch(const SpmmMat& A, const T* x, T* y, const T* w, T* yh
   const int kp = pad_k_(k);
   const unsigned grid = (unsigned)A.nblk;
   const size_t lds = (size_t)A.nnz_cap * sizeof(T) + (size_t)CPL * BS * sizeof(T) + (size_t)A.nnz_cap * 4 +
-                     (size_t)(A.rows_cap + 1) * 4 + (A.rowmap ? (size_t)A.rows_cap * 4 : 0) + 16;
+                     (size_t)(A.rows_cap + 1) * 4 + (size_t)A.rows_cap * 4 + 16;
   if (kp < CPL) return hipErrorInvalidValue;
   switch (kp) {
 #define SPMM_DOT_CASE(KP, KPL)                                                                                    \
