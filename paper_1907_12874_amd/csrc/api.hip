@@ -286,7 +286,7 @@ SpmmMat tiled_mat(const bicgstab_ctx* h) {
   m.val = h->val_p;
   m.blk = h->blk_p;
   m.nblk = (int)h->part_p.blk.size() - 1;
-  m.xcd_chunk = 1;
+  m.xcd_chunk = h->spmm_xcd_chunk;
   m.bpart = nullptr;
   m.nnz_cap = h->part_p.nnz_cap;
   m.rows_cap = h->part_p.rows_cap;
