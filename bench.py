@@ -137,7 +137,7 @@ def roofline_of(solver, b, n, nnz, k, iters=10):
 # Sources that define each kernel family's code and launch shape: counter
 # traffic is reported for a kernel only while these are unchanged.
 KERNEL_SOURCES = {
-    "spmm": ("spmm.hip", "internal.hpp", "reduce.hpp", "plan.hpp"),
+    "spmm": ("spmm.hip", "internal.hpp", "reduce.hpp", "plan.hpp", "api.hip"),
     "vector": ("kernels.hip", "method.hpp", "reduce.hpp", "internal.hpp", "plan.hpp", "plans.cpp", "api.hip"),
 }
 

@@ -114,10 +114,13 @@ typedef struct {
 typedef struct bicgstab_ctx* bicgstab_t;
 
 /* Create a solver for A with k right-hand sides (1 <= k <= BICGSTAB_MAX_K).
- * Reads row_ptr once (device to host) to plan the sparse products; no other
- * work. stream: a hipStream_t (NULL = the null stream). The Jacobi diagonal is
- * extracted at the first solve; a zero diagonal entry then fails with
- * BICGSTAB_EINVAL. */
+ * Reads row_ptr and col_idx once (device to host) to validate the pattern
+ * (malformed offsets or a column index out of range: BICGSTAB_EINVAL) and to
+ * plan the sparse products; for a 3D grid pattern at k = 32 it also builds a
+ * library-owned tile-ordered copy of A (nnz x 16 + n x 8 bytes of device
+ * memory, freed by bicgstab_destroy; see bicgstab_product_layout). stream: a
+ * hipStream_t (NULL = the null stream). The Jacobi diagonal is extracted at
+ * the first solve; a zero diagonal entry then fails with BICGSTAB_EINVAL. */
 int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant, int32_t formulation,
                     int32_t precond, int32_t precision, void* stream, bicgstab_t* out);
 
