@@ -460,17 +460,26 @@ def _pipelined_scalars(alpha, omega, rho, rho_next, sigma, delta, psi):
     return None, beta, alpha_next
 
 
-def alg4_merged_pipebicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False):
+def alg4_merged_pipebicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False, A_prec=None, Minv=None):
     """Alg. 4: merged Pipelined BiCGStab (Cools and Vanroose). The auxiliary
     vectors satisfy s = A p, z = A s, w = A r, t = A w, y = A q, v = A z in
-    exact arithmetic; the stop test is pi - omega*theta."""
+    exact arithmetic; the stop test is pi - omega*theta.
+
+    A_prec, if given, is A M^{-1} stored as a matrix (a diagonal M, with Minv
+    applying M^{-1}). Alg. 7 preconditions from the right: its plain vectors
+    (r, w, t, s, z, q, y, v) obey Alg. 4's recurrences with the operator
+    A M^{-1}, and each hat vector is M^{-1} times its plain one (p-hat =
+    M^{-1} p, q-hat = M^{-1} q, ...). So the products take A_prec and the
+    solution update is x += alpha M^{-1} p + omega M^{-1} q: Alg. 7's iterates
+    in exact arithmetic, with no hat vector kept."""
     rec = _Recorder(trace, trace_vectors)
     early, x, r, rho, eps2 = _begin(A, b, x0, tol)
     if early is not None:
         return early
+    op = A if A_prec is None else A_prec
     r0 = r.copy()
-    w = A @ r
-    t = A @ w
+    w = op @ r
+    t = op @ w
     rw = dot(r, w)
     if rw == 0.0:
         return ColumnResult(x, r, 0, BREAKDOWN)
@@ -489,12 +498,15 @@ def alg4_merged_pipebicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=Fal
         q = r - alpha * s
         y = w - alpha * z
         theta, phi, pi = dot(q, y), dot(y, y), dot(q, q)
-        v = A @ z
+        v = op @ z
         omega = theta / phi if phi != 0.0 else 0.0
         est = pi - omega * theta
         if not (np.isfinite(omega) and np.isfinite(est)):
             return ColumnResult(x, r, j + 1, NONFINITE, trace)
-        x = x + alpha * p + omega * q
+        if Minv is None:
+            x = x + alpha * p + omega * q
+        else:
+            x = x + alpha * Minv(p) + omega * Minv(q)
         r = q - omega * y
         rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est}, x=x, r=r, p=p, s=s, z=z, q=q, y=y, v=v, w=w, t=t)
         if est < eps2:
@@ -503,7 +515,7 @@ def alg4_merged_pipebicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=Fal
             return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
         w = y - omega * (t - alpha * v)
         rho_next, psi, sigma, delta = dot(r0, r), dot(r0, z), dot(r0, w), dot(r0, s)
-        t = A @ w
+        t = op @ w
         st, beta, alpha_next = _pipelined_scalars(alpha, omega, rho, rho_next, sigma, delta, psi)
         if st is not None:
             return ColumnResult(x, r, j + 1, st, trace)
@@ -588,8 +600,9 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     regrouping of the merged statements: dots formed in the sparse products'
     epilogues, the Jacobi division done by the pass that produces the vector)
     computes the merged listing's statements, so it maps to that listing;
-    for the classical method with Jacobi it folds M^{-1} into the products
-    (Alg. 5 with A M^{-1} stored as a matrix)."""
+    for the classical and Pipelined methods with Jacobi it folds M^{-1} into
+    the products (Alg. 5, and Alg. 4 standing for Alg. 7, with A M^{-1} stored
+    as a matrix)."""
     import scipy.sparse as sp
 
     A = sp.csr_matrix(A)
@@ -623,6 +636,9 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
         return alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, **kw)
     if precond == "none":
         return alg4_merged_pipebicgstab(A, b, x0, tol, maxit, **kw)
+    if fused:
+        # Alg. 7 with Jacobi folded into the products: Alg. 4 on A M^{-1}
+        return alg4_merged_pipebicgstab(A, b, x0, tol, maxit, A_prec=jacobi_folded_operator(A), Minv=Minv, **kw)
     return alg7_merged_ppipebicgstab(A, b, x0, tol, maxit, Minv, **kw)
 
 
