@@ -58,9 +58,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
-    "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g1", "pp_g2", "pp_g3", "pp_g4",
+    "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g12", "pp_g34",
     "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h", "ib_init", "ib_g1", "ib_g2",
-    "ib_g3", "ib_z", "ib_v", "ib_x", "f_pp_g2h", "f_pp_g4h", "re_r", "f_xr_rho_d",
+    "ib_g3", "ib_z", "ib_v", "ib_x", "re_r", "f_xr_rho_d", "f_p_g23", "f_p_g23d",
 ]
 
 
@@ -640,7 +640,7 @@ def small_2d_section(pk, dev, passes=100, reps=5, maxit=3000):
     x = torch.empty_like(b)
     rows = []
     for variant, form in (("classical", "basic"), ("classical", "merged"), ("classical", "fused"),
-                          ("pipelined", "basic"), ("pipelined", "merged")):
+                          ("pipelined", "basic"), ("pipelined", "merged"), ("pipelined", "fused")):
         sv = pk.Solver.from_csr(A, 1, variant=variant, formulation=form, precond="none", device=dev)
         tr = pk.plan_traffic(variant, form, "none")
         sv.solve(b, x0, tol=0.0, maxit=2, out=x)

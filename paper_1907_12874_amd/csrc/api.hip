@@ -133,6 +133,7 @@ struct bicgstab_ctx {
   int32_t* perm_p = nullptr;   // stored entry -> entry of A
   int32_t* rowmap_p = nullptr; // stored row -> row of A
   double* val_p = nullptr;
+  double* val_fold_p = nullptr;  // A M^{-1} in the same order, for plans with folded plain products
   int32_t* blk_p = nullptr;
   SpmmPartition part_p;
   std::vector<GraphEntry> graphs;
@@ -266,6 +267,7 @@ int prepare(bicgstab_ctx* h) {
   }
   if (fp32_inner(h)) HIPCHK(launch_convert_f32(h->val, h->val32, h->nnz, h->ws));
   if (has_fold(h)) HIPCHK(launch_fold_jacobi(h->col, h->val, h->diag, h->val_fold, h->val_fold32, h->nnz, h->ws));
+  if (h->val_fold_p) HIPCHK(launch_gather_values(h->val_fold, h->perm_p, h->val_fold_p, h->nnz, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   if (has_spmm_t(h) && h->n > 0) {
     const int rc = build_transpose(h);
@@ -275,15 +277,16 @@ int prepare(bicgstab_ctx* h) {
   return BICGSTAB_OK;
 }
 
-// The plain FP64 product with A stored tile by tile (rows in tile order, Y
-// written at each row's own index): bitwise the same sums as the row-ordered
-// product, with the neighbours of a tile's rows in fewer row blocks.
-SpmmMat tiled_mat(const bicgstab_ctx* h) {
+// The plain FP64 product with A (fold: A M^{-1}) stored tile by tile (rows in
+// tile order, Y written at each row's own index): bitwise the same sums as
+// the row-ordered product, with the neighbours of a tile's rows in fewer row
+// blocks.
+SpmmMat tiled_mat(const bicgstab_ctx* h, bool fold = false) {
   SpmmMat m;
   m.n = (int)h->n;
   m.row_ptr = h->rp_p;
   m.col = h->col_p;
-  m.val = h->val_p;
+  m.val = fold ? h->val_fold_p : h->val_p;
   m.blk = h->blk_p;
   m.nblk = (int)h->part_p.blk.size() - 1;
   m.xcd_chunk = h->spmm_xcd_chunk;
@@ -393,8 +396,8 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
   if (st.fold && !M.val) return hipErrorInvalidValue;
   switch (st.kind) {
     case K_SPMM:
-      if (h->tiled && !fp32 && !st.fold && M.blk == h->blk)
-        return launch_spmm(tiled_mat(h), vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
+      if (h->tiled && !fp32 && M.blk == h->blk && (!st.fold || h->val_fold_p))
+        return launch_spmm(tiled_mat(h, st.fold != 0), vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
       return launch_spmm(M, vp[st.in[0]], vp[st.out[0]], h->k, fp32, g, s);
     case K_SPMM_T: {
       // the other matrix of the pair (A, A^T): A^T when solving with A
@@ -412,8 +415,8 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
       return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
                          (int)h->n, h->k, fp32, g, s);
     case K_GROUP: {
-      const void* in[7] = {};
-      void* out[5] = {};
+      const void* in[kMaxPassIn] = {};
+      void* out[kMaxPassOut] = {};
       for (int i = 0; i < st.nin; ++i) in[i] = vp[st.in[i]];
       for (int i = 0; i < st.nout; ++i) out[i] = vp[st.out[i]];
       const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
@@ -505,8 +508,8 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
   for (const Step& st : h->plan.init) {
     if (fp32 && st.kind == K_SPMM && st.in[0] == V_X) {
       // inner solves start from d = 0, so A d = 0 without a product
-      const void* in0[7] = {};
-      void* out0[5] = {vp[st.out[0]]};
+      const void* in0[kMaxPassIn] = {};
+      void* out0[kMaxPassOut] = {vp[st.out[0]]};
       HIPCHK(launch_group(OP_FILL0, in0, out0, nullptr, (int)h->n, h->k, 0, F_NONE, ctl, true, h->caps, h->ws));
     } else {
       HIPCHK(launch_step(h, st, M, vp, ctl, fp32, h->ws));
@@ -535,8 +538,8 @@ int krylov(bicgstab_ctx* h, int which, bool fp32, const void* b, void* x, double
     // exit: true residual b - A x and ||r|| for every column
     void* z = vp[V_V];
     HIPCHK(launch_spmm(M, x, z, h->k, false, nullptr, h->ws));
-    const void* in[7] = {b, z, vp[V_R]};
-    void* out[5] = {};
+    const void* in[kMaxPassIn] = {b, z, vp[V_R]};
+    void* out[kMaxPassOut] = {};
     HIPCHK(launch_group(OP_EXIT, in, out, nullptr, (int)h->n, h->k, 0, F_EXIT, ctl, false, h->caps, h->ws));
     *launches += 2;
   }
@@ -588,8 +591,8 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     HIPCHK(launch_setup_state(ctl, tol, maxit, 0, h->ws));
     HIPCHK(launch_spmm(M64, x, Z, k, false, nullptr, h->ws));
     {
-      const void* in[7] = {b, Z};
-      void* out[5] = {R};
+      const void* in[kMaxPassIn] = {b, Z};
+      void* out[kMaxPassOut] = {R};
       HIPCHK(launch_group(OP_REF_RESID, in, out, nullptr, (int)h->n, k, 0, F_REFINE_NORM, ctl, false, h->caps, h->ws));
     }
     *launches += 3;
@@ -623,8 +626,8 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
       for (int c = 0; c < k; ++c) h->h_ist[I_ZEROB * kMaxK + c] = bnorm[c] == 0.0 ? 1 : 0;
       HIPCHK(hipMemcpyAsync(h->ist + I_ZEROB * kMaxK, h->h_ist + I_ZEROB * kMaxK, kMaxK * 4, hipMemcpyHostToDevice,
                             h->ws));
-      const void* in[7] = {};
-      void* out[5] = {x};
+      const void* in[kMaxPassIn] = {};
+      void* out[kMaxPassOut] = {x};
       HIPCHK(launch_group(OP_ZEROB, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, false, h->caps, h->ws));
       ++*launches;
     }
@@ -634,8 +637,8 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
     HIPCHK(hipMemcpyAsync(h->sc + S_SCALE * kMaxK, h->h_sc + S_SCALE * kMaxK, kMaxK * 8, hipMemcpyHostToDevice,
                           h->ws));
     {
-      const void* in[7] = {R};
-      void* out[5] = {B32, D};
+      const void* in[kMaxPassIn] = {R};
+      void* out[kMaxPassOut] = {B32, D};
       HIPCHK(launch_group(OP_REF_SCALE, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
@@ -650,8 +653,8 @@ int solve_refined(bicgstab_ctx* h, const double* b, double* x, double tol, int m
       }
     // x += ||r_c|| d (the inner solve does not touch S_SCALE)
     {
-      const void* in[7] = {x, D};
-      void* out[5] = {x};
+      const void* in[kMaxPassIn] = {x, D};
+      void* out[kMaxPassOut] = {x};
       HIPCHK(launch_group(OP_REF_UPDATE, in, out, nullptr, (int)h->n, k, 0, F_NONE, ctl, true, h->caps, h->ws));
       ++*launches;
     }
@@ -774,7 +777,8 @@ bool detect_grid(const std::vector<int32_t>& rp, const std::vector<int32_t>& col
 // us per product (2 x 2 x 8 tiles 290 us, 1 x 2 x 16 and 1 x 1 x 32 no gain);
 // at k = 16 (64-row blocks) tiles were no faster, so other widths keep the
 // row order. The entries are copied once (columns here, values by a gather
-// on the device, again whenever the values change); the sums, each row's
+// on the device, again whenever the values change; the folded values A M^{-1}
+// too where plain products of the plan use them); the sums, each row's
 // entries in stored order, are unchanged. Best effort: any failure leaves
 // the row-ordered product in use.
 void build_tiles(bicgstab_ctx* h, const std::vector<int32_t>& rp, const std::vector<int32_t>& cols) {
@@ -813,6 +817,10 @@ void build_tiles(bicgstab_ctx* h, const std::vector<int32_t>& rp, const std::vec
   bool ok = alloc((void**)&h->rp_p, ((size_t)n + 1) * 4) && alloc((void**)&h->col_p, (size_t)h->nnz * 4) &&
             alloc((void**)&h->perm_p, (size_t)h->nnz * 4) && alloc((void**)&h->rowmap_p, (size_t)n * 4) &&
             alloc((void**)&h->val_p, (size_t)h->nnz * 8) && alloc((void**)&h->blk_p, P.blk.size() * 4);
+  // folded values for plain products of the plan (filled where the fold is formed)
+  bool plain_fold = false;
+  for (const Step& st : h->plan.iter) plain_fold |= st.kind == K_SPMM && st.fold;
+  if (plain_fold && !fp32_inner(h)) ok = ok && alloc((void**)&h->val_fold_p, (size_t)h->nnz * 8);
   ok = ok && hipMemcpy(h->rp_p, rpp.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(h->col_p, colp.data(), (size_t)h->nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(h->perm_p, perm.data(), (size_t)h->nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
@@ -822,7 +830,7 @@ void build_tiles(bicgstab_ctx* h, const std::vector<int32_t>& rp, const std::vec
        hipStreamSynchronize(h->ws) == hipSuccess;
   if (!ok) {
     for (void** p : {(void**)&h->rp_p, (void**)&h->col_p, (void**)&h->perm_p, (void**)&h->rowmap_p,
-                     (void**)&h->val_p, (void**)&h->blk_p}) {
+                     (void**)&h->val_p, (void**)&h->val_fold_p, (void**)&h->blk_p}) {
       if (*p) hipFree(*p);
       *p = nullptr;
     }
@@ -1188,7 +1196,7 @@ int bicgstab_destroy(bicgstab_t h) {
   if (h->owned && h->base) hipFree(h->base);
   for (void* p : {(void*)h->rp_t, (void*)h->col_t, (void*)h->perm_t, (void*)h->val_t, (void*)h->val32_t,
                   (void*)h->val_fold_t, (void*)h->blk_t, (void*)h->bpart_t, (void*)h->rp_p, (void*)h->col_p,
-                  (void*)h->perm_p, (void*)h->rowmap_p, (void*)h->val_p, (void*)h->blk_p})
+                  (void*)h->perm_p, (void*)h->rowmap_p, (void*)h->val_p, (void*)h->val_fold_p, (void*)h->blk_p})
     if (p) hipFree(p);
   for (void* p : {(void*)h->h_blk, (void*)h->h_nrun, (void*)h->h_sc, (void*)h->h_ist, (void*)h->h_glob})
     if (p) hipHostFree(p);

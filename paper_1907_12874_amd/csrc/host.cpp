@@ -186,8 +186,8 @@ void group(Ctx& h, const Step& st, double* const* vp) {
     cf[c].c1 = SCh(h, S_C1, c);
     cf[c].c2 = SCh(h, S_C2, c);
   }
-  const double* in[8] = {};
-  double* out[6] = {};
+  const double* in[kMaxPassIn] = {};
+  double* out[kMaxPassOut] = {};
   for (int i = 0; i < Op::NIN; ++i) in[i] = vp[st.in[i]];
   for (int j = 0; j < Op::NOUT; ++j) out[j] = vp[st.out[j]];
   constexpr int NI = Op::NIN + (Op::USE_D ? 1 : 0) > 0 ? Op::NIN + (Op::USE_D ? 1 : 0) : 1;
@@ -241,10 +241,8 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_P_G1, KPG1)
     G(OP_P_G2, KPG2)
     G(OP_P_G3, KPG3)
-    G(OP_PP_G1, KPPG1)
-    G(OP_PP_G2, KPPG2)
-    G(OP_PP_G3, KPPG3)
-    G(OP_PP_G4, KPPG4)
+    G(OP_PP_G12, KPPG12)
+    G(OP_PP_G34, KPPG34)
     G(OP_F_SUB_ALPHA_H, KFSubAlphaH)
     G(OP_F_PUPD_H, KFPUpdH)
     G(OP_F_XR_RHO_H, KFXrRhoH)
@@ -255,10 +253,10 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_IB_Z, KIbZ)
     G(OP_IB_V, KIbV)
     G(OP_IB_X, KIbX)
-    G(OP_F_PP_G2H, KPPG2H)
-    G(OP_F_PP_G4H, KPPG4H)
     G(OP_RE_R, KReR)
     G(OP_F_XR_RHO_D, KFXrRhoD)
+    G(OP_F_P_G23, KFPG23)
+    G(OP_F_P_G23D, KFPG23D)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }

@@ -63,8 +63,8 @@ namespace bcg {
 // ---------------------------------------------------- cross-block reduction ---
 
 struct GArgs {
-  const void* in[7];
-  void* out[5];
+  const void* in[kMaxPassIn];
+  void* out[kMaxPassOut];
   const void* diag;  // a_ii (storage type) for USE_D ops
   long n;
   int k, kpl, slot, fin;
@@ -400,10 +400,8 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_P_G1: return launch_op<KPG1, T>(a, grid_cap, s, defer);
     case OP_P_G2: return launch_op<KPG2, T>(a, grid_cap, s, defer);
     case OP_P_G3: return launch_op<KPG3, T>(a, grid_cap, s, defer);
-    case OP_PP_G1: return launch_op<KPPG1, T>(a, grid_cap, s, defer);
-    case OP_PP_G2: return launch_op<KPPG2, T>(a, grid_cap, s, defer);
-    case OP_PP_G3: return launch_op<KPPG3, T>(a, grid_cap, s, defer);
-    case OP_PP_G4: return launch_op<KPPG4, T>(a, grid_cap, s, defer);
+    case OP_PP_G12: return launch_op<KPPG12, T>(a, grid_cap, s, defer);
+    case OP_PP_G34: return launch_op<KPPG34, T>(a, grid_cap, s, defer);
     case OP_REF_RESID: return launch_op<KRefResid, T>(a, grid_cap, s, defer);
     case OP_REF_SCALE: return launch_op<KRefScale, T>(a, grid_cap, s, defer);
     case OP_REF_UPDATE: return launch_op<KRefUpdate, T>(a, grid_cap, s, defer);
@@ -417,10 +415,10 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_IB_Z: return launch_op<KIbZ, T>(a, grid_cap, s, defer);
     case OP_IB_V: return launch_op<KIbV, T>(a, grid_cap, s, defer);
     case OP_IB_X: return launch_op<KIbX, T>(a, grid_cap, s, defer);
-    case OP_F_PP_G2H: return launch_op<KPPG2H, T>(a, grid_cap, s, defer);
-    case OP_F_PP_G4H: return launch_op<KPPG4H, T>(a, grid_cap, s, defer);
     case OP_RE_R: return launch_op<KReR, T>(a, grid_cap, s, defer);
     case OP_F_XR_RHO_D: return launch_op<KFXrRhoD, T>(a, grid_cap, s, defer);
+    case OP_F_P_G23: return launch_op<KFPG23, T>(a, grid_cap, s, defer);
+    case OP_F_P_G23D: return launch_op<KFPG23D, T>(a, grid_cap, s, defer);
     default: return hipErrorInvalidValue;
   }
 }
@@ -434,8 +432,8 @@ hipError_t launch_group(int op, const void* const* in, void* const* out, const v
                         int fin, const Ctl& ctl, bool fp32, const GridCaps& grid_cap, hipStream_t s,
                         const Pending* pending, bool defer) {
   GArgs a;
-  for (int i = 0; i < 7; ++i) a.in[i] = in[i];
-  for (int i = 0; i < 5; ++i) a.out[i] = out[i];
+  for (int i = 0; i < kMaxPassIn; ++i) a.in[i] = in[i];
+  for (int i = 0; i < kMaxPassOut; ++i) a.out[i] = out[i];
   a.diag = diag;
   a.n = n;
   a.k = k;

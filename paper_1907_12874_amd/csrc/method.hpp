@@ -216,6 +216,46 @@ struct KPG3 {  // in: y, t, v, r0, r, z, s ; out: w ; (r0,r), (r0,z), (r0,w), (r
     a[3] += v[3] * v[6];
   }
 };
+// Fused Alg. 4: {x, r} and {w and the four dots} in one pass; r is rounded to
+// the storage type as if stored and read back.
+struct KFPG23 {  // in: x, p, q, y, t, v, r0, z, s ; out: x, r, w ; (r0,r), (r0,z), (r0,w), (r0,s)
+  OP_HEAD(9, 3, 4, 1, 1, PART_RUN, true)
+  OP_F {
+    o[0] = v[0] + c.alpha * v[1] + c.omega * v[2];
+    const double r = R(v[2] - c.omega * v[3]);
+    const double w = R(v[3] - c.omega * (v[4] - c.alpha * v[5]));
+    o[1] = r;
+    o[2] = w;
+    a[0] += v[6] * r;
+    a[1] += v[6] * v[7];
+    a[2] += v[6] * w;
+    a[3] += v[6] * v[8];
+  }
+};
+// Alg. 7 as Alg. 4 on A M^{-1} (Jacobi folded into the products): the hat
+// vectors p-hat = p / a_ii and q-hat = q / a_ii are formed here for the
+// solution update alone (rounded to the storage type as a stored copy would
+// be).
+struct KFPG23D {  // in: x, p, q, y, t, v, r0, z, s (+ a_ii) ; out: x, r, w ; the same dots
+  OP_HEAD_D(9, 3, 4, 1, 1, PART_RUN, true)
+  OP_F {
+    const double ph = R(v[1] / v[9]);
+    const double qh = R(v[2] / v[9]);
+    o[0] = v[0] + c.alpha * ph + c.omega * qh;
+    const double r = R(v[2] - c.omega * v[3]);
+    const double w = R(v[3] - c.omega * (v[4] - c.alpha * v[5]));
+    o[1] = r;
+    o[2] = w;
+    a[0] += v[6] * r;
+    a[1] += v[6] * v[7];
+    a[2] += v[6] * w;
+    a[3] += v[6] * v[8];
+  }
+};
+// Alg. 7 in four groups: the preconditioned (hat) blocks of the first line
+// (KPPG1) and its plain blocks (KPPG2), then those of the second line (KPPG3,
+// KPPG4). The passes run a line's two groups together (KPPG12, KPPG34): the
+// groups read and write disjoint blocks, so joining them changes no value.
 struct KPPG1 {  // in: rh, ph, sh, wh, zh ; out: ph, sh, qh
   OP_HEAD(5, 3, 0, 0, 0, PART_RUN, true)
   OP_F {
@@ -262,38 +302,24 @@ struct KPPG4 {  // in: q, y, t, v, r0, z, s ; out: r, w ; (r0,r), (r0,z), (r0,w)
     a[3] += v[4] * v[6];
   }
 };
-// Fused Alg. 7: the passes that make z and w also write their Jacobi copies.
-struct KPPG2H {  // in: w, s, z, t, v, r (+ a_ii) ; out: s, z, q, y, zh ; (q, y), (y, y), (q, q)
-  OP_HEAD_D(6, 5, 3, 0, 0, PART_RUN, true)
+// in: rh, ph, sh, wh, zh, w, s, z, t, v, r ; out: ph, sh, qh, s, z, q, y ; (q, y), (y, y), (q, q)
+struct KPPG12 {
+  OP_HEAD(11, 7, 3, 0, 0, PART_RUN, true)
   OP_F {
-    double s = R(v[0] + c.beta * (v[1] - c.omega * v[2]));
-    double z = R(v[3] + c.beta * (v[2] - c.omega * v[4]));
-    double q = R(v[5] - c.alpha * s);
-    double y = R(v[0] - c.alpha * z);
-    o[0] = s;
-    o[1] = z;
-    o[2] = q;
-    o[3] = y;
-    o[4] = z / v[6];
-    a[0] += q * y;
-    a[1] += y * y;
-    a[2] += q * q;
+    KPPG1::f<T>(v, c, o, a);
+    KPPG2::f<T>(v + KPPG1::NIN, c, o + KPPG1::NOUT, a);
   }
 };
-struct KPPG4H {  // in: q, y, t, v, r0, z, s (+ a_ii) ; out: r, w, wh ; (r0,r), (r0,z), (r0,w), (r0,s)
-  OP_HEAD_D(7, 3, 4, 0, 0, PART_RUN, true)
+// in: x, ph, qh, wh, zh, q, y, t, v, r0, z, s ; out: x, rh, r, w ; (r0,r), (r0,z), (r0,w), (r0,s)
+struct KPPG34 {
+  OP_HEAD(12, 4, 4, 1, 1, PART_RUN, true)
   OP_F {
-    double r = R(v[0] - c.omega * v[1]);
-    double w = R(v[1] - c.omega * (v[2] - c.alpha * v[3]));
-    o[0] = r;
-    o[1] = w;
-    o[2] = w / v[7];
-    a[0] += v[4] * r;
-    a[1] += v[4] * v[5];
-    a[2] += v[4] * w;
-    a[3] += v[4] * v[6];
+    KPPG3::f<T>(v, c, o, a);
+    KPPG4::f<T>(v + KPPG3::NIN, c, o + KPPG3::NOUT, a);
   }
 };
+static_assert(KPPG12::NIN == KPPG1::NIN + KPPG2::NIN && KPPG12::NOUT == KPPG1::NOUT + KPPG2::NOUT, "");
+static_assert(KPPG34::NIN == KPPG3::NIN + KPPG4::NIN && KPPG34::NOUT == KPPG3::NOUT + KPPG4::NOUT, "");
 // Refinement passes (outer loop of the FP32 tier). Inputs/outputs marked in
 // XIN/XOUT are FP64; the rest are the inner (FP32) Krylov type.
 struct KRefResid {  // in: b, z (FP64) ; out: r (FP64) ; (r, r), (b, b)

@@ -118,10 +118,9 @@ enum OpId {
   OP_P_G1,         // Alg. 4 first group (p, s, z, q, y; theta, phi, pi)
   OP_P_G2,         // x += alpha p + omega q; r = q - omega y
   OP_P_G3,         // w = y - omega (t - alpha v); dots (r0,r), (r0,z), (r0,w), (r0,s)
-  OP_PP_G1,        // Alg. 7: ph, sh, qh
-  OP_PP_G2,        // Alg. 7: s, z, q, y; theta, phi, pi
-  OP_PP_G3,        // Alg. 7: x += alpha ph + omega qh; rh = qh - omega (wh - alpha zh)
-  OP_PP_G4,        // Alg. 7: r = q - omega y; w = y - omega (t - alpha v); 4 dots
+  OP_PP_G12,       // Alg. 7, first line: ph, sh, qh and s, z, q, y; theta, phi, pi
+  OP_PP_G34,       // Alg. 7, second line: x += alpha ph + omega qh, rh = qh - omega (wh - alpha zh)
+                   // and r = q - omega y, w = y - omega (t - alpha v); 4 dots
   OP_REF_RESID,    // refinement: r = b - z (FP64); dots (r,r), (b,b)
   OP_REF_SCALE,    // refinement: r32 = r / ||r_c|| (to FP32), d = 0
   OP_REF_UPDATE,   // refinement: x = x + ||r_c|| * d
@@ -135,12 +134,16 @@ enum OpId {
   OP_IB_Z,           // Alg. 3 basic: z = alpha r + c1 z - c2 v
   OP_IB_V,           // Alg. 3 basic: v = u + beta v - delta q
   OP_IB_X,           // Alg. 3 basic: x = x + z + omega s
-  OP_F_PP_G2H,       // fused Jacobi, Alg. 7: OP_PP_G2 that also writes zh = z / a_ii
-  OP_F_PP_G4H,       // fused Jacobi, Alg. 7: OP_PP_G4 that also writes wh = w / a_ii
   OP_RE_R,           // Alg. 6: r = rt - omega t; r0 = r for a column that restarts
   OP_F_XR_RHO_D,     // folded Jacobi, Alg. 5: x += alpha p / a_ii + omega s / a_ii; r = s - omega t; dot (r, r0)
+  OP_F_P_G23,        // fused Alg. 4: OP_P_G2 and OP_P_G3 in one pass (r kept in registers); 4 dots
+  OP_F_P_G23D,       // folded Jacobi, Alg. 7 as Alg. 4 on A M^{-1}: the same with x += (alpha p + omega q) / a_ii
   OP_NUM
 };
+
+// Blocks a vector pass reads and writes at most (Alg. 7's passes, which
+// update the preconditioned and the plain blocks of a line together).
+constexpr int kMaxPassIn = 12, kMaxPassOut = 8;
 
 // Vector names used by the launch plans (indices into the handle's table).
 enum VecId {
@@ -171,8 +174,8 @@ constexpr bool epilogue_prec(int epi) { return epi == E_PREC || epi == E_DOT_W_P
 struct Step {
   StepKind kind;
   int op;        // OpId for K_GROUP
-  int in[8];     // VecIds (a vector pass reads at most 7 blocks)
-  int out[6];    // (and writes at most 5)
+  int in[kMaxPassIn];    // VecIds of the blocks a vector pass reads
+  int out[kMaxPassOut];  // and writes
   int slot;      // first dot slot written
   int fin;       // FinStep
   int nin, nout; // vector reads / writes of the pass (traffic accounting)

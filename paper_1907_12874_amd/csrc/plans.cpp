@@ -40,10 +40,8 @@ const OpInfo kOps[OP_NUM] = {
     {7, 5, 3, "p_g1"},        // OP_P_G1
     {4, 2, 0, "p_g2"},        // OP_P_G2
     {7, 1, 4, "p_g3"},        // OP_P_G3
-    {5, 3, 0, "pp_g1"},       // OP_PP_G1
-    {6, 4, 3, "pp_g2"},       // OP_PP_G2
-    {5, 2, 0, "pp_g3"},       // OP_PP_G3
-    {7, 2, 4, "pp_g4"},       // OP_PP_G4
+    {11, 7, 3, "pp_g12"},     // OP_PP_G12
+    {12, 4, 4, "pp_g34"},     // OP_PP_G34
     {2, 1, 2, "ref_resid"},   // OP_REF_RESID
     {1, 2, 0, "ref_scale"},   // OP_REF_SCALE
     {2, 1, 0, "ref_update"},  // OP_REF_UPDATE
@@ -57,10 +55,10 @@ const OpInfo kOps[OP_NUM] = {
     {3, 1, 0, "ib_z"},           // OP_IB_Z
     {3, 1, 0, "ib_v"},           // OP_IB_V
     {3, 1, 0, "ib_x"},           // OP_IB_X
-    {6, 5, 3, "f_pp_g2h"},       // OP_F_PP_G2H
-    {7, 3, 4, "f_pp_g4h"},       // OP_F_PP_G4H
     {2, 2, 0, "re_r", 1},        // OP_RE_R (r0 written on a restart only)
     {5, 2, 1, "f_xr_rho_d"},     // OP_F_XR_RHO_D (+ the diagonal)
+    {9, 3, 4, "f_p_g23"},        // OP_F_P_G23
+    {9, 3, 4, "f_p_g23d"},       // OP_F_P_G23D (+ the diagonal)
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -68,9 +66,9 @@ Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, in
   std::memset(&s, 0, sizeof(s));
   s.kind = K_GROUP;
   s.op = op;
-  for (int i = 0; i < 8; ++i) s.in[i] = V_NONE;
-  for (int i = 0; i < 6; ++i) s.out[i] = V_NONE;
-  if (in.size() > 7 || out.size() > 5) std::abort();  // a plan bug; kernels take at most 7 in / 5 out
+  for (int i = 0; i < kMaxPassIn; ++i) s.in[i] = V_NONE;
+  for (int i = 0; i < kMaxPassOut; ++i) s.out[i] = V_NONE;
+  if (in.size() > (size_t)kMaxPassIn || out.size() > (size_t)kMaxPassOut) std::abort();  // a plan bug
   int i = 0;
   for (int v : in) s.in[i++] = v;
   int o = 0;
@@ -86,6 +84,13 @@ Step SPMM(int in, int out) {
   Step s = G(OP_COPY, {in}, {out});
   s.kind = K_SPMM;
   s.op = -1;
+  return s;
+}
+
+// The same with the Jacobi-folded matrix: y = (A M^{-1}) x.
+Step SPMM_FOLD(int in, int out) {
+  Step s = SPMM(in, out);
+  s.fold = 1;
   return s;
 }
 
@@ -275,7 +280,34 @@ void reordered(int formulation, int precond, Plan* P) {
 }
 
 // ------------------------------------------------------------- pipelined ---
+// Fused form (one device, beyond the paper's grouping): Alg. 4's lines
+// {x, r} and {w and the four dots} in one pass that keeps r in registers
+// (16 block reads per iteration instead of 18). With Jacobi, Alg. 7 is Alg. 4
+// on the operator A M^{-1}: its plain vectors obey Alg. 4's recurrences with
+// that operator and each hat vector is M^{-1} times its plain one. So the
+// products read the folded matrix (entries a_ij / a_jj), no hat block exists
+// (10 blocks instead of 15, 24 block passes per iteration instead of 38) and
+// the solution update divides p and q by a_ii itself.
+void pipelined_fused(int precond, Plan* P) {
+  const bool jac = precond == 1;
+  auto prod = [jac](int in, int out) { return jac ? SPMM_FOLD(in, out) : SPMM(in, out); };
+  P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X}), prod(V_R, V_W),
+             prod(V_W, V_T), G(OP_DOT, {V_R, V_W}, {}, 0, F_PIPE_INIT)};
+  for (int v : {V_S, V_Z, V_V, V_P}) P->init.push_back(G(OP_FILL0, {}, {v}));
+  auto& it = P->iter;
+  it.push_back(G(OP_P_G1, {V_R, V_P, V_S, V_W, V_Z, V_T, V_V}, {V_P, V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
+  it.push_back(prod(V_Z, V_V));
+  it.push_back(G(jac ? OP_F_P_G23D : OP_F_P_G23, {V_X, V_P, V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_X, V_R, V_W}, 3,
+                 F_PIPE_BETA_END));
+  it.push_back(prod(V_W, V_T));
+  P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T, V_Z, V_Q, V_W, V_Y};
+}
+
 void pipelined(int formulation, int precond, Plan* P) {
+  if (formulation == 2) {
+    pipelined_fused(precond, P);
+    return;
+  }
   const bool jac = precond == 1;
   auto& in = P->init;
   in = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
@@ -298,8 +330,7 @@ void pipelined(int formulation, int precond, Plan* P) {
 
   auto& it = P->iter;
   if (!jac) {
-    // without a preconditioner there is nothing to fold: fused = merged
-    if (formulation == 0 || formulation == 2) {
+    if (formulation == 0) {
       it.push_back(G(OP_P_G1, {V_R, V_P, V_S, V_W, V_Z, V_T, V_V}, {V_P, V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
       it.push_back(SPMM(V_Z, V_V));
       it.push_back(G(OP_P_G2, {V_X, V_P, V_Q, V_Y}, {V_X, V_R}));
@@ -328,21 +359,16 @@ void pipelined(int formulation, int precond, Plan* P) {
     P->vecs = {V_R, V_R0, V_P, V_V, V_S, V_T, V_Z, V_Q, V_W, V_Y};
   } else {
     if (formulation == 0) {
-      it.push_back(G(OP_PP_G1, {V_RH, V_PH, V_SH, V_WH, V_ZH}, {V_PH, V_SH, V_QH}));
-      it.push_back(G(OP_PP_G2, {V_W, V_S, V_Z, V_T, V_V, V_R}, {V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
+      // each line of Alg. 7 updates its hat (preconditioned) and plain blocks
+      // in one pass: {ph, sh, qh, s, z, q, y; theta, phi, pi} and
+      // {x, rh, r, w; the four dots}
+      it.push_back(G(OP_PP_G12, {V_RH, V_PH, V_SH, V_WH, V_ZH, V_W, V_S, V_Z, V_T, V_V, V_R},
+                     {V_PH, V_SH, V_QH, V_S, V_Z, V_Q, V_Y}, 0, F_PIPE_OMEGA));
       it.push_back(PREC(V_Z, V_ZH));
       it.push_back(SPMM(V_ZH, V_V));
-      it.push_back(G(OP_PP_G3, {V_X, V_PH, V_QH, V_WH, V_ZH}, {V_X, V_RH}));
-      it.push_back(G(OP_PP_G4, {V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_R, V_W}, 3, F_PIPE_BETA_END));
+      it.push_back(G(OP_PP_G34, {V_X, V_PH, V_QH, V_WH, V_ZH, V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S},
+                     {V_X, V_RH, V_R, V_W}, 3, F_PIPE_BETA_END));
       it.push_back(PREC(V_W, V_WH));
-      it.push_back(SPMM(V_WH, V_T));
-    } else if (formulation == 2) {
-      // fused (one device): the passes that make z and w also write zh and wh
-      it.push_back(G(OP_PP_G1, {V_RH, V_PH, V_SH, V_WH, V_ZH}, {V_PH, V_SH, V_QH}));
-      it.push_back(G(OP_F_PP_G2H, {V_W, V_S, V_Z, V_T, V_V, V_R}, {V_S, V_Z, V_Q, V_Y, V_ZH}, 0, F_PIPE_OMEGA));
-      it.push_back(SPMM(V_ZH, V_V));
-      it.push_back(G(OP_PP_G3, {V_X, V_PH, V_QH, V_WH, V_ZH}, {V_X, V_RH}));
-      it.push_back(G(OP_F_PP_G4H, {V_Q, V_Y, V_T, V_V, V_R0, V_Z, V_S}, {V_R, V_W, V_WH}, 3, F_PIPE_BETA_END));
       it.push_back(SPMM(V_WH, V_T));
     } else {
       it.push_back(G(OP_PUPD, {V_RH, V_PH, V_SH}, {V_PH}));  // ph = rh + beta (ph - omega sh)

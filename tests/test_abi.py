@@ -154,15 +154,20 @@ def test_fused_plan_traffic(L):
         assert L.bicgstab_create(ctypes.byref(desc), 4, 1, 3, formulation, precond, precision, None,
                                  ctypes.byref(h)) == _lib.EUNSUPPORTED
     assert L.bicgstab_plan_traffic(3, 2, 0, *[ctypes.byref(r)] * 5) == _lib.EINVAL
-    # fused Alg. 7 with Jacobi: the passes that make z and w also write zh and
-    # wh (23 / 13, no preconditioner pass, against 23 / 11 plus two passes of
-    # 1 / 1); without a preconditioner nothing is folded (fused = merged)
+    # fused Alg. 4: {x, r} and {w, four dots} in one pass keeps r in
+    # registers (16 / 8 against the merged 18 / 8, one launch fewer); with
+    # Jacobi, Alg. 7 runs as Alg. 4 on the folded matrix A M^{-1}: the same 16
+    # / 8 and no hat block, against 23 / 11 plus two passes of 1 / 1
+    f = plan_traffic("pipelined", "fused", "none")
+    mn = plan_traffic("pipelined", "merged", "none")
+    assert (f["reads"], f["writes"], f["spmms"], f["precond_apps"]) == (16, 8, 2, 0)
+    assert (mn["reads"], mn["writes"], mn["spmms"], mn["precond_apps"]) == (18, 8, 2, 0)
+    assert f["launches"] == mn["launches"] - 1
     e = plan_traffic("pipelined", "fused", "jacobi")
     mp = plan_traffic("pipelined", "merged", "jacobi")
-    assert (e["reads"], e["writes"], e["spmms"], e["precond_apps"]) == (23, 13, 2, 0)
+    assert (e["reads"], e["writes"], e["spmms"], e["precond_apps"]) == (16, 8, 2, 0)
     assert (mp["reads"], mp["writes"], mp["precond_apps"]) == (23, 11, 2)
     assert e["launches"] == mp["launches"] - 2
-    assert plan_traffic("pipelined", "fused", "none") == plan_traffic("pipelined", "merged", "none")
 
 
 def test_invalid_arguments_are_errors(L):

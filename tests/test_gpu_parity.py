@@ -38,7 +38,8 @@ from workloads import conv_diff, config_problem, manufactured_rhs, random_sparse
 pytestmark = pytest.mark.gpu
 
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
-# the fused forms (not Improved); their oracle is the merged listing
+# the fused forms (not Improved); their oracle is the merged listing, with
+# Jacobi folded into the products for the classical and Pipelined methods
 METHODS += [(v, "fused", p) for v in ("classical", "reordered", "pipelined") for p in ("none", "jacobi")]
 # Improved BiCGStab (Alg. 3) has no preconditioned form
 METHODS += [("improved", f, "none") for f in ("merged", "basic")]
@@ -121,6 +122,46 @@ def test_tiled_product_matches_row_order(lib, k):
     s = gpu_solver(lib, conv_diff(24, 3, (1.0, 0.7, 0.3)), 16)
     assert s.product_layout() == ((0, 0, 0), (0, 0, 0))
     s.close()
+
+
+def test_tiled_folded_product_pipelined_fused(lib):
+    """The fused Pipelined form with Jacobi runs its plain products on A M^{-1};
+    on a 3D grid at k = 32 those read a tile-ordered copy of the folded values.
+    Its solve equals the row-ordered one (BICGSTAB_SPMM_TILE=0 at create) bit
+    for bit, and the oracle's in the kernels' order on two columns; after
+    update_values the folded tile copy carries the new values (the two
+    handles still agree, and the oracle on the new matrix)."""
+    import os
+    import torch
+
+    say("tiled folded product, pipelined fused jacobi k=32")
+    A = conv_diff(24, 3, (1.0, 0.7, 0.3))
+    k = 32
+    b_np = manufactured_rhs(A, k, seed=12)[0]
+    b = torch.from_numpy(b_np).cuda()
+    st = gpu_solver(lib, A, k, "pipelined", "fused", "jacobi")
+    assert st.product_layout() == ((2, 4, 4), (24, 24, 24))
+    os.environ["BICGSTAB_SPMM_TILE"] = "0"
+    try:
+        sr = gpu_solver(lib, A, k, "pipelined", "fused", "jacobi")
+    finally:
+        del os.environ["BICGSTAB_SPMM_TILE"]
+    assert sr.product_layout() == ((0, 0, 0), (0, 0, 0))
+    for step, M in ((0, A), (1, CSR(A.n, A.row_ptr, A.col_idx, A.values * np.linspace(0.5, 1.5, A.nnz)))):
+        if step:
+            for s in (st, sr):
+                s.update_values(torch.from_numpy(M.values).cuda())
+        xt, it = st.solve(b, tol=1e-8, maxit=500)
+        xr, ir = sr.solve(b, tol=1e-8, maxit=500)
+        assert np.all(it.status == oracle.CONVERGED)
+        assert np.array_equal(it.iters, ir.iters) and np.array_equal(to_np(xt), to_np(xr))
+        X = to_np(xt)
+        for c in (0, k - 1):
+            with oracle_dot(fused_dot(M, k, "pipelined")):
+                ref = oracle.solve_column(M.to_scipy(), b_np[:, c], None, "pipelined", "fused", "jacobi", 1e-8, 500)
+            assert int(it.iters[c]) == ref.iters and np.array_equal(X[:, c], ref.x), (step, c)
+    st.close()
+    sr.close()
 
 
 def test_spmm_and_solve_unaligned_operands(lib):
