@@ -245,11 +245,13 @@ int bicgstab_destroy(bicgstab_t h);
  * Many independent systems A_s X_s = B_s, s = 0..nsys-1, each with its own
  * CSR matrix (sizes may differ widely) and k_s right-hand sides, solved by one
  * persistent kernel in one captured graph launch. Every system runs the
- * merged classical BiCGStab without preconditioner (Appendix B, Alg. 2) on
- * its own share of workgroups, with a barrier per system between the phases
- * of an iteration; the per-column scalars, stop test and statuses are those of
- * bicgstab_solve. The batched method is not in the paper: the paper treats
- * one system with several right-hand sides.
+ * merged classical BiCGStab (Appendix B, Alg. 2; with Jacobi, Alg. 5 in its
+ * fused form: the products read A M^{-1}, entries a_ij / a_jj, and the
+ * solution update divides p and s by a_ii, as bicgstab_solve's fused
+ * classical form does) on its own share of workgroups, with a barrier per
+ * system between the phases of an iteration; the per-column scalars, stop
+ * test and statuses are those of bicgstab_solve. The batched method is not in
+ * the paper: the paper treats one system with several right-hand sides.
  *
  * The kernel variant (threads per workgroup, rows a thread handles per step
  * of a vector phase and of a sparse product, entries per step of a row
@@ -274,9 +276,15 @@ typedef struct bicgstab_batched_ctx* bicgstab_batched_t;
 
 /* As[s]: the matrix of system s (1 <= n < 2^24, nnz < 2^29, n * k * 8 < 2^31;
  * pattern validated on the host, the arrays must outlive the handle); ks[s]
- * in [1, BICGSTAB_MAX_K]. nsys >= 1. Anything else: BICGSTAB_EINVAL. */
-int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, void* stream,
-                            bicgstab_batched_t* out);
+ * in [1, BICGSTAB_MAX_K]. nsys >= 1. variant: BICGSTAB_CLASSICAL (the other
+ * methods: BICGSTAB_EUNSUPPORTED). precond: BICGSTAB_PRECOND_NONE, or
+ * BICGSTAB_PRECOND_JACOBI for every system: create then forms each system's
+ * diagonal and A M^{-1} on the device ((n + nnz) x 8 bytes per system,
+ * library-owned, freed by bicgstab_batched_destroy; values changed after
+ * create are not seen) and a zero diagonal entry fails with BICGSTAB_EINVAL.
+ * Anything else: BICGSTAB_EINVAL. */
+int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, int32_t variant,
+                            int32_t precond, void* stream, bicgstab_batched_t* out);
 /* Device workspace in bytes: six n_s x k_s Krylov blocks per system, the
  * reduction partials, barrier counters, descriptors and results. */
 int bicgstab_batched_workspace_bytes(bicgstab_batched_t h, size_t* bytes);

@@ -78,7 +78,7 @@ def lib():
     L.bicgstab_last_error.argtypes = []
     L.bicgstab_last_error.restype = C.c_char_p
     L.bicgstab_kernel_times.argtypes = [H, vp, vp, i32, i32] + [C.POINTER(i32)] * 4 + [C.POINTER(dbl), C.POINTER(i32)]
-    L.bicgstab_batched_create.argtypes = [C.POINTER(CSRDesc), C.POINTER(i32), i32, vp, C.POINTER(H)]
+    L.bicgstab_batched_create.argtypes = [C.POINTER(CSRDesc), C.POINTER(i32), i32, i32, i32, vp, C.POINTER(H)]
     L.bicgstab_batched_workspace_bytes.argtypes = [H, C.POINTER(C.c_size_t)]
     L.bicgstab_batched_set_workspace.argtypes = [H, vp, C.c_size_t]
     L.bicgstab_batched_set_stream.argtypes = [H, vp]

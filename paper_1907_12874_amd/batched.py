@@ -35,9 +35,10 @@ def variant_info(variant: int):
 
 class BatchedSolver:
     """systems: a sequence of (row_ptr, col_idx, values, k) or of (A, k) with A
-    a host CSR object (row_ptr / col_idx / values arrays)."""
+    a host CSR object (row_ptr / col_idx / values arrays). precond: "none" or
+    "jacobi" (every system; the classical method in either case)."""
 
-    def __init__(self, systems, device="cuda"):
+    def __init__(self, systems, device="cuda", precond="none"):
         self.device = torch.device(device)
         self._mats = []
         descs, ks = [], []
@@ -61,7 +62,8 @@ class BatchedSolver:
         karr = (C.c_int32 * self.nsys)(*ks)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            check(lib().bicgstab_batched_create(arr, karr, self.nsys, C.c_void_p(_stream_ptr(self.device)),
+            check(lib().bicgstab_batched_create(arr, karr, self.nsys, _lib.VARIANTS["classical"],
+                                                _lib.PRECONDS[precond], C.c_void_p(_stream_ptr(self.device)),
                                                 C.byref(h)), "bicgstab_batched_create")
         self._h = h
         nbytes = C.c_size_t()

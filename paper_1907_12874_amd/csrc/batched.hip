@@ -2,8 +2,10 @@
 // right-hand sides each) solved by one persistent kernel launch.
 //
 // Every system owns a contiguous range of workgroups; its workgroups split its
-// rows into contiguous chunks and run the merged classical BiCGStab (Alg. 2)
-// with a per-system barrier between the phases of an iteration:
+// rows into contiguous chunks and run the merged classical BiCGStab (Alg. 2,
+// or with Jacobi Alg. 5 in its fused form: the products read A M^{-1} and the
+// solution update divides p and s by a_ii) with a per-system barrier between
+// the phases of an iteration:
 //   A  v = A p, partial delta = (v, r0)            | barrier | alpha
 //   B  s = r - alpha v                             | barrier (neighbours read s)
 //   C  t = A s, partial phi, psi, theta            | barrier | omega, stop test
@@ -25,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bicgstab.h"
@@ -37,6 +40,8 @@ struct BSys {
   const int32_t* row_ptr;
   const int32_t* col;
   const double* val;
+  const double* val_f;  // values of the iteration's products: A, or A M^{-1} with Jacobi
+  const double* diag;   // a_ii with Jacobi, else null
   const double* b;
   double* x;
   double* vec;   // r, r0, p, v, s, t: 6 blocks of n*k
@@ -206,12 +211,12 @@ __device__ void reduce_partials(const BSys& S, int slot, double (*out)[kMaxK]) {
 // entry 0 (a system without entries points at a zero dummy entry) and add
 // nothing.
 template <int CH, int RU, int NP, class Pre, class Emit>
-__device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
-                                                int row1, int c, Pre pre, Emit emit) {
+__device__ __forceinline__ void product_rows_ch(const BSys& S, const double* V, const gdouble* __restrict__ X,
+                                                int row, int rpp, int row1, int c, Pre pre, Emit emit) {
   if (row >= row1) return;
   gcint* __restrict__ rp = (gcint*)S.row_ptr;
   gcint* __restrict__ col = (gcint*)S.col;
-  gcdouble* __restrict__ val = (gcdouble*)S.val;
+  gcdouble* __restrict__ val = (gcdouble*)V;
   const int k = S.k;
   const int last = row1 - 1;
   // stage being computed: rows row + u * rpp, their offsets and column indices
@@ -293,17 +298,17 @@ __device__ __forceinline__ void product_rows_ch(const BSys& S, const gdouble* __
 // The product with CH pipelined slots at most: fewer when no row of the
 // system has more entries (5 for a 5-point, 7 for a 7-point stencil), so no
 // slot is spent on padding every row shares. The sums are the same (a slot
-// past a row's end is never added).
+// past a row's end is never added). V: the values (A's, or A M^{-1}'s).
 template <int CH, int RU, int NP, class Pre, class Emit>
-__device__ __forceinline__ void product_rows(const BSys& S, const gdouble* __restrict__ X, int row, int rpp,
-                                             int row1, int c, Pre pre, Emit emit) {
+__device__ __forceinline__ void product_rows(const BSys& S, const double* V, const gdouble* __restrict__ X, int row,
+                                             int rpp, int row1, int c, Pre pre, Emit emit) {
   if constexpr (CH > 5) {
-    if (S.maxlen <= 5) return product_rows_ch<5, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
+    if (S.maxlen <= 5) return product_rows_ch<5, RU, NP>(S, V, X, row, rpp, row1, c, pre, emit);
   }
   if constexpr (CH > 7) {
-    if (S.maxlen <= 7) return product_rows_ch<7, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
+    if (S.maxlen <= 7) return product_rows_ch<7, RU, NP>(S, V, X, row, rpp, row1, c, pre, emit);
   }
-  product_rows_ch<CH, RU, NP>(S, X, row, rpp, row1, c, pre, emit);
+  product_rows_ch<CH, RU, NP>(S, V, X, row, rpp, row1, c, pre, emit);
 }
 
 enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_EPS2, B_BB, B_NS };
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < k)
     product_rows<CH, RU, 1>(
-        S, x, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(b, e); },
+        S, S.val, x, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(b, e); },
         [&](int, unsigned e, double z, const double(&q)[1]) {
           const double bv = q[0];
           const double res = bv - z;
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     acc[0] = 0.0;
     if (run1)
       product_rows<CH, RU, 1>(
-          S, p, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(r0, e); },
+          S, S.val_f, p, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(r0, e); },
           [&](int, unsigned e, double z, const double(&q)[1]) {
             at(v, e) = z;
             acc[0] += z * q[0];
@@ -462,7 +467,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     acc[0] = acc[1] = acc[2] = 0.0;
     if (run2)
       product_rows<CH, RU, 1>(
-          S, s, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(s, e); },
+          S, S.val_f, s, row0 + rsub, rpp, row1, c, [&](unsigned e, double(&q)[1]) { q[0] = at(s, e); },
           [&](int, unsigned e, double tt, const double(&q)[1]) {
             const double ss = q[0];
             at(t, e) = tt;
@@ -491,12 +496,16 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
     }
     __syncthreads();
     // ---- D: x += alpha p + omega s; r = s - omega t; rho' = (r, r0)
+    // (with Jacobi x += alpha p / a_ii + omega s / a_ii: Alg. 5's p-hat and
+    // s-hat, formed here for the update alone)
     const bool run3 = c < k && st[c] == ST_RUNNING;
     acc[0] = 0.0;
-    if (run3) {
+    auto phase_d = [&](auto jac) {
+      constexpr bool J = decltype(jac)::value;
+      gcdouble* __restrict__ dg = (gcdouble*)S.diag;
       const double alpha = sc[B_ALPHA][c], omega = sc[B_OMEGA][c];
       for (int row = row0 + rsub; row < row1; row += VU * rpp) {
-        double xv[VU], pv[VU], sv[VU], tv[VU], qv[VU];
+        double xv[VU], pv[VU], sv[VU], tv[VU], qv[VU], dv[VU];
 #pragma unroll
         for (int u = 0; u < VU; ++u) {
           const int rr = row + u * rpp;
@@ -507,6 +516,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
             sv[u] = at(s, e);
             tv[u] = at(t, e);
             qv[u] = at(r0, e);
+            if constexpr (J) dv[u] = at(dg, (unsigned)rr);
           }
         }
 #pragma unroll
@@ -514,13 +524,22 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
           const int rr = row + u * rpp;
           if (rr < row1) {
             const unsigned e = eidx(rr);
-            at(x, e) = xv[u] + alpha * pv[u] + omega * sv[u];
+            if constexpr (J)
+              at(x, e) = xv[u] + alpha * (pv[u] / dv[u]) + omega * (sv[u] / dv[u]);
+            else
+              at(x, e) = xv[u] + alpha * pv[u] + omega * sv[u];
             const double res = sv[u] - omega * tv[u];
             at(r, e) = res;
             acc[0] += res * qv[u];
           }
         }
       }
+    };
+    if (run3) {
+      if (S.diag)
+        phase_d(std::true_type{});
+      else
+        phase_d(std::false_type{});
     }
     store_partials<BS, 1>(S, 3, w, acc, s_w);
     if (!barrier()) return;
@@ -585,7 +604,7 @@ __global__ __launch_bounds__(BS) void batched_kernel(const BGlob* __restrict__ G
   acc[0] = acc[1] = 0.0;
   if (c < k)
     product_rows<CH, RU, 2>(
-        S, x, row0 + rsub, rpp, row1, c,
+        S, S.val, x, row0 + rsub, rpp, row1, c,
         [&](unsigned e, double(&q)[2]) {
           q[0] = at(b, e);
           q[1] = at(r, e);
@@ -688,6 +707,11 @@ struct bicgstab_batched_ctx {
   std::vector<int> k;
   std::vector<const int32_t*> rp, col;
   std::vector<const double*> val;
+  // Jacobi: per system a_ii and A M^{-1} (entries a_ij / a_jj), formed at
+  // create in one library-owned allocation
+  int precond = BICGSTAB_PRECOND_NONE;
+  char* jac = nullptr;
+  std::vector<const double*> diag, val_f;
   size_t total_cols = 0;
   int kp_max = 1;
   hipStream_t user_stream = nullptr, ws = nullptr;
@@ -893,6 +917,8 @@ int run(bicgstab_batched_ctx* h, const double* const* b, double* const* x, doubl
     d.row_ptr = h->rp[s];
     d.col = h->nnz[s] > 0 ? h->col[s] : (const int32_t*)(h->base + h->o_dummy);
     d.val = h->nnz[s] > 0 ? h->val[s] : (const double*)(h->base + h->o_dummy + 8);
+    d.val_f = h->precond == BICGSTAB_PRECOND_JACOBI && h->nnz[s] > 0 ? h->val_f[s] : d.val;
+    d.diag = h->precond == BICGSTAB_PRECOND_JACOBI ? h->diag[s] : nullptr;
     d.b = b[s];
     d.x = x[s];
     d.vec = (double*)(h->base + h->o_vec[s]);
@@ -979,22 +1005,64 @@ void destroy_ctx(bicgstab_batched_ctx* h) {
   if (h->ws) (void)hipStreamSynchronize(h->ws);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   if (h->owned && h->base) (void)hipFree(h->base);
+  if (h->jac) (void)hipFree(h->jac);
   if (h->ws) (void)hipStreamDestroy(h->ws);
   for (hipEvent_t e : {h->ev, h->t0, h->t1})
     if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
+// Jacobi set-up: every system's diagonal (a zero entry is an error) and its
+// Jacobi-folded values A M^{-1}, one division per entry, as the single-system
+// path forms them.
+int build_jacobi(bicgstab_batched_ctx* h) {
+  size_t total = 256;  // a zero-diagonal counter first
+  std::vector<size_t> od(h->nsys), of(h->nsys);
+  for (int s = 0; s < h->nsys; ++s) {
+    od[s] = total;
+    total += ((size_t)h->n[s] * 8 + 255) / 256 * 256;
+    of[s] = total;
+    total += ((size_t)h->nnz[s] * 8 + 255) / 256 * 256;
+  }
+  if (hipMalloc((void**)&h->jac, total) != hipSuccess) {
+    h->jac = nullptr;
+    (void)hipGetLastError();
+    return bfail(BICGSTAB_ENOMEM, "Jacobi set-up: device allocation failed");
+  }
+  Globals* g = (Globals*)h->jac;
+  BCHK(hipMemsetAsync(g, 0, sizeof(Globals), h->ws));
+  for (int s = 0; s < h->nsys; ++s) {
+    double* d = (double*)(h->jac + od[s]);
+    double* f = (double*)(h->jac + of[s]);
+    h->diag.push_back(d);
+    h->val_f.push_back(f);
+    BCHK(launch_extract_diag(h->rp[s], h->col[s], h->val[s], d, nullptr, (int)h->n[s], g, h->ws));
+    BCHK(launch_fold_jacobi(h->col[s], h->val[s], d, f, nullptr, h->nnz[s], h->ws));
+  }
+  Globals hg;
+  BCHK(hipMemcpyAsync(&hg, g, sizeof hg, hipMemcpyDeviceToHost, h->ws));
+  BCHK(hipStreamSynchronize(h->ws));
+  if (hg.zero_diag > 0)
+    return bfail(BICGSTAB_EINVAL, "Jacobi preconditioner: " + std::to_string(hg.zero_diag) + " zero diagonal entries");
+  return BICGSTAB_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, void* stream,
-                            bicgstab_batched_t* out) {
+int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t nsys, int32_t variant,
+                            int32_t precond, void* stream, bicgstab_batched_t* out) {
   if (!As || !ks || !out || nsys < 1) return bfail(BICGSTAB_EINVAL, "null argument or no systems");
   *out = nullptr;
+  if (variant < BICGSTAB_CLASSICAL || variant > BICGSTAB_IMPROVED ||
+      (precond != BICGSTAB_PRECOND_NONE && precond != BICGSTAB_PRECOND_JACOBI))
+    return bfail(BICGSTAB_EINVAL, "unknown variant or preconditioner");
+  if (variant != BICGSTAB_CLASSICAL)
+    return bfail(BICGSTAB_EUNSUPPORTED, "the batched kernel runs the classical method only");
   auto* h = new bicgstab_batched_ctx();
   h->nsys = nsys;
+  h->precond = precond;
   h->user_stream = (hipStream_t)stream;
   for (int s = 0; s < nsys; ++s) {
     const bicgstab_csr& A = As[s];
@@ -1045,6 +1113,13 @@ int bicgstab_batched_create(const bicgstab_csr* As, const int32_t* ks, int32_t n
   }
   if (wall_khz > 0) h->wall_hz = 1e3 * wall_khz;
   h->cus = prop.multiProcessorCount;
+  if (precond == BICGSTAB_PRECOND_JACOBI) {
+    const int rc = build_jacobi(h);
+    if (rc) {
+      destroy_ctx(h);
+      return rc;
+    }
+  }
   for (int v = 0; v < kNumVariants; ++v) {
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel_of(v), kVariants[v].block, 0) != hipSuccess) {

@@ -35,6 +35,11 @@ def oracle_kernel_order(A, k, nw, block, *args, **kw):
         return oracle.solve(A.to_scipy(), *args, **kw)
 
 
+# the oracle of the batched kernel: Alg. 2, or with Jacobi Alg. 5 with M^{-1}
+# folded into the products (the single-system path's fused classical form)
+METHOD = {"none": {}, "jacobi": {"variant": "classical", "formulation": "fused", "precond": "jacobi"}}
+
+
 def _batch(nsys, seed, nmin=200, nmax=5000):
     systems = batched_systems(nsys, seed, nmin=nmin, nmax=nmax)
     rhs = [manufactured_rhs(A, k, seed * 1000 + s)[0] for s, (A, k) in enumerate(systems)]
@@ -50,7 +55,7 @@ def _gpu_solve(lib, systems, rhs, tol, maxit, x0s=None, solver=None):
     return bs, [x.cpu().numpy() for x in xs], infos
 
 
-def _check_bitwise(bs, systems, rhs, X, infos, tol, maxit, x0s=None, which=None):
+def _check_bitwise(bs, systems, rhs, X, infos, tol, maxit, x0s=None, which=None, precond="none"):
     """Per system: the oracle in the kernel's summation order gives the same
     pass counts, statuses and iterates, bit for bit; the library's true
     residual equals one recomputed on the host."""
@@ -59,7 +64,8 @@ def _check_bitwise(bs, systems, rhs, X, infos, tol, maxit, x0s=None, which=None)
     for s in (range(len(systems)) if which is None else which):
         A, k = systems[s]
         b = rhs[s]
-        ref = oracle_kernel_order(A, k, int(wg[s]), block, b, None if x0s is None else x0s[s], tol=tol, maxit=maxit)
+        ref = oracle_kernel_order(A, k, int(wg[s]), block, b, None if x0s is None else x0s[s], tol=tol, maxit=maxit,
+                                  **METHOD[precond])
         info = infos[s]
         assert np.array_equal(info.status, ref.status), (s, info.status, ref.status)
         assert np.array_equal(info.iters, ref.iters), (s, info.iters, ref.iters)
@@ -232,6 +238,61 @@ def test_batched_variants_agree_bitwise(lib):
         v += 1
     assert v >= 2 and len(by_block) >= 2
     bs.close()
+
+
+def _row_scaled(systems, seed):
+    """The systems with each row scaled by a factor in [0.3, 3]: a diagonal
+    that varies from row to row, so Jacobi is not a plain rescaling."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for A, k in systems:
+        f = rng.uniform(0.3, 3.0, A.n)
+        out.append((CSR(A.n, A.row_ptr, A.col_idx, A.values * np.repeat(f, np.diff(A.row_ptr))), k))
+    return out
+
+
+def test_batched_jacobi_bitwise(lib):
+    """Jacobi on every system (12 row-scaled systems, n in [200, 5000], k in
+    1..8): 12 fixed passes, then a solve to 1e-8 with initial guesses, bit for
+    bit the oracle's Alg. 5 with A M^{-1} folded into the products, summed in
+    the kernel's order; every column converges with a true residual <= 1.1
+    tol."""
+    systems, _ = _batch(12, seed=5)
+    systems = _row_scaled(systems, 6)
+    rhs = [manufactured_rhs(A, k, 600 + s)[0] for s, (A, k) in enumerate(systems)]
+    x0s = [np.random.default_rng(700 + s).uniform(-0.5, 0.5, (A.n, k)) for s, (A, k) in enumerate(systems)]
+    say(f"batched jacobi: {[(A.n, k) for A, k in systems]}")
+    bs = lib.BatchedSolver(systems, precond="jacobi")
+    _, X, infos = _gpu_solve(lib, systems, rhs, tol=0.0, maxit=12, solver=bs)
+    _check_bitwise(bs, systems, rhs, X, infos, 0.0, 12, precond="jacobi")
+    _, X, infos = _gpu_solve(lib, systems, rhs, tol=1e-8, maxit=3000, x0s=x0s, solver=bs)
+    say(f"  passes {[int(i.iters.max()) for i in infos]}")
+    for info in infos:
+        assert np.all(info.status == oracle.CONVERGED) and np.all(info.relres_true <= 1.1e-8)
+    _check_bitwise(bs, systems, rhs, X, infos, 1e-8, 3000, x0s=x0s, precond="jacobi")
+    bs.close()
+
+
+def test_batched_jacobi_rejects(lib):
+    """Jacobi with a zero diagonal entry in any system fails at create; a
+    method other than the classical one is unsupported."""
+    from paper_1907_12874_amd import _lib
+
+    A = conv_diff(6, 2, (1.0, 0.5))
+    vals = A.values.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    vals[(rows == 4) & (A.col_idx == 4)] = 0.0
+    with pytest.raises(lib.BicgstabError, match="zero diagonal"):
+        lib.BatchedSolver([(A, 1), (CSR(A.n, A.row_ptr, A.col_idx, vals), 2)], precond="jacobi")
+    lib.BatchedSolver([(CSR(A.n, A.row_ptr, A.col_idx, vals), 2)]).close()  # fine without a preconditioner
+    import ctypes as C
+
+    desc = (_lib.CSRDesc * 1)(_lib.CSRDesc(4, 0, None, None, None))
+    ks = (C.c_int32 * 1)(1)
+    h = C.c_void_p()
+    L = _lib.lib()
+    assert L.bicgstab_batched_create(desc, ks, 1, 2, 0, None, C.byref(h)) == _lib.EUNSUPPORTED
+    assert L.bicgstab_batched_create(desc, ks, 1, 0, 7, None, C.byref(h)) == _lib.EINVAL
 
 
 def test_batched_rejects_bad_input(lib):
