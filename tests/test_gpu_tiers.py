@@ -25,8 +25,9 @@ def say(*a):
 # ------------------------------------------------------------- precision ---
 
 @pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
-                                                         ("pipelined", "none", "merged"), ("reordered", "jacobi", "merged"),
-                                                         ("classical", "jacobi", "fused"), ("reordered", "jacobi", "fused"),
+                                                         ("pipelined", "none", "merged"), ("pipelined", "jacobi", "merged"),
+                                                         ("reordered", "jacobi", "merged"), ("classical", "jacobi", "fused"),
+                                                         ("reordered", "jacobi", "fused"), ("pipelined", "none", "fused"),
                                                          ("pipelined", "jacobi", "fused")])
 def test_precision_tier_matches_refinement_oracle(lib, variant, precond, formulation):
     """27-point random matrix (the precision-tier recipe at 20^3), k = 8,
