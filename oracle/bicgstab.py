@@ -370,7 +370,7 @@ def alg3_merged_ibicgstab(A, b, x0, tol, maxit, trace=None, trace_vectors=False)
 
 # ------------------------------------------------------------- reordered ---
 
-def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False):
+def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=False, A_prec=None, Minv_x=None):
     """Alg. 6: merged Reordered BiCGStab. The preconditioner is applied to
     v_j and t_j (s_j = M^{-1} v_j, q_j = M^{-1} t_j) so that z_{j+1} = M^{-1}
     r_{j+1} comes from a vector update; rho_{j+1} = -omega_j psi_j uses the
@@ -378,11 +378,21 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     taken as printed (it already carries the paper's fix of the original).
     When rounding has used up what that relation carries (the restart test of
     the module docstring), the method restarts with r_{j+1} as the shadow
-    vector."""
+    vector.
+
+    A_prec, if given, is A M^{-1} stored as a matrix (a diagonal M, with
+    Minv_x applying M^{-1}); Minv is then the identity. Alg. 6 preconditions
+    from the right: with p_j defined by v-hat_j = M^{-1} p_j, its vectors obey
+    v = (A M^{-1}) p, t-hat = M^{-1} r-tilde, t = (A M^{-1}) r-tilde, z =
+    M^{-1} r, so the listing run on A M^{-1} without a preconditioner carries
+    p and r-tilde where it carried v-hat and t-hat, and the solution update
+    becomes x += alpha M^{-1} p + omega M^{-1} r-tilde: Alg. 6's iterates in
+    exact arithmetic, with no preconditioned block kept."""
     rec = _Recorder(trace, trace_vectors)
     early, x, r, rho, eps2 = _begin(A, b, x0, tol)
     if early is not None:
         return early
+    op = A if A_prec is None else A_prec
     r0 = r.copy()
     z = Minv(r)
     vh = z.copy()
@@ -390,7 +400,7 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
     err = rho         # E_0
     est_prev = rho    # ||r_0||^2
     for j in range(maxit):
-        v = A @ vh
+        v = op @ vh
         delta = dot(v, r0)
         if delta == 0.0:
             return ColumnResult(x, r, j + 1, BREAKDOWN, trace)
@@ -399,7 +409,7 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
         if not np.isfinite(alpha):
             return ColumnResult(x, r, j + 1, NONFINITE, trace)
         th = z - alpha * s
-        t = A @ th
+        t = op @ th
         rt = r - alpha * v
         theta, phi, psi, eta = dot(t, rt), dot(t, t), dot(t, r0), dot(rt, rt)
         q = Minv(t)
@@ -428,7 +438,10 @@ def alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, trace=None, trace_vectors=
                     if not np.isfinite(beta):
                         return ColumnResult(x, r, j + 1, NONFINITE, trace)
         r = rt - omega * t
-        x = x + alpha * vh + omega * th
+        if Minv_x is None:
+            x = x + alpha * vh + omega * th
+        else:
+            x = x + alpha * Minv_x(vh) + omega * Minv_x(th)
         rec(j, {"alpha": alpha, "omega": omega, "rho": rho, "est": est, "theta": theta, "phi": phi, "psi": psi,
                 "eta": eta, "err": err, "restart": restart}, x=x, r=r, rt=rt, r0=r0)
         if stop:
@@ -600,9 +613,8 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
     regrouping of the merged statements: dots formed in the sparse products'
     epilogues, the Jacobi division done by the pass that produces the vector)
     computes the merged listing's statements, so it maps to that listing;
-    for the classical and Pipelined methods with Jacobi it folds M^{-1} into
-    the products (Alg. 5, and Alg. 4 standing for Alg. 7, with A M^{-1} stored
-    as a matrix)."""
+    with Jacobi it folds M^{-1} into the products (Alg. 5, Alg. 6, and Alg. 4
+    standing for Alg. 7, with A M^{-1} stored as a matrix)."""
     import scipy.sparse as sp
 
     A = sp.csr_matrix(A)
@@ -633,6 +645,10 @@ def solve_column(A, b, x0=None, variant="classical", formulation="merged", preco
             return alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, A_prec=jacobi_folded_operator(A), **kw)
         return alg5_merged_pbicgstab(A, b, x0, tol, maxit, Minv, **kw)
     if variant == "reordered":
+        if fused and precond == "jacobi":
+            # Alg. 6 with Jacobi folded into the products: the listing on A M^{-1}
+            return alg6_merged_rbicgstab(A, b, x0, tol, maxit, identity_preconditioner(A),
+                                         A_prec=jacobi_folded_operator(A), Minv_x=Minv, **kw)
         return alg6_merged_rbicgstab(A, b, x0, tol, maxit, Minv, **kw)
     if precond == "none":
         return alg4_merged_pipebicgstab(A, b, x0, tol, maxit, **kw)

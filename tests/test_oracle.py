@@ -17,10 +17,10 @@ from workloads import conv_diff, manufactured_rhs, random_sparse
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
-# the fused classical and Pipelined forms with Jacobi fold M^{-1} into the
-# products (A M^{-1} as a matrix), a rounding-level change of Alg. 5 and Alg.
-# 7; the other fused forms run the merged listing
-METHODS += [("classical", "fused", "jacobi"), ("pipelined", "fused", "jacobi")]
+# the fused forms with Jacobi fold M^{-1} into the products (A M^{-1} as a
+# matrix), a rounding-level change of Alg. 5, 6 and 7; without a
+# preconditioner the fused forms run the merged listing
+METHODS += [("classical", "fused", "jacobi"), ("reordered", "fused", "jacobi"), ("pipelined", "fused", "jacobi")]
 
 
 def _tiny_systems():
@@ -237,6 +237,36 @@ def test_pipelined_folded_jacobi_tracks_alg7():
     r7 = solve_column(A, b, None, "pipelined", "merged", "jacobi", 1e-10, 500)
     assert rf.status == r7.status == CONVERGED and abs(rf.iters - r7.iters) <= 2
     assert np.linalg.norm(b - A @ rf.x) <= 1.1e-10 * np.linalg.norm(b)
+
+
+def test_reordered_folded_jacobi_tracks_alg6():
+    """The folded Reordered form (Alg. 6 on A M^{-1} with no preconditioner,
+    x += alpha M^{-1} p + omega M^{-1} r-tilde) takes Alg. 6's steps: over
+    the first passes its x, r and scalars agree with the preconditioned
+    listing's to rounding (r-tilde too, against ||b||), and both
+    stop at 1e-10 within three passes of each other. A product with A instead
+    of A M^{-1}, or an update with p in place of M^{-1} p, fails from the
+    first pass."""
+    A = conv_diff(10, 3, (1.0, 0.7, 0.3)).to_scipy()
+    A.data = A.data * np.random.default_rng(6).uniform(0.5, 2.0, A.nnz)
+    A = A + sp.diags(np.random.default_rng(7).uniform(2.0, 9.0, A.shape[0]) * abs(A).sum(axis=1).A1 / 4)
+    A = sp.csr_matrix(A)
+    b = np.random.default_rng(8).uniform(-1, 1, A.shape[0])
+    tf, t6 = [], []
+    solve_column(A, b, None, "reordered", "fused", "jacobi", 0.0, 6, trace=tf, trace_vectors=True)
+    solve_column(A, b, None, "reordered", "merged", "jacobi", 0.0, 6, trace=t6, trace_vectors=True)
+    nb = np.linalg.norm(b)
+    for f, m in zip(tf, t6):
+        assert np.linalg.norm(f["vec"]["x"] - m["vec"]["x"]) <= 1e-10 * np.linalg.norm(m["vec"]["x"])
+        assert np.linalg.norm(f["vec"]["r"] - m["vec"]["r"]) <= 1e-12 * nb
+        assert np.linalg.norm(f["vec"]["rt"] - m["vec"]["rt"]) <= 1e-12 * nb
+    for f, m in zip(tf[:4], t6[:4]):
+        assert abs(f["alpha"] - m["alpha"]) <= 1e-10 * abs(m["alpha"])
+        assert abs(f["omega"] - m["omega"]) <= 1e-10 * abs(m["omega"])
+    rf = solve_column(A, b, None, "reordered", "fused", "jacobi", 1e-10, 500)
+    r6 = solve_column(A, b, None, "reordered", "merged", "jacobi", 1e-10, 500)
+    assert rf.status == r6.status == CONVERGED and abs(rf.iters - r6.iters) <= 3
+    assert np.linalg.norm(b - A @ rf.x) <= 1.1e-10 * nb
 
 
 def test_pipelined_auxiliary_vectors():
