@@ -72,11 +72,11 @@ enum { BICGSTAB_CLASSICAL = 0, BICGSTAB_REORDERED = 1, BICGSTAB_PIPELINED = 2, B
  * fused = the merged statements with the further fusions only a single device
  * allows: dot products formed in the sparse products' epilogues, the Jacobi
  * scaling written by the pass or product that makes its input, adjacent
- * passes of one scalar phase joined. With Jacobi the classical and Pipelined
- * fused forms fold M^{-1} into the products (A M^{-1} stored as a matrix, one
- * more nnz x 8 bytes of workspace; Alg. 5 and Alg. 7 precondition from the
- * right, so the iterates are the listings' in exact arithmetic and differ
- * from the merged form's by rounding). Built for the classical, Reordered and
+ * passes of one scalar phase joined. With Jacobi the fused forms fold M^{-1}
+ * into the products (A M^{-1} stored as a matrix, one more nnz x 8 bytes of
+ * workspace; Alg. 5, 6 and 7 precondition from the right, so the iterates are
+ * the listings' in exact arithmetic and differ from the merged form's by
+ * rounding). Built for the classical, Reordered and
  * Pipelined methods; fused Improved returns BICGSTAB_EUNSUPPORTED. */
 enum { BICGSTAB_MERGED = 0, BICGSTAB_BASIC = 1, BICGSTAB_FUSED = 2 };
 /* Preconditioners: none, or Jacobi M = diag(A) applied as u / a_ii. */
@@ -121,8 +121,8 @@ typedef struct bicgstab_ctx* bicgstab_t;
  * (malformed offsets or a column index out of range: BICGSTAB_EINVAL) and to
  * plan the sparse products; for a 3D grid pattern at k = 32 it also builds a
  * library-owned tile-ordered copy of A (nnz x 16 + n x 8 bytes of device
- * memory, nnz x 8 more for the fused Pipelined form with Jacobi, which also
- * keeps A M^{-1} in that order; freed by bicgstab_destroy; see
+ * memory, nnz x 8 more for the fused Reordered and Pipelined forms with
+ * Jacobi, which also keep A M^{-1} in that order; freed by bicgstab_destroy; see
  * bicgstab_product_layout). stream: a
  * hipStream_t (NULL = the null stream). The Jacobi diagonal is extracted at
  * the first solve; a zero diagonal entry then fails with BICGSTAB_EINVAL. */
@@ -209,8 +209,8 @@ int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y);
  * tx}, grid = {nz, ny, nx}, all zero when A is stored row by row (other
  * patterns, other k, the FP32 tier, the environment variable
  * BICGSTAB_SPMM_TILE=0 at create). Products with dot epilogues keep the row
- * order; the plain products of A M^{-1} (fused Pipelined with Jacobi) use the
- * tile order too. Either pointer may be NULL. */
+ * order; the plain products of A M^{-1} (fused Reordered and Pipelined with
+ * Jacobi) use the tile order too. Either pointer may be NULL. */
 int bicgstab_product_layout(bicgstab_t h, int32_t* tile, int32_t* grid);
 
 /* Per-iteration history of the last solve: for iteration j < count and column

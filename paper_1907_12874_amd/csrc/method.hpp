@@ -171,6 +171,32 @@ struct KRG3 {  // in: r, v, t, r0 ; out: rt ; (t, rt), (t, t), (t, r0), (rt, rt)
     a[3] += rt * rt;
   }
 };
+struct KRDots {  // in: t, rt, r0 ; (t, rt), (t, t), (t, r0), (rt, rt)
+  OP_HEAD(3, 0, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    a[0] += v[0] * v[1];
+    a[1] += v[0] * v[0];
+    a[2] += v[0] * v[2];
+    a[3] += v[1] * v[1];
+  }
+};
+// Alg. 6 on A M^{-1} (Jacobi folded into the products): in: rt, t, x, p, v
+// (+ a_ii) ; out: r, x, p, and r0 = r where the column restarts. Alg. 6's
+// z_{j+1} is r_{j+1} here, and its v-hat and t-hat are p / a_ii and rt / a_ii,
+// formed for the solution update alone (rounded to the storage type as a
+// stored copy would be).
+struct KFReXvD {
+  OP_HEAD_C(5, 4, 0, 4, 2, PART_RUN, true, true, 8u)
+  OP_F {
+    const double r = R(v[0] - c.omega * v[1]);
+    const double ph = R(v[3] / v[5]);
+    const double th = R(v[0] / v[5]);
+    o[0] = r;
+    o[1] = v[2] + c.alpha * ph + c.omega * th;
+    o[2] = r + c.beta * (v[3] - c.omega * v[4]);
+    o[3] = r;
+  }
+};
 struct KRXzv {  // in: x, vh, th, q, s ; out: x, z, vh
   OP_HEAD(5, 3, 0, 1, 1, PART_RUN, true)
   OP_F {

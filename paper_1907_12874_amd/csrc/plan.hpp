@@ -138,6 +138,9 @@ enum OpId {
   OP_F_XR_RHO_D,     // folded Jacobi, Alg. 5: x += alpha p / a_ii + omega s / a_ii; r = s - omega t; dot (r, r0)
   OP_F_P_G23,        // fused Alg. 4: OP_P_G2 and OP_P_G3 in one pass (r kept in registers); 4 dots
   OP_F_P_G23D,       // folded Jacobi, Alg. 7 as Alg. 4 on A M^{-1}: the same with x += (alpha p + omega q) / a_ii
+  OP_R_DOTS,         // Alg. 6: (t, rt), (t, t), (t, r0), (rt, rt)
+  OP_F_RE_XVD,       // folded Jacobi, Alg. 6 on A M^{-1}: r = rt - omega t (r0 = r on a restart);
+                     //   x += alpha p / a_ii + omega rt / a_ii; p = r + beta (p - omega v)
   OP_NUM
 };
 
