@@ -121,8 +121,8 @@ typedef struct bicgstab_ctx* bicgstab_t;
  * (malformed offsets or a column index out of range: BICGSTAB_EINVAL) and to
  * plan the sparse products; for a 3D grid pattern at k = 32 it also builds a
  * library-owned tile-ordered copy of A (nnz x 16 + n x 8 bytes of device
- * memory, nnz x 8 more for the fused Reordered and Pipelined forms with
- * Jacobi, which also keep A M^{-1} in that order; freed by bicgstab_destroy; see
+ * memory, nnz x 8 more for the fused forms with Jacobi, which also keep
+ * A M^{-1} in that order; freed by bicgstab_destroy; see
  * bicgstab_product_layout). stream: a
  * hipStream_t (NULL = the null stream). The Jacobi diagonal is extracted at
  * the first solve; a zero diagonal entry then fails with BICGSTAB_EINVAL. */
@@ -198,19 +198,22 @@ int bicgstab_update_values(bicgstab_t h, const double* d_values);
  * handle's stream, asynchronous. For kernel-level checks and timing. */
 int bicgstab_spmm(bicgstab_t h, const double* d_x, double* d_y);
 
-/* How the plain FP64 product (Section 3.1's SpMM; the product of the merged
- * and basic forms and of bicgstab_spmm) stores A. When the pattern is a 3D
- * grid in natural order (x fastest) whose entries couple each row only to rows
- * one step away in x, y and z (7- and 27-point stencils), k = 32 (row blocks
- * of 32 rows) and the grid divides into 2 x 4 x 4 tiles, create keeps a
- * library-owned copy of A with its rows tile by tile (one tile per row block)
- * and the product writes each row of Y at its own index: the same sums,
- * bitwise, with fewer row blocks sharing a row's neighbours. tile = {tz, ty,
- * tx}, grid = {nz, ny, nx}, all zero when A is stored row by row (other
- * patterns, other k, the FP32 tier, the environment variable
- * BICGSTAB_SPMM_TILE=0 at create). Products with dot epilogues keep the row
- * order; the plain products of A M^{-1} (fused Reordered and Pipelined with
- * Jacobi) use the tile order too. Either pointer may be NULL. */
+/* How the FP64 sparse products (Section 3.1's SpMM: the plain product, the
+ * products with dot epilogues of the fused forms, and bicgstab_spmm) store A.
+ * When the pattern is a 3D grid in natural order (x fastest) whose entries
+ * couple each row only to rows one step away in x, y and z (7- and 27-point
+ * stencils), k = 32 (row blocks of 32 rows) and the grid divides into
+ * 2 x 4 x 4 tiles, create keeps a library-owned copy of A with its rows tile
+ * by tile (one tile per row block): the tiles in the natural order of their
+ * first grid point, the points of a tile in natural order within it (x
+ * fastest). Each product writes every row of Y at its own index, and each
+ * row's sum is bitwise that of the row order, with fewer row blocks sharing a
+ * row's neighbours; the dot products of a product's epilogue add the rows in
+ * the stored order (so a fused form's iterates follow the layout). The fused
+ * forms with Jacobi keep A M^{-1} in the same order. tile = {tz, ty, tx},
+ * grid = {nz, ny, nx}, all zero when A is stored row by row (other patterns,
+ * other k, the FP32 tier, the environment variable BICGSTAB_SPMM_TILE=0 at
+ * create). Either pointer may be NULL. */
 int bicgstab_product_layout(bicgstab_t h, int32_t* tile, int32_t* grid);
 
 /* Per-iteration history of the last solve: for iteration j < count and column

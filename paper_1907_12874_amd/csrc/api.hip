@@ -408,8 +408,17 @@ hipError_t launch_step(bicgstab_ctx* h, const Step& st, const SpmmMat& M0, void*
       const void* w = epilogue_dots(st.op) > 0 ? vp[st.in[1]] : nullptr;
       void* yh = epilogue_prec(st.op) ? vp[st.out[1]] : nullptr;
       const void* diag = fp32 ? (const void*)h->diag32 : (const void*)h->diag;
-      return launch_spmm_dot(M, vp[st.in[0]], vp[st.out[0]], w, yh, diag, st.op, h->k, fp32, ctl, st.slot, st.fin,
-                             M.bpart, g, s, defer);
+      // the tile-ordered copy where it holds these values and the same number
+      // of row blocks (the partials buffer and the pending-step links are
+      // sized by it); the epilogue reads and writes each row at its own index
+      SpmmMat Me = M;
+      if (h->tiled && !fp32 && M.blk == h->blk && (!st.fold || h->val_fold_p) &&
+          h->part_p.blk.size() == h->part.blk.size()) {
+        Me = tiled_mat(h, st.fold != 0);
+        Me.bpart = M.bpart;
+      }
+      return launch_spmm_dot(Me, vp[st.in[0]], vp[st.out[0]], w, yh, diag, st.op, h->k, fp32, ctl, st.slot, st.fin,
+                             Me.bpart, g, s, defer);
     }
     case K_PREC:
       return launch_prec(vp[st.in[0]], vp[st.out[0]], fp32 ? (const void*)h->diag32 : (const void*)h->diag,
@@ -817,10 +826,10 @@ void build_tiles(bicgstab_ctx* h, const std::vector<int32_t>& rp, const std::vec
   bool ok = alloc((void**)&h->rp_p, ((size_t)n + 1) * 4) && alloc((void**)&h->col_p, (size_t)h->nnz * 4) &&
             alloc((void**)&h->perm_p, (size_t)h->nnz * 4) && alloc((void**)&h->rowmap_p, (size_t)n * 4) &&
             alloc((void**)&h->val_p, (size_t)h->nnz * 8) && alloc((void**)&h->blk_p, P.blk.size() * 4);
-  // folded values for plain products of the plan (filled where the fold is formed)
-  bool plain_fold = false;
-  for (const Step& st : h->plan.iter) plain_fold |= st.kind == K_SPMM && st.fold;
-  if (plain_fold && !fp32_inner(h)) ok = ok && alloc((void**)&h->val_fold_p, (size_t)h->nnz * 8);
+  // folded values for the plan's products with A M^{-1} (filled where the fold is formed)
+  bool any_fold = false;
+  for (const Step& st : h->plan.iter) any_fold |= (st.kind == K_SPMM || st.kind == K_SPMM_DOT) && st.fold;
+  if (any_fold && !fp32_inner(h)) ok = ok && alloc((void**)&h->val_fold_p, (size_t)h->nnz * 8);
   ok = ok && hipMemcpy(h->rp_p, rpp.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(h->col_p, colp.data(), (size_t)h->nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(h->perm_p, perm.data(), (size_t)h->nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&

@@ -161,7 +161,8 @@ struct DotEpilogue {
   }
 };
 
-// Y rows of row block L; every finished row (row, its CPL values) goes to epi.
+// Y rows of row block L; every finished row (its own row index, its CPL values)
+// goes to epi, in the stored order (the block's dot partials follow it).
 // KPL = log2(kp); lane c0 = (lane mod (kp / CPL)) * CPL holds columns c0 ..
 // c0 + CPL - 1 (all below k, or all at or above it: CPL divides k).
 template <class T, int KPL, int CPL, int BS, bool OFF32, int STYLE, class Epi>
@@ -240,7 +241,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
           }
         }
         store_y<T, CPL>(Y, yrow(r), k, c, sv);
-        epi(r0 + r, sv);
+        epi(yrow(r), sv);
       }
     } else {
       for (int r = rsub; r < nr; r += 2 * rpp) {
@@ -306,11 +307,11 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
         }
         const T outA[1] = {sumA};
         store_y<T, 1>(Y, yrow(r), k, c, outA);
-        epi(r0 + r, outA);
+        epi(yrow(r), outA);
         if (has_b) {
           const T outB[1] = {sumB};
           store_y<T, 1>(Y, yrow(rb), k, c, outB);
-          epi(r0 + rb, outB);
+          epi(yrow(rb), outB);
         }
       }
     }
@@ -353,7 +354,7 @@ __device__ __forceinline__ void row_block(const SpmmMat& A, const T* __restrict_
         out[h] = v;
       }
       store_y<T, CPL>(Y, s_map[0], k, c, out);
-      epi(r0, out);
+      epi(s_map[0], out);
     }
   }
 }
@@ -591,9 +592,6 @@ hipError_t launch_spmm_dot(const SpmmMat& A, const void* X, void* Y, const void*
                            const Globals* glob, hipStream_t s, bool defer) {
   if (epi < 0 || epi >= E_NUM || (epilogue_dots(epi) > 0 && !W) || (epilogue_prec(epi) && (!Yh || !diag)))
     return hipErrorInvalidValue;
-  // the epilogue's partials follow the stored row order, which its fixed
-  // summation order assumes to be the rows' own
-  if (A.rowmap) return hipErrorInvalidValue;
   const int P = epilogue_dots(epi) * k;
   if (P > 256) return hipErrorInvalidValue;  // one thread per pair in reduce_runs_kernel
   const int G = spmm_dot_runs(A.nblk);

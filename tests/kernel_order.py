@@ -127,13 +127,34 @@ def spmm_row_blocks(row_ptr, k, block=256, nnz_max=4096, rows_max=1024):
     return blk
 
 
-def spmm_epilogue_dot(row_ptr, k, block=256, runs_max=256, fin_lanes=16):
+def tile_order(grid, tile):
+    """Rows of a natural-order nz x ny x nx grid (x fastest) in the order
+    of a tile-by-tile copy: tiles of tz x ty x tx points in the natural order
+    of their first point, the points of a tile in natural order within it."""
+    nz, ny, nx = grid
+    tz, ty, tx = tile
+    z, y, x = np.meshgrid(np.arange(tz), np.arange(ty), np.arange(tx), indexing="ij")
+    inner = ((z * ny + y) * nx + x).ravel()
+    Z, Y, X = np.meshgrid(np.arange(0, nz, tz), np.arange(0, ny, ty), np.arange(0, nx, tx), indexing="ij")
+    corner = ((Z * ny + Y) * nx + X).ravel()
+    return (corner[:, None] + inner[None, :]).ravel()
+
+
+def spmm_epilogue_dot(row_ptr, k, block=256, runs_max=256, fin_lanes=16, perm=None):
     """Dot of two length-n columns as the product's epilogue forms it: in row
     block L, row slot s (a group of kp / cpl lanes) sums rows
     r0 + s + j * (block * cpl / kp) in order of j; the row slots of a wave by a
     pairwise tree; the waves in order; then the G = min(#blocks, runs_max)
     runs of consecutive blocks in block order; then the finalize kernel's
-    lanes over the runs."""
+    lanes over the runs. perm: the stored order of the rows when the matrix
+    is kept permuted (row i of the copy is row perm[i]); the blocks and sums
+    then run over the stored rows."""
+    if perm is not None:
+        perm = np.asarray(perm)
+        cnt = np.diff(np.asarray(row_ptr))[perm]
+        row_ptr = np.concatenate(([0], np.cumsum(cnt)))
+        inner = spmm_epilogue_dot(row_ptr, k, block, runs_max, fin_lanes)
+        return lambda u, w: inner(np.asarray(u)[perm], np.asarray(w)[perm])
     kp = _pad_pow2(k)
     cpl = _spmm_cols_per_lane(k)
     rpp, slots, waves = block * cpl // kp, 64 * cpl // kp, block // 64

@@ -535,7 +535,7 @@ def test_fused_equals_merged_up_to_dot_order(lib):
 
 # ----------------------------------------------------------- bitwise ---
 
-from kernel_order import group_dot, oracle_dot, scheduled_dot, spmm_epilogue_dot  # noqa: E402
+from kernel_order import group_dot, oracle_dot, scheduled_dot, spmm_epilogue_dot, tile_order  # noqa: E402
 
 BITWISE = [m for m in METHODS if m[1] != "fused"]
 
@@ -588,14 +588,20 @@ def test_bitwise_converged(lib, variant, formulation, precond):
         assert np.array_equal(to_np(x), ref.x)
 
 
-def fused_dot(A, k, variant="classical"):
+def fused_dot(A, k, variant="classical", solver=None):
     """A fused form's dot sequence: (r, r), (b, b) from the start pass, then
     per pass: classical, delta from the first product's epilogue, phi, psi,
     theta from the second's and rho' from a vector pass; Reordered, delta from
     the first product's epilogue and theta, phi, psi, eta from a vector
-    pass."""
+    pass. solver: the handle whose layout the products follow (a tile-ordered
+    copy of A makes the epilogues add its rows in the stored order)."""
     g = group_dot(A.n, k)
-    e = spmm_epilogue_dot(A.row_ptr, k)
+    perm = None
+    if solver is not None:
+        tile, grid = solver.product_layout()
+        if tile[0] > 0:
+            perm = tile_order(grid, tile)
+    e = spmm_epilogue_dot(A.row_ptr, k, perm=perm)
     if variant == "pipelined":  # no product epilogue dots: every dot from a vector pass
         return g
     if variant == "reordered":
@@ -623,7 +629,7 @@ def test_bitwise_fused(lib, variant, precond, k):
         x, info = s.solve(torch.from_numpy(b).cuda(), tol=tol, maxit=maxit)
         X = to_np(x)
         for c in range(k):
-            with oracle_dot(fused_dot(A, k, variant)):
+            with oracle_dot(fused_dot(A, k, variant, s)):
                 ref = oracle.solve_column(S, b[:, c], None, variant, "fused", precond, tol, maxit)
             assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), (c, info.iters[c], ref.iters)
             assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
@@ -646,7 +652,7 @@ def test_bitwise_fused_k64_multichunk(lib, variant):
     x, info = s.solve(torch.from_numpy(b).cuda(), tol=0.0, maxit=3)
     X = to_np(x)
     for c in (0, k - 1):
-        with oracle_dot(fused_dot(A, k, variant)):
+        with oracle_dot(fused_dot(A, k, variant, s)):
             ref = oracle.solve_column(S, b[:, c], None, variant, "fused", "jacobi", 0.0, 3)
         assert np.array_equal(X[:, c], ref.x), (c, np.abs(X[:, c] - ref.x).max())
 
@@ -672,7 +678,7 @@ def test_reordered_restart_bitwise(lib, formulation):
     restarts = 0
     for c in range(k):
         tr = []
-        with oracle_dot(fused_dot(A, k, "reordered") if formulation == "fused" else group_dot(A.n, k)):
+        with oracle_dot(fused_dot(A, k, "reordered", s) if formulation == "fused" else group_dot(A.n, k)):
             ref = oracle.solve_column(S, b[:, c], None, "reordered", formulation, "jacobi", 1e-8, 500, trace=tr)
         restarts += sum(bool(t["restart"]) for t in tr)
         assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), (c, info.iters[c], ref.iters)
@@ -698,7 +704,7 @@ def test_reordered_restart_full_size(lib):
     hist = s.history()
     c = 19
     tr = []
-    with oracle_dot(fused_dot(A, 32, "reordered")):
+    with oracle_dot(fused_dot(A, 32, "reordered", s)):
         ref = oracle.solve_column(A.to_scipy(), b[:, c], None, "reordered", "fused", "jacobi", 1e-8, 36, trace=tr)
     assert any(t["restart"] for t in tr)
     assert np.array_equal(to_np(x)[:, c], ref.x)
@@ -764,7 +770,7 @@ def test_full_size_cfg1_sampled(lib):
         x, info = s3.solve(bt, tol=0.0, maxit=3)
         X = to_np(x)
         for c in (0, 31):
-            with oracle_dot(fused_dot(A, 32, v) if f == "fused" else group_dot(A.n, 32)):
+            with oracle_dot(fused_dot(A, 32, v, s3) if f == "fused" else group_dot(A.n, 32)):
                 ref = oracle.solve_column(S, b[:, c], None, v, f, "jacobi", 0.0, 3)
             assert np.array_equal(X[:, c], ref.x), (v, f, c)
         del s3
@@ -879,7 +885,7 @@ def test_random_systems_property_gpu(lib):
             # each column's oracle run gets the fused plan's dot schedule
             S = A.to_scipy()
             for c in range(k):
-                with oracle_dot(fused_dot(A, k, v)):
+                with oracle_dot(fused_dot(A, k, v, s)):
                     ref = oracle.solve_column(S, b[:, c], None, v, f, p, tol, maxit)
                 assert (int(info.iters[c]), int(info.status[c])) == (ref.iters, ref.status), c
                 assert np.array_equal(X[:, c], ref.x, equal_nan=True), c

@@ -3,7 +3,7 @@ vectorised path of the product-epilogue dot (row blocks of equal length)
 against a plain loop over blocks, row slots and waves."""
 import numpy as np
 
-from kernel_order import _pad_pow2, _wave_tree, spmm_epilogue_dot, spmm_row_blocks
+from kernel_order import _pad_pow2, _wave_tree, spmm_epilogue_dot, spmm_row_blocks, tile_order
 from workloads import conv_diff, random_sparse
 
 
@@ -50,6 +50,24 @@ def test_epilogue_dot_uniform_and_ragged_blocks():
                  (conv_diff(13, 3, (0.3, 0.2, 0.1)), 32), (random_sparse(3001, 9, seed=1), 8)):
         u, w = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
         assert spmm_epilogue_dot(A.row_ptr, k)(u, w) == _loop_epilogue_dot(A.row_ptr, k, u, w)
+
+
+def test_tile_order_and_permuted_epilogue_dot():
+    """The tile order is a permutation whose first block is the first tile
+    (z, y, x nested in that order); the permuted epilogue dot equals the
+    plain loop over the permuted rows."""
+    g, t = (4, 8, 8), (2, 4, 4)
+    perm = tile_order(g, t)
+    assert sorted(perm.tolist()) == list(range(4 * 8 * 8))
+    first = [(z * 8 + y) * 8 + x for z in range(2) for y in range(4) for x in range(4)]
+    assert perm[:32].tolist() == first
+    assert perm[32:36].tolist() == [4, 5, 6, 7]  # the next tile along x
+    A = conv_diff(8, 3, (1.0, 0.7, 0.3))
+    perm = tile_order((8, 8, 8), t)
+    rng = np.random.default_rng(9)
+    u, w = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    rp = np.concatenate(([0], np.cumsum(np.diff(A.row_ptr)[perm])))
+    assert spmm_epilogue_dot(A.row_ptr, 32, perm=perm)(u, w) == _loop_epilogue_dot(rp, 32, u[perm], w[perm])
 
 
 def _loop_batched_dot(n, k, nw, block, u, w):
