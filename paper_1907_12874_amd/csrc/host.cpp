@@ -259,6 +259,7 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_F_P_G23D, KFPG23D)
     G(OP_R_DOTS, KRDots)
     G(OP_F_RE_XVD, KFReXvD)
+    G(OP_F_RE_XV, KFReXv)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }

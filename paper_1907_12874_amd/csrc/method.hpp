@@ -197,6 +197,18 @@ struct KFReXvD {
     o[3] = r;
   }
 };
+// Fused Alg. 6 without a preconditioner (z = r, s = v, t-hat = r-tilde): in:
+// rt, t, x, p, v ; out: r, x, p, and r0 = r where the column restarts.
+struct KFReXv {
+  OP_HEAD_C(5, 4, 0, 4, 2, PART_RUN, true, false, 8u)
+  OP_F {
+    const double r = R(v[0] - c.omega * v[1]);
+    o[0] = r;
+    o[1] = v[2] + c.alpha * v[3] + c.omega * v[0];
+    o[2] = r + c.beta * (v[3] - c.omega * v[4]);
+    o[3] = r;
+  }
+};
 struct KRXzv {  // in: x, vh, th, q, s ; out: x, z, vh
   OP_HEAD(5, 3, 0, 1, 1, PART_RUN, true)
   OP_F {

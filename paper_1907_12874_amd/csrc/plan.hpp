@@ -141,6 +141,7 @@ enum OpId {
   OP_R_DOTS,         // Alg. 6: (t, rt), (t, t), (t, r0), (rt, rt)
   OP_F_RE_XVD,       // folded Jacobi, Alg. 6 on A M^{-1}: r = rt - omega t (r0 = r on a restart);
                      //   x += alpha p / a_ii + omega rt / a_ii; p = r + beta (p - omega v)
+  OP_F_RE_XV,        // fused Alg. 6 without a preconditioner: the same with x += alpha p + omega rt
   OP_NUM
 };
 

@@ -61,6 +61,7 @@ const OpInfo kOps[OP_NUM] = {
     {9, 3, 4, "f_p_g23d"},       // OP_F_P_G23D (+ the diagonal)
     {3, 0, 4, "r_dots"},         // OP_R_DOTS
     {5, 4, 0, "f_re_xvd", 1},    // OP_F_RE_XVD (+ the diagonal; r0 written on a restart only)
+    {5, 4, 0, "f_re_xv", 1},     // OP_F_RE_XV (r0 written on a restart only)
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -214,44 +215,40 @@ void classical(int formulation, int precond, Plan* P) {
 }
 
 // ------------------------------------------------------------- reordered ---
-// Fused form of Alg. 6 without a preconditioner (one device, beyond the
-// paper's grouping): delta = (v, r0) is formed in the epilogue of v = A vh.
-// With Jacobi the fused form is reordered_folded below.
-void reordered_fused(Plan* P) {
-  auto& it = P->iter;
-  it.push_back(SPMM_DOT(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
-  it.push_back(G(OP_SUB_ALPHA, {V_Z, V_S}, {V_TH}));             // t-hat = z - alpha s (s aliases v)
-  it.push_back(SPMM(V_TH, V_T));
-  it.push_back(G(OP_R_G3, {V_R, V_V, V_T, V_R0}, {V_RT}, 0, F_RE_OMEGA));
-  it.push_back(G(OP_RE_R, {V_RT, V_T}, {V_R, V_R0}));             // r = rt - omega t
-  it.push_back(G(OP_R_XZV, {V_X, V_VH, V_TH, V_Q, V_S}, {V_X, V_Z, V_VH}, 0, F_END));
-}
-
-// Fused form with Jacobi: Alg. 6 preconditions from the right, so with v-hat
-// = M^{-1} p it is the listing run on the folded matrix A M^{-1} with no
-// preconditioner, carrying p and r-tilde where it carried v-hat and t-hat
-// (s = v, q = t, z = r): v = (A M^{-1}) p with delta in the product's
-// epilogue; rt = r - alpha v; t = (A M^{-1}) rt; the four dots; then one pass
-// {r = rt - omega t (r0 = r on a restart), x += alpha p / a_ii + omega rt /
-// a_ii, p = r + beta (p - omega v)}, the scalar step having formed beta with
-// omega. No preconditioned block exists: 11 block reads and 4 writes per
-// iteration instead of 14 / 8.
-void reordered_folded(Plan* P) {
+// Fused form of Alg. 6 (one device, beyond the paper's grouping). Without a
+// preconditioner Alg. 6's z is r, s is v and t-hat is r-tilde (bit for bit:
+// the same updates of the same operands), and with Jacobi, Alg. 6
+// preconditions from the right, so with v-hat = M^{-1} p it is the listing
+// run on the folded matrix A M^{-1} with no preconditioner, carrying p and
+// r-tilde where it carried v-hat and t-hat. Either way: v = A p with delta in
+// the product's epilogue; rt = r - alpha v; t = A rt; the four dots; then one
+// pass {r = rt - omega t (r0 = r on a restart), x += alpha p + omega rt (with
+// Jacobi p / a_ii and rt / a_ii), p = r + beta (p - omega v)}, the scalar
+// step having formed beta with omega (A being A M^{-1} with Jacobi). 11 block
+// reads and 4 writes per iteration, no z, s, t-hat or q block.
+void reordered_fused(int precond, Plan* P) {
+  const bool jac = precond == 1;
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X}),
              G(OP_COPY, {V_R}, {V_VH})};  // p_0 = r_0 (held in the v-hat block)
   auto& it = P->iter;
-  it.push_back(SPMM_DOT_FOLD(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));  // v = A M^{-1} p, delta
-  it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));                  // rt = r - alpha v
-  it.push_back(SPMM_FOLD(V_RT, V_T));                                  // t = A M^{-1} rt
+  if (jac) {
+    it.push_back(SPMM_DOT_FOLD(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));  // v = A M^{-1} p, delta
+    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));                  // rt = r - alpha v
+    it.push_back(SPMM_FOLD(V_RT, V_T));                                  // t = A M^{-1} rt
+  } else {
+    it.push_back(SPMM_DOT(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
+    it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));
+    it.push_back(SPMM(V_RT, V_T));
+  }
   it.push_back(G(OP_R_DOTS, {V_T, V_RT, V_R0}, {}, 0, F_RE_OMEGA));
-  it.push_back(G(OP_F_RE_XVD, {V_RT, V_T, V_X, V_VH, V_V}, {V_R, V_X, V_VH, V_R0}, 0, F_END));
+  it.push_back(G(jac ? OP_F_RE_XVD : OP_F_RE_XV, {V_RT, V_T, V_X, V_VH, V_V}, {V_R, V_X, V_VH, V_R0}, 0, F_END));
   P->vecs = {V_R, V_R0, V_V, V_T, V_RT, V_VH};
 }
 
 void reordered(int formulation, int precond, Plan* P) {
   const bool jac = precond == 1;
-  if (formulation == 2 && jac) {
-    reordered_folded(P);
+  if (formulation == 2) {
+    reordered_fused(precond, P);
     return;
   }
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
@@ -261,9 +258,6 @@ void reordered(int formulation, int precond, Plan* P) {
     P->init.push_back(G(OP_COPY, {V_R}, {V_Z}));
   P->init.push_back(G(OP_COPY, {V_Z}, {V_VH}));  // v-hat_0 = z_0
   auto& it = P->iter;
-  if (formulation == 2) {
-    reordered_fused(P);
-  } else {
   it.push_back(SPMM(V_VH, V_V));
   it.push_back(G(OP_DOT, {V_V, V_R0}, {}, 0, F_ALPHA));  // delta
   if (jac) it.push_back(PREC(V_V, V_S));                 // s = M^{-1} v (alias of v when M = I)
@@ -286,7 +280,6 @@ void reordered(int formulation, int precond, Plan* P) {
     it.push_back(G(OP_SUB_OMEGA, {V_TH, V_Q}, {V_Z}));   // z = th - omega q
     Step s = G(OP_PUPD, {V_Z, V_VH, V_S}, {V_VH}, 0, F_END);  // vh = z + beta (vh - omega s)
     it.push_back(s);
-  }
   }
   P->vecs = {V_R, V_R0, V_V, V_T, V_Z, V_TH, V_RT, V_VH};
   if (jac) {
