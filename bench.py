@@ -60,7 +60,7 @@ OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
     "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g12", "pp_g34",
     "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h", "ib_init", "ib_g1", "ib_g2",
-    "ib_g3", "ib_z", "ib_v", "ib_x", "re_r", "f_xr_rho_d", "f_p_g23", "f_p_g23d", "r_dots", "f_re_xvd", "f_re_xv",
+    "ib_g3", "ib_z", "ib_v", "ib_x", "re_r", "f_xr_rho_d", "f_p_g23", "f_p_g23d", "f_re_xvd", "f_re_xv",
 ]
 
 
@@ -85,10 +85,11 @@ def step_bytes(step, n, nnz, k):
     if step["kind"] == "spmm":
         return spmm_bytes(n, nnz, k)
     if step["kind"] == "spmm_dot":
-        # the product, plus the epilogue's second operand (dots) and / or its
-        # Jacobi-scaled copy with the diagonal (E_PREC, E_DOT_W_PREC)
+        # the product, plus the epilogue's second operand (dots), its own input
+        # row (E_RE4) and / or its Jacobi-scaled copy with the diagonal
+        # (E_PREC, E_DOT_W_PREC)
         epi = step["op"]
-        extra = (blk if epi in (0, 1, 3) else 0) + (blk + 8 * n if epi in (2, 3) else 0)
+        extra = (blk if epi in (0, 1, 3, 4) else 0) + (blk if epi == 4 else 0) + (blk + 8 * n if epi in (2, 3) else 0)
         return spmm_bytes(n, nnz, k) + extra
     if step["kind"] == "prec":
         return 2 * blk + 8 * n
@@ -99,7 +100,7 @@ def kernel_name(step):
     if step["kind"] == "spmm":
         return "spmm_kernel"
     if step["kind"] == "spmm_dot":
-        return "spmm_dot_kernel<" + ("dot_w", "ppt", "prec", "dot_w_prec")[step["op"]] + ">"
+        return "spmm_dot_kernel<" + ("dot_w", "ppt", "prec", "dot_w_prec", "re4")[step["op"]] + ">"
     if step["kind"] == "prec":
         return "prec_kernel"
     return "group_kernel<" + OP_NAMES[step["op"]] + ">"

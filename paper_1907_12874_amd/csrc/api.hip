@@ -198,7 +198,8 @@ size_t layout(bicgstab_ctx* h, bool assign) {
   const size_t o_blk = take(h->part.blk.size() * 4);
   const size_t o_part = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
   const size_t o_part_alt = take((size_t)std::max(h->caps.dot_blocks, 256) * 7 * kMaxK * 8);
-  const size_t o_bpart = take(has_spmm_dot(h) ? (h->part.blk.size() - 1) * 3 * (size_t)h->k * 8 : 0);
+  const size_t o_bpart =
+      take(has_spmm_dot(h) ? (h->part.blk.size() - 1) * kMaxEpilogueDots * (size_t)h->k * 8 : 0);
   const size_t o_sc = take((size_t)S_NSCAL * kMaxK * 8);
   const size_t o_ist = take((size_t)I_NINT * kMaxK * 4);
   const size_t o_glob = take(sizeof(Globals));
@@ -733,7 +734,8 @@ int build_transpose(bicgstab_ctx* h) {
   HIPCHK(hipFree(counts));
   h->part_t = spmm_partition(rp, h->k, h->spmm_opl);
   HIPCHK(alloc((void**)&h->blk_t, h->part_t.blk.size() * 4));
-  if (has_spmm_dot(h)) HIPCHK(alloc((void**)&h->bpart_t, (h->part_t.blk.size() - 1) * 3 * (size_t)h->k * 8));
+  if (has_spmm_dot(h))
+    HIPCHK(alloc((void**)&h->bpart_t, (h->part_t.blk.size() - 1) * kMaxEpilogueDots * (size_t)h->k * 8));
   HIPCHK(hipMemcpyAsync(h->blk_t, h->part_t.blk.data(), h->part_t.blk.size() * 4, hipMemcpyHostToDevice, h->ws));
   HIPCHK(hipStreamSynchronize(h->ws));
   h->have_t = true;
@@ -1243,7 +1245,7 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
       // the epilogue's second operand and scaled copy (the product's own
       // traffic is counted apart); the partial-sum and finalize kernels
       if (epilogue_dots(s.op) > 0) {
-        r += 1;
+        r += 1 + (epilogue_reads_x(s.op) ? 1 : 0);
         fin_kernels += 2;
       } else if (s.fin != F_NONE) {
         fin_kernels += 1;

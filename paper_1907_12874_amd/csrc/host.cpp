@@ -115,7 +115,8 @@ void spmm(const Ctx& h, const std::vector<int32_t>& rp, const std::vector<int32_
 }
 
 // The product with an epilogue: the dots (y, w), or (y, w), (y, y), (w, w),
-// and / or the Jacobi-scaled copy yh = y / a_ii.
+// or (y, x), (y, y), (y, w), (x, x), and / or the Jacobi-scaled copy
+// yh = y / a_ii.
 void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, int epi, int slot, int fin,
               bool fold) {
   const int k = h.k;
@@ -137,7 +138,17 @@ void spmm_dot(Ctx& h, const double* X, double* Y, const double* W, double* Yh, i
       for (int c = 0; c < k; ++c) yr[c] = acc[c];
       if (scaled)
         for (int c = 0; c < k; ++c) Yh[(size_t)i * k + c] = acc[c] / h.diag[i];
-      if (nd > 0) {
+      if (epi == E_RE4) {
+        // (y, x), (y, y), (y, w), (x, x) with x at the row itself
+        const double* wr = W + (size_t)i * k;
+        const double* xr = X + (size_t)i * k;
+        for (int c = 0; c < k; ++c) {
+          part[c] += acc[c] * xr[c];
+          part[k + c] += acc[c] * acc[c];
+          part[2 * k + c] += acc[c] * wr[c];
+          part[3 * k + c] += xr[c] * xr[c];
+        }
+      } else if (nd > 0) {
         const double* wr = W + (size_t)i * k;
         for (int c = 0; c < k; ++c) {
           part[c] += acc[c] * wr[c];
@@ -257,7 +268,6 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_F_XR_RHO_D, KFXrRhoD)
     G(OP_F_P_G23, KFPG23)
     G(OP_F_P_G23D, KFPG23D)
-    G(OP_R_DOTS, KRDots)
     G(OP_F_RE_XVD, KFReXvD)
     G(OP_F_RE_XV, KFReXv)
 #undef G

@@ -171,15 +171,6 @@ struct KRG3 {  // in: r, v, t, r0 ; out: rt ; (t, rt), (t, t), (t, r0), (rt, rt)
     a[3] += rt * rt;
   }
 };
-struct KRDots {  // in: t, rt, r0 ; (t, rt), (t, t), (t, r0), (rt, rt)
-  OP_HEAD(3, 0, 4, 0, 0, PART_RUN, true)
-  OP_F {
-    a[0] += v[0] * v[1];
-    a[1] += v[0] * v[0];
-    a[2] += v[0] * v[2];
-    a[3] += v[1] * v[1];
-  }
-};
 // Alg. 6 on A M^{-1} (Jacobi folded into the products): in: rt, t, x, p, v
 // (+ a_ii) ; out: r, x, p, and r0 = r where the column restarts. Alg. 6's
 // z_{j+1} is r_{j+1} here, and its v-hat and t-hat are p / a_ii and rt / a_ii,

@@ -138,7 +138,6 @@ enum OpId {
   OP_F_XR_RHO_D,     // folded Jacobi, Alg. 5: x += alpha p / a_ii + omega s / a_ii; r = s - omega t; dot (r, r0)
   OP_F_P_G23,        // fused Alg. 4: OP_P_G2 and OP_P_G3 in one pass (r kept in registers); 4 dots
   OP_F_P_G23D,       // folded Jacobi, Alg. 7 as Alg. 4 on A M^{-1}: the same with x += (alpha p + omega q) / a_ii
-  OP_R_DOTS,         // Alg. 6: (t, rt), (t, t), (t, r0), (rt, rt)
   OP_F_RE_XVD,       // folded Jacobi, Alg. 6 on A M^{-1}: r = rt - omega t (r0 = r on a restart);
                      //   x += alpha p / a_ii + omega rt / a_ii; p = r + beta (p - omega v)
   OP_F_RE_XV,        // fused Alg. 6 without a preconditioner: the same with x += alpha p + omega rt
@@ -169,10 +168,16 @@ enum SpmmEpilogue {
   E_PPT,         // y = A x; dots (y, w), (y, y), (w, w)
   E_PREC,        // y = A x; yh = y / a_ii
   E_DOT_W_PREC,  // y = A x; yh = y / a_ii; dot (y, w)
+  E_RE4,         // y = A x; dots (y, x), (y, y), (y, w), (x, x) with x read at the row itself (Alg. 6)
   E_NUM
 };
 // Dot products and scaled-copy output of an epilogue.
-constexpr int epilogue_dots(int epi) { return epi == E_PPT ? 3 : (epi == E_DOT_W || epi == E_DOT_W_PREC) ? 1 : 0; }
+constexpr int epilogue_dots(int epi) {
+  return epi == E_RE4 ? 4 : epi == E_PPT ? 3 : (epi == E_DOT_W || epi == E_DOT_W_PREC) ? 1 : 0;
+}
+constexpr int kMaxEpilogueDots = 4;
+// the epilogue also reads the product's own input row (not only gathers it)
+constexpr bool epilogue_reads_x(int epi) { return epi == E_RE4; }
 constexpr bool epilogue_prec(int epi) { return epi == E_PREC || epi == E_DOT_W_PREC; }
 
 struct Step {

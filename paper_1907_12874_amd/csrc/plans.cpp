@@ -59,7 +59,6 @@ const OpInfo kOps[OP_NUM] = {
     {5, 2, 1, "f_xr_rho_d"},     // OP_F_XR_RHO_D (+ the diagonal)
     {9, 3, 4, "f_p_g23"},        // OP_F_P_G23
     {9, 3, 4, "f_p_g23d"},       // OP_F_P_G23D (+ the diagonal)
-    {3, 0, 4, "r_dots"},         // OP_R_DOTS
     {5, 4, 0, "f_re_xvd", 1},    // OP_F_RE_XVD (+ the diagonal; r0 written on a restart only)
     {5, 4, 0, "f_re_xv", 1},     // OP_F_RE_XV (r0 written on a restart only)
 };
@@ -221,11 +220,12 @@ void classical(int formulation, int precond, Plan* P) {
 // preconditions from the right, so with v-hat = M^{-1} p it is the listing
 // run on the folded matrix A M^{-1} with no preconditioner, carrying p and
 // r-tilde where it carried v-hat and t-hat. Either way: v = A p with delta in
-// the product's epilogue; rt = r - alpha v; t = A rt; the four dots; then one
-// pass {r = rt - omega t (r0 = r on a restart), x += alpha p + omega rt (with
-// Jacobi p / a_ii and rt / a_ii), p = r + beta (p - omega v)}, the scalar
-// step having formed beta with omega (A being A M^{-1} with Jacobi). 11 block
-// reads and 4 writes per iteration, no z, s, t-hat or q block.
+// the product's epilogue; rt = r - alpha v; t = A rt with the four dots (t,
+// rt), (t, t), (t, r0), (rt, rt) in its epilogue; then one pass {r = rt -
+// omega t (r0 = r on a restart), x += alpha p + omega rt (with Jacobi p / a_ii
+// and rt / a_ii), p = r + beta (p - omega v)}, the scalar step having formed
+// beta with omega (A being A M^{-1} with Jacobi). 10 block reads and 4 writes
+// per iteration, no z, s, t-hat or q block.
 void reordered_fused(int precond, Plan* P) {
   const bool jac = precond == 1;
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X}),
@@ -234,13 +234,12 @@ void reordered_fused(int precond, Plan* P) {
   if (jac) {
     it.push_back(SPMM_DOT_FOLD(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));  // v = A M^{-1} p, delta
     it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));                  // rt = r - alpha v
-    it.push_back(SPMM_FOLD(V_RT, V_T));                                  // t = A M^{-1} rt
+    it.push_back(SPMM_DOT_FOLD(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));  // t = A M^{-1} rt, four dots
   } else {
     it.push_back(SPMM_DOT(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
     it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));
-    it.push_back(SPMM(V_RT, V_T));
+    it.push_back(SPMM_DOT(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));
   }
-  it.push_back(G(OP_R_DOTS, {V_T, V_RT, V_R0}, {}, 0, F_RE_OMEGA));
   it.push_back(G(jac ? OP_F_RE_XVD : OP_F_RE_XV, {V_RT, V_T, V_X, V_VH, V_V}, {V_R, V_X, V_VH, V_R0}, 0, F_END));
   P->vecs = {V_R, V_R0, V_V, V_T, V_RT, V_VH};
 }

@@ -125,8 +125,9 @@ struct DotEpilogue {
   const T* W;
   T* Yh;
   const T* diag;
+  const T* X;  // the product's input, read at the row itself for E_RE4
   int k, c;
-  double acc[3 * CPL];
+  double acc[kMaxEpilogueDots * CPL];
   __device__ __forceinline__ void operator()(int row, const T (&y)[CPL]) {
     if constexpr (epilogue_prec(EPI)) {
       const T d = diag[row];
@@ -147,14 +148,35 @@ struct DotEpilogue {
 #pragma unroll
         for (int h = 0; h < CPL; ++h) w[h] = t[h];
       }
+      if constexpr (EPI == E_RE4) {
+        // x at the row itself: the product has just gathered it, so an
+        // ordinary load (served by the caches)
+        T xv[CPL];
+        if constexpr (CPL == 1) {
+          xv[0] = X[(size_t)row * k + c];
+        } else {
+          const typename VecOf<T, CPL>::type t = *(const typename VecOf<T, CPL>::type*)(X + (size_t)row * k + c);
 #pragma unroll
-      for (int h = 0; h < CPL; ++h) {
-        const double yv = (double)y[h];
-        const double wv = (double)w[h];
-        acc[h] += yv * wv;
-        if (EPI == E_PPT) {
+          for (int h = 0; h < CPL; ++h) xv[h] = t[h];
+        }
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+          const double yv = (double)y[h], xx = (double)xv[h], wv = (double)w[h];
+          acc[h] += yv * xx;
           acc[CPL + h] += yv * yv;
-          acc[2 * CPL + h] += wv * wv;
+          acc[2 * CPL + h] += yv * wv;
+          acc[3 * CPL + h] += xx * xx;
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+          const double yv = (double)y[h];
+          const double wv = (double)w[h];
+          acc[h] += yv * wv;
+          if (EPI == E_PPT) {
+            acc[CPL + h] += yv * yv;
+            acc[2 * CPL + h] += wv * wv;
+          }
         }
       }
     }
@@ -379,7 +401,7 @@ __global__ __launch_bounds__(BS) void spmm_dot_kernel(SpmmMat A, const T* __rest
   constexpr int ND = epilogue_dots(EPI);
   constexpr int LPL = KPL - (CPL == 4 ? 2 : CPL == 2 ? 1 : 0);
   const int L = block_of(blockIdx.x, A.nblk, A.xcd_chunk);
-  DotEpilogue<T, EPI, CPL> epi{W, Yh, diag, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
+  DotEpilogue<T, EPI, CPL> epi{W, Yh, diag, X, k, (int)(threadIdx.x & ((1 << LPL) - 1)) * CPL, {}};
   row_block<T, KPL, CPL, BS, OFF32, STYLE>(A, X, Y, k, L, epi);
   // lanes past k returned from the row loop with their sums still zero
   if constexpr (ND > 0) store_block_partials_strided<ND, BS, CPL>(epi.acc, bpart + (size_t)L * ND * k, k, LPL, 1);
@@ -528,6 +550,7 @@ hipError_t spmm_dot_dispatch_cpl(const SpmmMat& A, const T* x, T* y, const T* w,
     case E_PPT: return spmm_epi_launch<T, CPL, E_PPT>(A, x, y, w, yh, diag, k, bpart, glob, s);
     case E_PREC: return spmm_epi_launch<T, CPL, E_PREC>(A, x, y, w, yh, diag, k, bpart, glob, s);
     case E_DOT_W_PREC: return spmm_epi_launch<T, CPL, E_DOT_W_PREC>(A, x, y, w, yh, diag, k, bpart, glob, s);
+    case E_RE4: return spmm_epi_launch<T, CPL, E_RE4>(A, x, y, w, yh, diag, k, bpart, glob, s);
     default: return hipErrorInvalidValue;
   }
 }
