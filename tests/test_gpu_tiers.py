@@ -114,7 +114,8 @@ def test_grad_values_kernel(lib):
 
 @pytest.mark.parametrize("variant,precond,formulation", [("classical", "none", "merged"), ("classical", "jacobi", "merged"),
                                                          ("classical", "jacobi", "fused"), ("improved", "none", "merged"),
-                                                         ("reordered", "jacobi", "fused")])
+                                                         ("reordered", "jacobi", "fused"), ("reordered", "none", "fused"),
+                                                         ("pipelined", "jacobi", "merged"), ("pipelined", "jacobi", "fused")])
 def test_transpose_solve(lib, variant, precond, formulation):
     """A^T Lambda = G by the same method on the device-built transposed CSR
     (nonsymmetric matrix, so A vs A^T matters)."""
