@@ -19,6 +19,25 @@ def test_bench_refuses_several_gpus():
     assert r.stdout.strip() == ""
 
 
+def test_kernel_names_follow_the_op_table():
+    """The bench names a vector pass by its op id: its list follows the op
+    enumeration and the library's op table entry for entry."""
+    import re
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    csrc = os.path.join(ROOT, "paper_1907_12874_amd", "csrc")
+    plan = open(os.path.join(csrc, "plan.hpp")).read()
+    i = plan.index("enum OpId")
+    ops = re.findall(r"^\s*(OP_[A-Z0-9_]+)", plan[i:plan.index("OP_NUM", i)], re.M)
+    table = open(os.path.join(csrc, "plans.cpp")).read()
+    a = table.index("const OpInfo kOps")
+    body = table[a:table.index("};", a)]
+    assert re.findall(r"// (OP_[A-Z0-9_]+)", body) == ops
+    assert re.findall(r'"([a-z0-9_]+)"', body) == bench.OP_NAMES
+
+
 @pytest.mark.gpu
 def test_bench_json_contract():
     """A small run (32^3 grid, k = 4, no sweep or extra sections) prints one
