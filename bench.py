@@ -60,7 +60,7 @@ OP_NAMES = [
     "init", "init_p", "zerob", "copy", "fill0", "exit", "dot", "dotself", "sub_alpha", "sub_omega", "xupd", "pupd",
     "c_ppt", "c_xr_rho", "c_r_rho", "r_g3", "r_xzv", "p_g1", "p_g2", "p_g3", "pp_g12", "pp_g34",
     "ref_resid", "ref_scale", "ref_update", "f_sub_alpha_h", "f_pupd_h", "f_xr_rho_h", "ib_init", "ib_g1", "ib_g2",
-    "ib_g3", "ib_z", "ib_v", "ib_x", "re_r", "f_xr_rho_d", "f_p_g23", "f_p_g23d", "f_re_xvd", "f_re_xv",
+    "ib_g3", "ib_z", "ib_v", "ib_x", "re_r", "f_xr_rho_d", "f_p_g23", "f_p_g23d", "f_re_xvd", "f_re_xv", "r_dots",
 ]
 
 

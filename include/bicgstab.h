@@ -348,7 +348,9 @@ int bicgstab_axpby_tab1(int32_t run, int64_t n, double a, double b, double c, co
 /* Host-only query of the launch plan of one iteration (no device needed):
  * vector block reads and writes of its vector-operation passes (the counting
  * of Table 2), preconditioner applications, sparse products and kernel
- * launches per iteration. */
+ * launches per iteration. Plans are the same for every k except the fused
+ * Reordered form, which below k = 4 forms its four dots in a pass of its own
+ * (one block read more); this query gives the plan for k >= 4. */
 int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond, int32_t* reads, int32_t* writes,
                           int32_t* precond_apps, int32_t* spmms, int32_t* launches);
 

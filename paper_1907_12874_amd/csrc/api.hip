@@ -929,7 +929,7 @@ int bicgstab_create(const bicgstab_csr* A, int64_t n, int32_t k, int32_t variant
   h->chunk = std::max(1, env_int("BICGSTAB_CHUNK", 8));
   h->use_graph = env_int("BICGSTAB_GRAPH", 1) != 0;
   std::string err;
-  if (!build_plan(variant, formulation, precond, &h->plan, &err)) {
+  if (!build_plan(variant, formulation, precond, k, &h->plan, &err)) {
     delete h;
     return fail(BICGSTAB_EINVAL, err);
   }
@@ -1230,7 +1230,7 @@ int bicgstab_plan_traffic(int32_t variant, int32_t formulation, int32_t precond,
                           int32_t* precond_apps, int32_t* spmms, int32_t* launches) {
   Plan P;
   std::string err;
-  if (!build_plan(variant, formulation, precond, &P, &err)) return fail(BICGSTAB_EINVAL, err);
+  if (!build_plan(variant, formulation, precond, kMaxK / 2, &P, &err)) return fail(BICGSTAB_EINVAL, err);
   int r = 0, w = 0, pa = 0, sp = 0;
   int fin_kernels = 0;
   for (const Step& s : P.iter) {

@@ -270,6 +270,7 @@ int run_group(Ctx& h, const Step& st, double* const* vp) {
     G(OP_F_P_G23D, KFPG23D)
     G(OP_F_RE_XVD, KFReXvD)
     G(OP_F_RE_XV, KFReXv)
+    G(OP_R_DOTS, KRDots)
 #undef G
     default: return fail(BICGSTAB_EINVAL, "host executor: op not available on the host");
   }
@@ -329,7 +330,7 @@ int bicgstab_host_create(const bicgstab_host_csr* A, int32_t k, int32_t variant,
     return fail(BICGSTAB_EUNSUPPORTED, "Improved BiCGStab has no preconditioned form");
   std::unique_ptr<Ctx> h(new Ctx);
   std::string err;
-  if (!build_plan(variant, formulation, precond, &h->plan, &err)) return fail(BICGSTAB_EINVAL, err);
+  if (!build_plan(variant, formulation, precond, k, &h->plan, &err)) return fail(BICGSTAB_EINVAL, err);
   h->n = A->n;
   h->k = k;
   h->variant = variant;

@@ -421,6 +421,7 @@ hipError_t dispatch_op(int op, const GArgs& a, const GridCaps& grid_cap, hipStre
     case OP_F_P_G23D: return launch_op<KFPG23D, T>(a, grid_cap, s, defer);
     case OP_F_RE_XVD: return launch_op<KFReXvD, T>(a, grid_cap, s, defer);
     case OP_F_RE_XV: return launch_op<KFReXv, T>(a, grid_cap, s, defer);
+    case OP_R_DOTS: return launch_op<KRDots, T>(a, grid_cap, s, defer);
     default: return hipErrorInvalidValue;
   }
 }

@@ -188,6 +188,15 @@ struct KFReXvD {
     o[3] = r;
   }
 };
+struct KRDots {  // in: t, rt, r0 ; (t, rt), (t, t), (t, r0), (rt, rt)
+  OP_HEAD(3, 0, 4, 0, 0, PART_RUN, true)
+  OP_F {
+    a[0] += v[0] * v[1];
+    a[1] += v[0] * v[0];
+    a[2] += v[0] * v[2];
+    a[3] += v[1] * v[1];
+  }
+};
 // Fused Alg. 6 without a preconditioner (z = r, s = v, t-hat = r-tilde): in:
 // rt, t, x, p, v ; out: r, x, p, and r0 = r where the column restarts.
 struct KFReXv {

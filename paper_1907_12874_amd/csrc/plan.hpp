@@ -141,6 +141,7 @@ enum OpId {
   OP_F_RE_XVD,       // folded Jacobi, Alg. 6 on A M^{-1}: r = rt - omega t (r0 = r on a restart);
                      //   x += alpha p / a_ii + omega rt / a_ii; p = r + beta (p - omega v)
   OP_F_RE_XV,        // fused Alg. 6 without a preconditioner: the same with x += alpha p + omega rt
+  OP_R_DOTS,         // Alg. 6: (t, rt), (t, t), (t, r0), (rt, rt)
   OP_NUM
 };
 
@@ -200,7 +201,9 @@ struct Plan {
 
 // Builds the launch plan of (variant, formulation, precond). Returns false on
 // an unknown combination.
-bool build_plan(int variant, int formulation, int precond, Plan* plan, std::string* err);
+// k: the right-hand sides (from k = 4 on the fused Reordered form takes its
+// four dots in a product's epilogue; below, in a pass of their own).
+bool build_plan(int variant, int formulation, int precond, int k, Plan* plan, std::string* err);
 
 // Static description of every op (for traffic accounting and validation).
 // The last ncond outputs are written only for a column that restarts (a rare

@@ -61,6 +61,7 @@ const OpInfo kOps[OP_NUM] = {
     {9, 3, 4, "f_p_g23d"},       // OP_F_P_G23D (+ the diagonal)
     {5, 4, 0, "f_re_xvd", 1},    // OP_F_RE_XVD (+ the diagonal; r0 written on a restart only)
     {5, 4, 0, "f_re_xv", 1},     // OP_F_RE_XV (r0 written on a restart only)
+    {3, 0, 4, "r_dots"},         // OP_R_DOTS
 };
 
 Step G(int op, std::initializer_list<int> in, std::initializer_list<int> out, int slot = 0, int fin = F_NONE) {
@@ -225,29 +226,39 @@ void classical(int formulation, int precond, Plan* P) {
 // omega t (r0 = r on a restart), x += alpha p + omega rt (with Jacobi p / a_ii
 // and rt / a_ii), p = r + beta (p - omega v)}, the scalar step having formed
 // beta with omega (A being A M^{-1} with Jacobi). 10 block reads and 4 writes
-// per iteration, no z, s, t-hat or q block.
-void reordered_fused(int precond, Plan* P) {
+// per iteration, no z, s, t-hat or q block. Below k = 4 the blocks stay in
+// the caches and the epilogue's run-sum kernel costs more than it saves: the
+// four dots then take a pass of their own after a plain product (11 / 4).
+void reordered_fused(int precond, int k, Plan* P) {
   const bool jac = precond == 1;
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X}),
              G(OP_COPY, {V_R}, {V_VH})};  // p_0 = r_0 (held in the v-hat block)
   auto& it = P->iter;
+  const bool epi4 = k >= 4;
   if (jac) {
     it.push_back(SPMM_DOT_FOLD(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));  // v = A M^{-1} p, delta
     it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));                  // rt = r - alpha v
-    it.push_back(SPMM_DOT_FOLD(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));  // t = A M^{-1} rt, four dots
+    if (epi4)
+      it.push_back(SPMM_DOT_FOLD(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));  // t = A M^{-1} rt, four dots
+    else
+      it.push_back(SPMM_FOLD(V_RT, V_T));
   } else {
     it.push_back(SPMM_DOT(V_VH, V_V, E_DOT_W, V_R0, 0, F_ALPHA));
     it.push_back(G(OP_SUB_ALPHA, {V_R, V_V}, {V_RT}));
-    it.push_back(SPMM_DOT(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));
+    if (epi4)
+      it.push_back(SPMM_DOT(V_RT, V_T, E_RE4, V_R0, 0, F_RE_OMEGA));
+    else
+      it.push_back(SPMM(V_RT, V_T));
   }
+  if (!epi4) it.push_back(G(OP_R_DOTS, {V_T, V_RT, V_R0}, {}, 0, F_RE_OMEGA));
   it.push_back(G(jac ? OP_F_RE_XVD : OP_F_RE_XV, {V_RT, V_T, V_X, V_VH, V_V}, {V_R, V_X, V_VH, V_R0}, 0, F_END));
   P->vecs = {V_R, V_R0, V_V, V_T, V_RT, V_VH};
 }
 
-void reordered(int formulation, int precond, Plan* P) {
+void reordered(int formulation, int precond, int k, Plan* P) {
   const bool jac = precond == 1;
   if (formulation == 2) {
-    reordered_fused(precond, P);
+    reordered_fused(precond, k, P);
     return;
   }
   P->init = {SPMM(V_X, V_V), G(OP_INIT, {V_B, V_V}, {V_R, V_R0}, 0, F_INIT), G(OP_ZEROB, {}, {V_X})};
@@ -453,7 +464,7 @@ void improved(int formulation, Plan* P) {
 
 const OpInfo& op_info(int op) { return kOps[op]; }
 
-bool build_plan(int variant, int formulation, int precond, Plan* P, std::string* err) {
+bool build_plan(int variant, int formulation, int precond, int k, Plan* P, std::string* err) {
   P->init.clear();
   P->iter.clear();
   P->vecs.clear();
@@ -476,7 +487,7 @@ bool build_plan(int variant, int formulation, int precond, Plan* P, std::string*
   }
   switch (variant) {
     case 0: classical(formulation, precond, P); break;
-    case 1: reordered(formulation, precond, P); break;
+    case 1: reordered(formulation, precond, k, P); break;
     case 2: pipelined(formulation, precond, P); break;
     case 3: improved(formulation, P); break;
     default: *err = "unknown variant"; return false;

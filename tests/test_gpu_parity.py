@@ -593,7 +593,7 @@ def fused_dot(A, k, variant="classical", solver=None):
     per pass: classical, delta from the first product's epilogue, phi, psi,
     theta from the second's and rho' from a vector pass; Reordered, delta from
     the first product's epilogue and theta, phi, psi, eta from a vector
-    pass, now from the second product's epilogue. solver: the handle whose
+    pass (from k = 4 on, from the second product's epilogue). solver: the handle whose
     layout the products follow (a tile-ordered copy of A makes the epilogues
     add its rows in the stored order)."""
     g = group_dot(A.n, k)
@@ -606,7 +606,7 @@ def fused_dot(A, k, variant="classical", solver=None):
     if variant == "pipelined":  # no product epilogue dots: every dot from a vector pass
         return g
     if variant == "reordered":
-        return scheduled_dot([g, g], [e, e, e, e, e])
+        return scheduled_dot([g, g], [e, e, e, e, e] if k >= 4 else [e, g, g, g, g])
     return scheduled_dot([g, g], [e, e, e, e, g])
 
 
