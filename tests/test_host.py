@@ -63,7 +63,10 @@ def test_random_sparse_ragged_ranges_and_x0(host):
     rng = np.random.default_rng(2)
     b = rng.uniform(-1, 1, (A.n, 5))
     x0 = rng.uniform(-0.1, 0.1, (A.n, 5))
-    for v, f, p in (("classical", "merged", "jacobi"), ("pipelined", "merged", "none"), ("improved", "merged", "none")):
+    # k = 5: the fused Reordered form takes its four dots in the second
+    # product's epilogue (from k = 4 on; the k = 3 cases above use a dot pass)
+    for v, f, p in (("classical", "merged", "jacobi"), ("pipelined", "merged", "none"), ("improved", "merged", "none"),
+                    ("reordered", "fused", "jacobi"), ("reordered", "fused", "none")):
         x, info = _solve(host, A, b, v, f, p, 7, 1e-9, 400, x0=x0)
         ref = _ref(A, b, v, f, p, 7, 1e-9, 400, x0=x0)
         assert np.array_equal(info.iters, ref.iters) and np.array_equal(x, ref.x), (v, f, p)
