@@ -39,7 +39,7 @@ pytestmark = pytest.mark.gpu
 
 METHODS = [(v, f, p) for v in ("classical", "reordered", "pipelined") for f in ("merged", "basic") for p in ("none", "jacobi")]
 # the fused forms (not Improved); their oracle is the merged listing, with
-# Jacobi folded into the products for the classical and Pipelined methods
+# Jacobi folded into the products
 METHODS += [(v, "fused", p) for v in ("classical", "reordered", "pipelined") for p in ("none", "jacobi")]
 # Improved BiCGStab (Alg. 3) has no preconditioned form
 METHODS += [("improved", f, "none") for f in ("merged", "basic")]
